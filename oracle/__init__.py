@@ -1,0 +1,174 @@
+"""Reserve oracle: TEST INFRASTRUCTURE ONLY.
+
+Plain, slow CPU evaluation of reserves for the tests, the smoke check and the
+CPU-baseline leg of the benchmark (see ``oracle.c`` for the method and the
+readings of the paper it follows).  The GPU library never imports this
+package and this package never imports the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+OUT_STATES = 4
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (FP64, no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Basis(ctypes.Structure):
+    _fields_ = [("n_ages", ctypes.c_int), ("n_tables", ctypes.c_int),
+                ("q", ctypes.c_void_p), ("n_nodes", ctypes.c_int),
+                ("n_scen", ctypes.c_int), ("n_steps", ctypes.c_int),
+                ("v", ctypes.c_void_p), ("shock", ctypes.c_void_p)]
+
+
+class _Portfolio(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("product", ctypes.c_void_p),
+                ("age1", ctypes.c_void_p), ("age2", ctypes.c_void_p),
+                ("term", ctypes.c_void_p), ("table1", ctypes.c_void_p),
+                ("table2", ctypes.c_void_p), ("timing", ctypes.c_void_p),
+                ("amount", ctypes.c_void_p), ("premium", ctypes.c_void_p)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        vp, ci = ctypes.c_void_p, ctypes.c_int
+        lib.orc_reserves.argtypes = [vp, vp, ci, ci, ci, ci, ci, vp, vp, vp, vp, ci]
+        lib.orc_reserves.restype = ci
+        lib.orc_reserve_paths.argtypes = [vp, vp, ci, ci, ci, vp, ci]
+        lib.orc_reserve_paths.restype = ci
+        lib.orc_reserve_path_summation.argtypes = [vp, vp, ci, ci, ci, ci, vp]
+        lib.orc_reserve_path_summation.restype = ci
+        lib.orc_build_w.argtypes = [ci, ci, vp, ctypes.c_double, vp]
+        lib.orc_build_w.restype = ci
+        lib.orc_n_states.argtypes = [ci]
+        lib.orc_n_states.restype = ci
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class _Args:
+    """Holds contiguous copies so the pointers stay valid during a call."""
+
+    def __init__(self, basis, pf):
+        self.q = np.ascontiguousarray(basis.q, np.float64)
+        self.v = np.ascontiguousarray(basis.v, np.float64)
+        self.shock = None if basis.shock is None else np.ascontiguousarray(basis.shock, np.float64)
+        self.b = _Basis(self.q.shape[1], self.q.shape[0], _ptr(self.q), self.v.shape[0],
+                        self.v.shape[1], self.v.shape[2], _ptr(self.v), _ptr(self.shock))
+        i32 = lambda x: np.ascontiguousarray(x, np.int32)
+        f64 = lambda x: np.ascontiguousarray(x, np.float64)
+        self.arrs = [i32(pf.product), i32(pf.age1_m), i32(pf.age2_m), i32(pf.term_m),
+                     i32(pf.table1), i32(pf.table2), i32(pf.timing), f64(pf.amount),
+                     f64(pf.premium)]
+        self.p = _Portfolio(int(pf.product.shape[0]), *[_ptr(a) for a in self.arrs])
+        self.n = int(pf.product.shape[0])
+
+
+def default_threads() -> int:
+    return int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+
+
+def reserves(basis, pf, node0=0, nnode=None, scen0=0, nscen=None, node_step=12,
+             want_gross=True, n_threads=None):
+    """Dense backward recurrence (Eq. 3.1) for every policy/node/scenario.
+
+    Returns dict with r_all [nnode, n, nscen, 4], gross [nnode, n, nscen],
+    totals [nnode, nscen], gross_totals [nnode, nscen].
+    """
+    lib = _load()
+    a = _Args(basis, pf)
+    nnode = basis.v.shape[0] - node0 if nnode is None else nnode
+    nscen = basis.v.shape[1] - scen0 if nscen is None else nscen
+    r_all = np.zeros((nnode, a.n, nscen, OUT_STATES))
+    gross = np.zeros((nnode, a.n, nscen)) if want_gross else None
+    totals = np.zeros((nnode, nscen))
+    gtot = np.zeros((nnode, nscen)) if want_gross else None
+    rc = lib.orc_reserves(ctypes.byref(a.b), ctypes.byref(a.p), node0, nnode, scen0, nscen,
+                          node_step, _ptr(r_all), _ptr(gross), _ptr(totals), _ptr(gtot),
+                          n_threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (rc={rc})")
+    return {"r_all": r_all, "gross": gross, "totals": totals, "gross_totals": gtot}
+
+
+def path_offsets(term_m, node=0, node_step=12):
+    S = np.maximum(np.asarray(term_m, np.int64) - node * node_step, 0)
+    off = np.zeros(S.shape[0] + 1, np.int64)
+    np.cumsum(S + 1, out=off[1:])
+    return off
+
+
+def reserve_paths(basis, pf, node=0, scen=0, node_step=12, n_threads=None):
+    """State-0 reserve at every step of every policy (ragged, see oracle.c)."""
+    lib = _load()
+    a = _Args(basis, pf)
+    off = path_offsets(pf.term_m, node, node_step)
+    path = np.zeros(int(off[-1]))
+    rc = lib.orc_reserve_paths(ctypes.byref(a.b), ctypes.byref(a.p), node, scen, node_step,
+                               _ptr(path), n_threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (rc={rc})")
+    return path, off
+
+
+def reserve_path_summation(basis, pf, i, node=0, scen=0, node_step=12):
+    """Eq. (3.5) evaluated directly at each t = 0..S for policy i: [S+1, n_states]."""
+    lib = _load()
+    a = _Args(basis, pf)
+    S = int(pf.term_m[i]) - node * node_step
+    n_states = lib.orc_n_states(int(pf.product[i]))
+    out = np.zeros((S + 1) * max(n_states, 1))
+    rc = lib.orc_reserve_path_summation(ctypes.byref(a.b), ctypes.byref(a.p), i, node, scen,
+                                        node_step, _ptr(out))
+    if rc < 0:
+        raise ValueError("oracle rejected the input")
+    return out.reshape(S + 1, n_states)
+
+
+def build_w(n_lives: int, model: int, q, g: float = 1.0) -> np.ndarray:
+    """Transition matrix of n_lives independent lives (Kronecker form)."""
+    lib = _load()
+    qa = np.ascontiguousarray(q, np.float64)
+    W = np.zeros(81)
+    n = lib.orc_build_w(n_lives, model, _ptr(qa), float(g), _ptr(W))
+    if n < 0:
+        raise ValueError("too many states")
+    return W[: n * n].reshape(n, n)
+
+
+def n_states(product: int) -> int:
+    return int(_load().orc_n_states(int(product)))
+
+
+def node_stats(totals: np.ndarray, tail: float = 0.005):
+    """Per-node mean and the ceil(tail*K)-th largest of K scenario totals
+    (the paper's 5th largest of 1,000 scenarios, Sec. 2.1)."""
+    K = totals.shape[1]
+    j = max(1, int(np.ceil(tail * K - 1e-12)))
+    srt = np.sort(totals, axis=1)[:, ::-1]
+    return totals.mean(axis=1), srt[:, j - 1]

@@ -1,0 +1,460 @@
+/*
+ * Reserve oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU evaluation of prospective reserves of
+ * non-unit-linked life policies, written from Tucker & Bull, "An efficient
+ * algorithm for the calculation of reserves for non-unit linked life
+ * policies" (arXiv 1401.1757).  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code with the
+ * GPU library.
+ *
+ * Two evaluations are provided:
+ *   - orc_reserves: the general vector recurrence, Eq. (3.1), applied densely
+ *     (full n x n transition matrices, every state kept, no zero-reserve-state
+ *     reduction) and backward from the boundary condition (Sec. 3.8.2);
+ *   - orc_reserve_path_summation: the reserve summation, Eq. (3.5), evaluated
+ *     directly at every time step, O(S^2) per policy (Sec. 3.8.1), used only
+ *     to check the recurrence on tiny inputs.
+ *
+ * Readings of the paper (where it is silent or ambiguous):
+ *   - W row index = state at the start of the step (the explicit matrices of
+ *     Sec. 2.4.2 and 4 and the per-state relation, Eq. (3.7)); the entry
+ *     (j, i) is the probability of moving from j to i.
+ *   - Each cash-flow type is its own stream with its own timing f; the
+ *     streams are summed (Eq. (3.5) is linear in c).  Premiums are paid at
+ *     f = 0 in state 0, annuity payments at f = 0 or 1 (policy timing), death
+ *     benefits at f = 1 in the died-in-step state.
+ *   - For f in (0, 1) the fractional death probability is f*q (uniform
+ *     distribution of deaths) and the discount is v^f; products here use
+ *     f in {0, 1} only, where this is exact.
+ *   - Time t counts months since the node; life l has attained age
+ *     age_l + node*node_step + t (equivalent to the paper's age-shift form by
+ *     the cash-flow shift identity, Eq. (3.2)).
+ *   - Node shock m multiplies every monthly q, capped at 1.
+ *   - A policy whose remaining term at the node is <= 0 has expired: all its
+ *     outputs are 0 and it is left out of totals.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Product codes (input format). */
+enum {
+    O_SL_ANN = 0, O_JL_ANN = 1, O_REV_ANN = 2, O_LS_ANN = 3,
+    O_TERM = 4, O_ENDOW = 5, O_ENDOW_ASSUR = 6, O_N_PRODUCTS = 7
+};
+
+#define ORC_MAX_STATES 9
+#define ORC_OUT_STATES 4
+
+typedef struct {
+    int n_ages;
+    int n_tables;
+    const double *q;        /* [n_tables][n_ages] monthly death probability */
+    int n_nodes;
+    int n_scen;
+    int n_steps;
+    const double *v;        /* [n_nodes][n_scen][n_steps] one-step discount */
+    const double *shock;    /* [n_nodes] multiplier on q, or NULL */
+} orc_basis;
+
+typedef struct {
+    int n;
+    const int32_t *product;
+    const int32_t *age1;
+    const int32_t *age2;
+    const int32_t *term;
+    const int32_t *table1;
+    const int32_t *table2;
+    const int32_t *timing;   /* 0: annuity at f = 0, 1: at f = 1 */
+    const double *amount;    /* annual annuity amount, or sum assured */
+    const double *premium;   /* level monthly premium, paid in advance */
+} orc_portfolio;
+
+/* A contract in the paper's state-space form (Sec. 3.1, Sec. 4). */
+typedef struct {
+    int n_lives;
+    int life_model;                     /* 2: alive/dead; 3: alive/died-in-step/dead */
+    int n_states;
+    double f_ann;                       /* timing of the annuity stream */
+    double c_ann[ORC_MAX_STATES];       /* annuity stream, at f_ann */
+    double c_ben[ORC_MAX_STATES];       /* death benefit stream, at f = 1 */
+    double c_prem[ORC_MAX_STATES];      /* premium stream, at f = 0 */
+    double boundary[ORC_MAX_STATES];    /* reserve vector at the end of the term */
+} orc_contract;
+
+/* ------------------------------------------------------------------------ */
+/* Transition matrices (Sec. 4.1, 4.1.3, 4.2, 4.3).                          */
+/* ------------------------------------------------------------------------ */
+
+/* One life over a fraction g of a step, death probability q over the whole
+ * step.  2-state model (Sec. 4.1): [[gp, gq], [0, 1]].  3-state model
+ * (Sec. 4.1.3): [[gp, gq, 0], [0, 0, 1], [0, 0, 1]]. */
+static int life_matrix(int model, double q, double g, double *W)
+{
+    double gq = g * q;
+    double gp = 1.0 - gq;
+    if (model == 2) {
+        W[0] = gp;  W[1] = gq;
+        W[2] = 0.0; W[3] = 1.0;
+        return 2;
+    }
+    W[0] = gp;  W[1] = gq;  W[2] = 0.0;
+    W[3] = 0.0; W[4] = 0.0; W[5] = 1.0;
+    W[6] = 0.0; W[7] = 0.0; W[8] = 1.0;
+    return 3;
+}
+
+/* Kronecker product C = A (na x na) (x) B (nb x nb). */
+static void kron(const double *A, int na, const double *B, int nb, double *C)
+{
+    int n = na * nb;
+    for (int i1 = 0; i1 < na; ++i1)
+        for (int j1 = 0; j1 < na; ++j1)
+            for (int i2 = 0; i2 < nb; ++i2)
+                for (int j2 = 0; j2 < nb; ++j2)
+                    C[(i1 * nb + i2) * n + (j1 * nb + j2)] = A[i1 * na + j1] * B[i2 * nb + j2];
+}
+
+/* W for m independent lives by the Kronecker recursion of Sec. 4.3,
+ * starting from the 1 x 1 matrix (1).  Life 1 is the most significant digit
+ * of the state label (binary labels of Sec. 2.4.2, ternary of Sec. 4.2.3).
+ * Returns the number of states. */
+int orc_build_w(int n_lives, int model, const double *q, double g, double *W)
+{
+    double acc[ORC_MAX_STATES * ORC_MAX_STATES];
+    double tmp[ORC_MAX_STATES * ORC_MAX_STATES];
+    double L[9];
+    int n = 1;
+    acc[0] = 1.0;
+    for (int l = 0; l < n_lives; ++l) {
+        int nl = life_matrix(model, q[l], g, L);
+        if (n * nl > ORC_MAX_STATES) return -1;
+        kron(acc, n, L, nl, tmp);
+        n *= nl;
+        memcpy(acc, tmp, sizeof(double) * n * n);
+    }
+    memcpy(W, acc, sizeof(double) * n * n);
+    return n;
+}
+
+/* y = A x for an n x n matrix. */
+static void matvec(const double *A, const double *x, int n, double *y)
+{
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += A[j * n + i] * x[i];
+        y[j] = s;
+    }
+}
+
+/* C = A B for n x n matrices. */
+static void matmul(const double *A, const double *B, int n, double *C)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
+            C[i * n + j] = s;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contracts (Sec. 4).                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Fill the state model, cash-flow vectors and boundary condition of one
+ * policy.  With gross != 0 every amount is taken positive, so the result is
+ * PV(benefits) + PV(premiums). */
+int orc_contract_of(int product, int timing, double amount, double premium,
+                    int gross, orc_contract *k)
+{
+    memset(k, 0, sizeof(*k));
+    double prem = gross ? fabs(premium) : -premium;
+    double pay = (gross ? fabs(amount) : amount) / 12.0;    /* monthly annuity */
+    double sa = gross ? fabs(amount) : amount;
+    if (timing != 0 && timing != 1) return -1;
+    k->f_ann = (double)timing;
+    switch (product) {
+    case O_SL_ANN:       /* Sec. 4.1.1: c = (theta, 0) */
+        k->n_lives = 1; k->life_model = 2; k->n_states = 2;
+        k->c_ann[0] = pay;
+        break;
+    case O_ENDOW:        /* Sec. 4.1.2: boundary (1, 0) times SA */
+        k->n_lives = 1; k->life_model = 2; k->n_states = 2;
+        k->boundary[0] = sa;
+        break;
+    case O_TERM:         /* Sec. 4.1.3: c = (0, 1, 0) times SA, boundary 0 */
+        k->n_lives = 1; k->life_model = 3; k->n_states = 3;
+        k->c_ben[1] = sa;
+        break;
+    case O_ENDOW_ASSUR:  /* term assurance with the pure-endowment boundary */
+        k->n_lives = 1; k->life_model = 3; k->n_states = 3;
+        k->c_ben[1] = sa;
+        k->boundary[0] = sa;
+        break;
+    case O_JL_ANN:       /* Sec. 4.2.1 b: c = (1, 0, 0, 0) */
+        k->n_lives = 2; k->life_model = 2; k->n_states = 4;
+        k->c_ann[0] = pay;
+        break;
+    case O_REV_ANN:      /* Sec. 4.2.1 a: c = (0, 0, 1, 0) */
+        k->n_lives = 2; k->life_model = 2; k->n_states = 4;
+        k->c_ann[2] = pay;
+        break;
+    case O_LS_ANN:       /* Sec. 4.2.1 c: c = (1, 1, 1, 0) */
+        k->n_lives = 2; k->life_model = 2; k->n_states = 4;
+        k->c_ann[0] = pay; k->c_ann[1] = pay; k->c_ann[2] = pay;
+        break;
+    default:
+        return -1;
+    }
+    k->c_prem[0] = prem;   /* premiums while every life is alive */
+    return 0;
+}
+
+static double q_at(const orc_basis *b, int table, int age, double m)
+{
+    double q = b->q[(size_t)table * b->n_ages + age];
+    double s = m * q;
+    return s < 1.0 ? s : 1.0;
+}
+
+/* Per-life death probabilities over step t. */
+static void step_q(const orc_basis *b, const orc_portfolio *p, int i,
+                   int age_shift, double m, int t, double *q)
+{
+    q[0] = q_at(b, p->table1[i], p->age1[i] + age_shift + t, m);
+    q[1] = q_at(b, p->table2[i], p->age2[i] + age_shift + t, m);
+}
+
+/* Add v^g W_g c to acc, one cash-flow stream of Eq. (3.1). */
+static void add_stream(const orc_contract *k, const double *q, double v, double g,
+                       const double *c, double *acc)
+{
+    int n = k->n_states, any = 0;
+    for (int j = 0; j < n; ++j) any |= (c[j] != 0.0);
+    if (!any) return;
+    double W[ORC_MAX_STATES * ORC_MAX_STATES], y[ORC_MAX_STATES];
+    orc_build_w(k->n_lives, k->life_model, q, g, W);
+    matvec(W, c, n, y);
+    double vg = pow(v, g);
+    for (int j = 0; j < n; ++j) acc[j] += vg * y[j];
+}
+
+/* Backward recurrence, Eq. (3.1), for one policy / node / scenario.  Writes
+ * the reserve vector at t = 0 into r0 (n_states entries) and, if path is not
+ * NULL, the state-0 reserve at t = 0..S into path[0..S]. */
+static void recurrence_one(const orc_basis *b, const orc_portfolio *p, int i,
+                           const orc_contract *k, int node, int age_shift, int S,
+                           const double *vcurve, double *r0, double *path)
+{
+    int n = k->n_states;
+    double m = b->shock ? b->shock[node] : 1.0;
+    double r[ORC_MAX_STATES], rn[ORC_MAX_STATES], q[2];
+    double W1[ORC_MAX_STATES * ORC_MAX_STATES], y[ORC_MAX_STATES];
+    for (int j = 0; j < n; ++j) r[j] = k->boundary[j];
+    if (path) path[S] = r[0];
+    for (int t = S - 1; t >= 0; --t) {
+        double v = vcurve[t];
+        step_q(b, p, i, age_shift, m, t, q);
+        for (int j = 0; j < n; ++j) rn[j] = 0.0;
+        add_stream(k, q, v, 0.0, k->c_prem, rn);
+        add_stream(k, q, v, k->f_ann, k->c_ann, rn);
+        add_stream(k, q, v, 1.0, k->c_ben, rn);
+        orc_build_w(k->n_lives, k->life_model, q, 1.0, W1);
+        matvec(W1, r, n, y);
+        for (int j = 0; j < n; ++j) rn[j] += v * y[j];
+        for (int j = 0; j < n; ++j) r[j] = rn[j];
+        if (path) path[t] = r[0];
+    }
+    for (int j = 0; j < n; ++j) r0[j] = r[j];
+}
+
+/* Neumaier-compensated sum. */
+typedef struct { double s, c; } neumaier;
+static void nm_add(neumaier *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static int validate(const orc_basis *b, const orc_portfolio *p)
+{
+    for (int i = 0; i < p->n; ++i) {
+        if (p->product[i] < 0 || p->product[i] >= O_N_PRODUCTS) return -1;
+        if (p->term[i] < 1 || p->term[i] > b->n_steps) return -1;
+        if (p->age1[i] < 0 || p->age1[i] + p->term[i] > b->n_ages - 1) return -1;
+        if (p->table1[i] < 0 || p->table1[i] >= b->n_tables) return -1;
+        int two = p->product[i] == O_JL_ANN || p->product[i] == O_REV_ANN ||
+                  p->product[i] == O_LS_ANN;
+        if (two) {
+            if (p->age2[i] < 0 || p->age2[i] + p->term[i] > b->n_ages - 1) return -1;
+            if (p->table2[i] < 0 || p->table2[i] >= b->n_tables) return -1;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Reserves of every policy at nodes [node0, node0+nnode) and scenarios
+ * [scen0, scen0+nscen).
+ *   r_all  [nnode][n][nscen][4]  reserve vector at t = 0 (states >= n_states: 0)
+ *   gross  [nnode][n][nscen]     PV(benefits) + PV(premiums), state 0 (or NULL)
+ *   totals [nnode][nscen]        sum over live policies of state-0 reserves
+ *   gross_totals [nnode][nscen]  same for gross (or NULL)
+ * Any output pointer may be NULL.  Returns 0, or -1 on invalid input.
+ */
+int orc_reserves(const orc_basis *b, const orc_portfolio *p, int node0, int nnode,
+                 int scen0, int nscen, int node_step, double *r_all, double *gross,
+                 double *totals, double *gross_totals, int n_threads)
+{
+    if (validate(b, p)) return -1;
+    if (node0 < 0 || nnode < 0 || node0 + nnode > b->n_nodes) return -1;
+    if (scen0 < 0 || nscen < 0 || scen0 + nscen > b->n_scen) return -1;
+    int n = p->n;
+    double *r0s = (double *)calloc((size_t)nnode * n * nscen, sizeof(double));
+    double *g0s = (double *)calloc((size_t)nnode * n * nscen, sizeof(double));
+    if (!r0s || !g0s) { free(r0s); free(g0s); return -2; }
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+    for (int i = 0; i < n; ++i) {
+        orc_contract k, kg;
+        orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], 0, &k);
+        orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], 1, &kg);
+        double r0[ORC_MAX_STATES], g0[ORC_MAX_STATES];
+        for (int a = 0; a < nnode; ++a) {
+            int node = node0 + a;
+            int shift = node * node_step;
+            int S = p->term[i] - shift;
+            for (int s = 0; s < nscen; ++s) {
+                size_t o = ((size_t)a * n + i) * nscen + s;
+                double *ro = r_all ? r_all + o * ORC_OUT_STATES : NULL;
+                if (ro) for (int j = 0; j < ORC_OUT_STATES; ++j) ro[j] = 0.0;
+                if (S <= 0) { r0s[o] = 0.0; g0s[o] = 0.0; if (gross) gross[o] = 0.0; continue; }
+                const double *vc = b->v + ((size_t)node * b->n_scen + (scen0 + s)) * b->n_steps;
+                recurrence_one(b, p, i, &k, node, shift, S, vc, r0, NULL);
+                if (ro) for (int j = 0; j < k.n_states && j < ORC_OUT_STATES; ++j) ro[j] = r0[j];
+                r0s[o] = r0[0];
+                if (gross || gross_totals) {
+                    recurrence_one(b, p, i, &kg, node, shift, S, vc, g0, NULL);
+                    g0s[o] = g0[0];
+                    if (gross) gross[o] = g0[0];
+                }
+            }
+        }
+    }
+    for (int a = 0; a < nnode; ++a)
+        for (int s = 0; s < nscen; ++s) {
+            neumaier tr = {0, 0}, tg = {0, 0};
+            for (int i = 0; i < n; ++i) {
+                size_t o = ((size_t)a * n + i) * nscen + s;
+                nm_add(&tr, r0s[o]);
+                nm_add(&tg, g0s[o]);
+            }
+            if (totals) totals[(size_t)a * nscen + s] = tr.s + tr.c;
+            if (gross_totals) gross_totals[(size_t)a * nscen + s] = tg.s + tg.c;
+        }
+    free(r0s);
+    free(g0s);
+    return 0;
+}
+
+/*
+ * State-0 reserve path of every policy at one node and one scenario:
+ * path[off_i + t] for t = 0..S_i, with S_i = term_i - node*node_step and
+ * off_i = sum over j < i of (max(S_j, 0) + 1) ... for expired policies
+ * (S_i <= 0) the single entry path[off_i] is 0.
+ */
+int orc_reserve_paths(const orc_basis *b, const orc_portfolio *p, int node, int scen,
+                      int node_step, double *path, int n_threads)
+{
+    if (validate(b, p)) return -1;
+    if (node < 0 || node >= b->n_nodes || scen < 0 || scen >= b->n_scen) return -1;
+    int n = p->n;
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!off) return -2;
+    off[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        int S = p->term[i] - node * node_step;
+        off[i + 1] = off[i] + (S > 0 ? S : 0) + 1;
+    }
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
+    for (int i = 0; i < n; ++i) {
+        int S = p->term[i] - node * node_step;
+        if (S <= 0) { path[off[i]] = 0.0; continue; }
+        orc_contract k;
+        double r0[ORC_MAX_STATES];
+        orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], 0, &k);
+        const double *vc = b->v + ((size_t)node * b->n_scen + scen) * b->n_steps;
+        recurrence_one(b, p, i, &k, node, node * node_step, S, vc, r0, path + off[i]);
+    }
+    free(off);
+    return 0;
+}
+
+/*
+ * Reserve summation, Eq. (3.5), for one policy at one node and scenario,
+ * evaluated independently at every t = 0..S (two nested forward loops,
+ * O(S^2) matrix products; Sec. 3.8.1).  The probability of moving from
+ * state j at t to state i at t+s+g is the (j, i) entry of the product of the
+ * one-step matrices over [t, t+s) times W_g of step t+s (Eq. (3.4)); the
+ * discount is the product of the one-step factors (Eq. (3.3)) times v^g.
+ * The boundary vector enters as a cash flow at the end of the term.
+ * Writes the full vector r_t into out[t*n_states ..] for t = 0..S.
+ */
+int orc_reserve_path_summation(const orc_basis *b, const orc_portfolio *p, int i,
+                               int node, int scen, int node_step, double *out)
+{
+    if (validate(b, p)) return -1;
+    int shift = node * node_step;
+    int S = p->term[i] - shift;
+    if (S <= 0) return -1;
+    orc_contract k;
+    orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], 0, &k);
+    int n = k.n_states;
+    double m = b->shock ? b->shock[node] : 1.0;
+    const double *vc = b->v + ((size_t)node * b->n_scen + scen) * b->n_steps;
+    double P[ORC_MAX_STATES * ORC_MAX_STATES], T[ORC_MAX_STATES * ORC_MAX_STATES];
+    double Wg[ORC_MAX_STATES * ORC_MAX_STATES], PW[ORC_MAX_STATES * ORC_MAX_STATES];
+    double y[ORC_MAX_STATES], q[2];
+    const double *streams[3] = {k.c_prem, k.c_ann, k.c_ben};
+    double gs[3] = {0.0, k.f_ann, 1.0};
+    for (int t = 0; t <= S; ++t) {
+        double r[ORC_MAX_STATES] = {0};
+        /* P = identity (probabilities from t to t), D = 1 */
+        for (int a = 0; a < n * n; ++a) P[a] = 0.0;
+        for (int a = 0; a < n; ++a) P[a * n + a] = 1.0;
+        double D = 1.0;
+        for (int u = t; u < S; ++u) {
+            step_q(b, p, i, shift, m, u, q);
+            double v = vc[u];
+            for (int st = 0; st < 3; ++st) {
+                orc_build_w(k.n_lives, k.life_model, q, gs[st], Wg);
+                matmul(P, Wg, n, PW);
+                matvec(PW, streams[st], n, y);
+                double d = D * pow(v, gs[st]);
+                for (int j = 0; j < n; ++j) r[j] += d * y[j];
+            }
+            orc_build_w(k.n_lives, k.life_model, q, 1.0, Wg);
+            matmul(P, Wg, n, T);
+            memcpy(P, T, sizeof(double) * n * n);
+            D *= v;
+        }
+        matvec(P, k.boundary, n, y);
+        for (int j = 0; j < n; ++j) r[j] += D * y[j];
+        for (int j = 0; j < n; ++j) out[(size_t)t * n + j] = r[j];
+    }
+    return n;
+}
+
+/* Number of states of a product's model (for callers sizing buffers). */
+int orc_n_states(int product)
+{
+    orc_contract k;
+    if (orc_contract_of(product, 1, 1.0, 0.0, 0, &k)) return -1;
+    return k.n_states;
+}

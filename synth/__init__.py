@@ -1,0 +1,374 @@
+"""Seeded synthetic inputs for the reserve recurrence.
+
+This module only draws and shapes inputs: mortality tables, discount
+curves, portfolios and the sampling recipe for surrogate training.  It holds
+none of the valuation arithmetic (no discounting of cash flows, no transition
+matrices, no reserves); both the CPU oracle and the GPU library consume what
+it returns, as plain NumPy arrays.
+
+The paper states that mortality and interest may come from any model that
+yields the one-step quantities when needed (Sec. 3.7.2, 3.7.3) and evaluates
+its method on its own synthetic annuity data (Sec. 5), which is not
+published.  The recipes here stand in for those data:
+
+* mortality: Gompertz-Makeham force mu(x) = A + B c^x (A=5e-4, B=7.5e-5,
+  c=1.1), integrated exactly over each month to give the monthly death
+  probability q by attained age in whole months; q = 1 from age 120 on
+  (the paper's limiting age, Sec. 4.1.1); per-table loadings multiply q and
+  are capped at 1;
+* interest: flat 3 % effective per year, or the Vasicek short rate
+  (a=0.1, b=0.03, sigma=0.01) simulated with the exact Gaussian transition of
+  (r, integral of r) over each month; the one-step discount factor is
+  exp(-integral of r over the month);
+* portfolios: the mixes described in the module-level ``config_*`` builders.
+
+Product codes are an interface value shared by convention with the library
+header and the oracle (each side keeps its own copy of the numbers).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# Interface values (input format): product codes and annuity timing.
+# ----------------------------------------------------------------------------
+SL_ANN = 0        # single-life annuity (2-state model, Sec. 4.1.1)
+JL_ANN = 1        # joint-life annuity (4-state model, Sec. 4.2.1 b)
+REV_ANN = 2       # reversionary annuity to the second life (Sec. 4.2.1 a)
+LS_ANN = 3        # last-survivor annuity (Sec. 4.2.1 c)
+TERM = 4          # term assurance (3-state model, Sec. 4.1.3)
+ENDOW = 5         # pure endowment (Sec. 4.1.2)
+ENDOW_ASSUR = 6   # endowment assurance: term assurance + pure endowment
+N_PRODUCTS = 7
+TWO_LIFE = (JL_ANN, REV_ANN, LS_ANN)
+
+ADVANCE = 0       # annuity paid at the start of each month (f = 0)
+ARREARS = 1       # annuity paid at the end of each month (f = 1)
+
+GM_A, GM_B, GM_C = 5e-4, 7.5e-5, 1.1
+LIMIT_AGE_M = 1440   # 120 years in months
+VAS_A, VAS_B, VAS_SIGMA, VAS_R0 = 0.1, 0.03, 0.01, 0.03
+DT = 1.0 / 12.0
+
+
+# ----------------------------------------------------------------------------
+# Mortality basis
+# ----------------------------------------------------------------------------
+def gm_monthly_q(n_ages: int, loading: float = 1.0, A: float = GM_A,
+                 B: float = GM_B, c: float = GM_C,
+                 limit_m: int = LIMIT_AGE_M) -> np.ndarray:
+    """Monthly death probability by attained age in whole months.
+
+    q(a) = 1 - exp(-int_{a/12}^{(a+1)/12} mu(s) ds) with mu(s) = A + B c^s,
+    whose integral is A/12 + (B / ln c) c^{a/12} (c^{1/12} - 1).  The loading
+    multiplies q and the result is capped at 1; ages >= limit_m die surely.
+    """
+    a = np.arange(n_ages, dtype=np.float64)
+    x = a / 12.0
+    H = A / 12.0 + (B / math.log(c)) * np.power(c, x) * (c ** (1.0 / 12.0) - 1.0)
+    q = -np.expm1(-H)
+    q = np.minimum(1.0, loading * q)
+    q[np.arange(n_ages) >= limit_m] = 1.0
+    return q
+
+
+def mortality_tables(n_ages: int, loadings) -> np.ndarray:
+    """Stack of GM tables, one per loading: shape [n_tables, n_ages]."""
+    return np.stack([gm_monthly_q(n_ages, lam) for lam in loadings])
+
+
+# ----------------------------------------------------------------------------
+# Interest basis
+# ----------------------------------------------------------------------------
+def flat_v(n_steps: int, annual_rate: float = 0.03) -> np.ndarray:
+    """One-step (monthly) discount factors for a flat effective annual rate."""
+    return np.full(n_steps, (1.0 + annual_rate) ** (-1.0 / 12.0))
+
+
+def vasicek_paths(rng: np.random.Generator, n_paths: int, n_steps: int,
+                  r0, a: float = VAS_A, b: float = VAS_B,
+                  sigma: float = VAS_SIGMA, dt: float = DT):
+    """Exact simulation of the Vasicek short rate and its monthly integral.
+
+    Returns (v, r): v[p, t] = exp(-int_t^{t+dt} r) and r[p, t] for
+    t = 0..n_steps (r[:, 0] = r0).  The pair (r_{t+dt}, int r) is jointly
+    Gaussian given r_t (Glasserman, Monte Carlo Methods in Financial
+    Engineering, Sec. 3.3); it is sampled with two independent normals.
+    """
+    r0 = np.broadcast_to(np.asarray(r0, dtype=np.float64), (n_paths,))
+    e = math.exp(-a * dt)
+    mr_coef = e
+    var_r = sigma ** 2 * (1.0 - e * e) / (2.0 * a)
+    var_y = (sigma ** 2 / a ** 2) * (dt - 2.0 * (1.0 - e) / a + (1.0 - e * e) / (2.0 * a))
+    cov = (sigma ** 2 / (2.0 * a ** 2)) * (1.0 - e) ** 2
+    sd_r = math.sqrt(var_r)
+    sd_y = math.sqrt(var_y)
+    rho = cov / (sd_r * sd_y)
+    sd_y_perp = sd_y * math.sqrt(max(0.0, 1.0 - rho * rho))
+    r = np.empty((n_paths, n_steps + 1))
+    y = np.empty((n_paths, n_steps))
+    r[:, 0] = r0
+    for t in range(n_steps):
+        z = rng.standard_normal((2, n_paths))
+        rt = r[:, t]
+        y[:, t] = b * dt + (rt - b) * (1.0 - e) / a + rho * sd_y * z[0] + sd_y_perp * z[1]
+        r[:, t + 1] = b + (rt - b) * mr_coef + sd_r * z[0]
+    return np.exp(-y), r
+
+
+def vasicek_zcb(T: float, r0: float, a: float = VAS_A, b: float = VAS_B,
+                sigma: float = VAS_SIGMA) -> float:
+    """Vasicek zero-coupon bond price P(0, T) (closed form)."""
+    Bt = (1.0 - math.exp(-a * T)) / a
+    lnA = (Bt - T) * (a * a * b - 0.5 * sigma * sigma) / (a * a) - sigma * sigma * Bt * Bt / (4.0 * a)
+    return math.exp(lnA - Bt * r0)
+
+
+# ----------------------------------------------------------------------------
+# Portfolios
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class Portfolio:
+    product: np.ndarray   # int32 [n]
+    age1_m: np.ndarray    # int32 [n] attained age of life 1 at node 0 (months)
+    age2_m: np.ndarray    # int32 [n] attained age of life 2 (two-life products)
+    term_m: np.ndarray    # int32 [n] remaining term at node 0 (months)
+    table1: np.ndarray    # int32 [n] mortality table of life 1
+    table2: np.ndarray    # int32 [n] mortality table of life 2
+    timing: np.ndarray    # int32 [n] annuity timing (ADVANCE / ARREARS)
+    amount: np.ndarray    # float64 [n] annual annuity amount or sum assured
+    premium: np.ndarray   # float64 [n] level monthly premium, paid in advance
+
+    @property
+    def n(self) -> int:
+        return int(self.product.shape[0])
+
+    def subset(self, idx) -> "Portfolio":
+        return Portfolio(**{f.name: np.ascontiguousarray(getattr(self, f.name)[idx])
+                            for f in dataclasses.fields(self)})
+
+    def scaled(self, factor: float) -> "Portfolio":
+        d = {f.name: getattr(self, f.name).copy() for f in dataclasses.fields(self)}
+        d["amount"] = d["amount"] * factor
+        d["premium"] = d["premium"] * factor
+        return Portfolio(**d)
+
+
+@dataclasses.dataclass
+class Basis:
+    q: np.ndarray           # float64 [n_tables, n_ages] monthly q by attained age (months)
+    v: np.ndarray           # float64 [n_nodes, n_scen, n_steps] one-step discount factors
+    shock: np.ndarray | None = None   # float64 [n_nodes] mortality multiplier or None
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.v.shape[0])
+
+    @property
+    def n_scen(self) -> int:
+        return int(self.v.shape[1])
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.v.shape[2])
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    basis: Basis
+    portfolio: Portfolio
+    node_step_m: int = 12
+    note: str = ""
+
+
+def _lognormal(rng, mean, sigma, size):
+    """Lognormal with the given arithmetic mean and log-scale sd sigma."""
+    mu = math.log(mean) - 0.5 * sigma * sigma
+    return rng.lognormal(mu, sigma, size)
+
+
+# Loadings on q per table: annuitants, term assurance, endowments.
+TABLE_ANNUITANT, TABLE_TERM, TABLE_ENDOW = 0, 1, 2
+C2_LOADINGS = (0.80, 1.20, 1.00)
+
+
+def _premiums(rng, product, age1_m, term_m, sa):
+    """Level monthly premiums by a simple rating rule (not a valuation).
+
+    Term assurance: sum assured times the GM force of mortality at the age
+    half way through the term, over 12, times U(0.9, 1.3).  Endowments:
+    sum assured over the number of months, times U(0.6, 0.95).  Annuities
+    are single-premium (no premiums after the valuation date).
+    """
+    n = product.shape[0]
+    prem = np.zeros(n)
+    u = rng.uniform(0.0, 1.0, n)
+    mid_age = (age1_m + 0.5 * term_m) / 12.0
+    mu_mid = (GM_A + GM_B * np.power(GM_C, mid_age)) * C2_LOADINGS[TABLE_TERM]
+    is_term = product == TERM
+    prem[is_term] = sa[is_term] * mu_mid[is_term] / 12.0 * (0.9 + 0.4 * u[is_term])
+    is_end = (product == ENDOW) | (product == ENDOW_ASSUR)
+    prem[is_end] = sa[is_end] / term_m[is_end] * (0.6 + 0.35 * u[is_end])
+    return prem
+
+
+def portfolio_single_life_annuities(rng, n: int, term_m: int = 300,
+                                    age_lo_y: int = 60, age_hi_y: int = 80,
+                                    mean_amount: float = 1.0e4,
+                                    sigma: float = 0.5,
+                                    table: int = 0,
+                                    timing: int = ARREARS) -> Portfolio:
+    """Level single-life annuities, monthly, ages uniform in whole months."""
+    age = rng.integers(age_lo_y * 12, age_hi_y * 12, n, endpoint=True).astype(np.int32)
+    amt = _lognormal(rng, mean_amount, sigma, n)
+    z = np.zeros(n, np.int32)
+    return Portfolio(product=np.full(n, SL_ANN, np.int32), age1_m=age,
+                     age2_m=z.copy(), term_m=np.full(n, term_m, np.int32),
+                     table1=np.full(n, table, np.int32), table2=np.full(n, table, np.int32),
+                     timing=np.full(n, timing, np.int32), amount=amt,
+                     premium=np.zeros(n))
+
+
+def portfolio_mixed(rng, n: int, mix=(0.4, 0.2, 0.2, 0.2),
+                    products=(SL_ANN, JL_ANN, TERM, ENDOW),
+                    age_lo_y: int = 20, age_hi_y: int = 85,
+                    term_lo_m: int = 60, term_hi_m: int = 600) -> Portfolio:
+    """Mixed portfolio: shares ``mix`` of ``products`` (exact counts, shuffled)."""
+    counts = np.floor(np.asarray(mix) * n).astype(int)
+    counts[0] += n - counts.sum()
+    product = np.concatenate([np.full(c, p, np.int32) for c, p in zip(counts, products)])
+    rng.shuffle(product)
+    age1 = rng.integers(age_lo_y * 12, age_hi_y * 12, n, endpoint=True).astype(np.int32)
+    age2 = rng.integers(age_lo_y * 12, age_hi_y * 12, n, endpoint=True).astype(np.int32)
+    term = rng.integers(term_lo_m, term_hi_m, n, endpoint=True).astype(np.int32)
+    theta = _lognormal(rng, 1.0e4, 0.5, n)
+    sa = _lognormal(rng, 1.0e5, 0.8, n)
+    is_ann = np.isin(product, (SL_ANN, JL_ANN, REV_ANN, LS_ANN))
+    amount = np.where(is_ann, theta, sa)
+    table = np.full(n, TABLE_ANNUITANT, np.int32)
+    table[product == TERM] = TABLE_TERM
+    table[(product == ENDOW) | (product == ENDOW_ASSUR)] = TABLE_ENDOW
+    premium = _premiums(rng, product, age1, term, sa)
+    is_two = np.isin(product, TWO_LIFE)
+    age2 = np.where(is_two, age2, 0).astype(np.int32)
+    return Portfolio(product=product, age1_m=age1, age2_m=age2, term_m=term,
+                     table1=table, table2=table.copy(),
+                     timing=np.full(n, ARREARS, np.int32), amount=amount,
+                     premium=premium)
+
+
+def max_attained_age(p: Portfolio) -> int:
+    a = int((p.age1_m + p.term_m).max(initial=0))
+    two = np.isin(p.product, TWO_LIFE)
+    if two.any():
+        a = max(a, int((p.age2_m[two] + p.term_m[two]).max()))
+    return a
+
+
+# ----------------------------------------------------------------------------
+# Named workloads
+# ----------------------------------------------------------------------------
+def config_c1(seed: int = 1001) -> Workload:
+    """1,000 single-life level annuities, monthly in arrears, ages 60-80,
+    300 steps, GM mortality, flat 3 %, one scenario."""
+    rng = np.random.default_rng(seed)
+    pf = portfolio_single_life_annuities(rng, 1000)
+    n_steps = 300
+    q = mortality_tables(max(max_attained_age(pf) + 1, 1), (1.0,))
+    v = flat_v(n_steps)[None, None, :]
+    return Workload("C1: 1,000 single-life annuities x 1 flat scenario, 300 monthly steps",
+                    Basis(q=q, v=v), pf)
+
+
+def config_c2(seed: int = 1002, n: int = 100_000) -> Workload:
+    """Mixed portfolio: 40 % SL, 20 % JL, 20 % term, 20 % endowments; ages
+    20-85, terms 60-600 months; one flat 3 % scenario."""
+    rng = np.random.default_rng(seed)
+    pf = portfolio_mixed(rng, n)
+    n_steps = 600
+    q = mortality_tables(max_attained_age(pf) + 1, C2_LOADINGS)
+    v = flat_v(n_steps)[None, None, :]
+    return Workload(f"C2: {n:,}-policy mixed portfolio x 1 flat scenario, 60-600 monthly steps",
+                    Basis(q=q, v=v), pf)
+
+
+def config_c3(seed: int = 1003, n: int = 10_000, n_scen: int = 1000,
+              scen_seed: int = 2003, n_steps: int = 600) -> Workload:
+    """Nested brute force: the C2 policy laws x Vasicek inner scenarios."""
+    rng = np.random.default_rng(seed)
+    pf = portfolio_mixed(rng, n)
+    q = mortality_tables(max_attained_age(pf) + 1, C2_LOADINGS)
+    srng = np.random.default_rng(scen_seed)
+    v, _ = vasicek_paths(srng, n_scen, n_steps, VAS_R0)
+    return Workload(f"C3: {n:,} mixed policies x {n_scen:,} Vasicek scenarios, 60-600 monthly steps",
+                    Basis(q=q, v=v[None]), pf)
+
+
+def config_c3a(seed: int = 1013, n: int = 10_000, n_scen: int = 1000,
+               scen_seed: int = 2013) -> Workload:
+    """C1-law single-life annuities x Vasicek scenarios, 300 steps."""
+    rng = np.random.default_rng(seed)
+    pf = portfolio_single_life_annuities(rng, n)
+    q = mortality_tables(max_attained_age(pf) + 1, (1.0,))
+    srng = np.random.default_rng(scen_seed)
+    v, _ = vasicek_paths(srng, n_scen, 300, VAS_R0)
+    return Workload(f"C3a: {n:,} single-life annuities x {n_scen:,} Vasicek scenarios, 300 steps",
+                    Basis(q=q, v=v[None]), pf)
+
+
+def outer_path(rng, n_nodes: int, node_step_m: int = 12):
+    """One outer Vasicek path observed every node_step_m months: r at nodes."""
+    _, r = vasicek_paths(rng, 1, n_nodes * node_step_m, VAS_R0)
+    return r[0, ::node_step_m][:n_nodes].copy()
+
+
+def config_c4(seed: int = 1004, n: int = 10_000, n_nodes: int = 60,
+              n_inner: int = 500, scen_seed: int = 2004,
+              shock_seed: int = 3004, n_steps: int = 600,
+              node_step_m: int = 12) -> Workload:
+    """Full nested valuation: one outer path, annual nodes, inner Vasicek
+    scenarios from each node's short rate, a mortality shock per node."""
+    rng = np.random.default_rng(seed)
+    pf = portfolio_mixed(rng, n)
+    q = mortality_tables(max_attained_age(pf) + 1, C2_LOADINGS)
+    srng = np.random.default_rng(scen_seed)
+    r_nodes = outer_path(srng, n_nodes, node_step_m)
+    v = np.empty((n_nodes, n_inner, n_steps))
+    for k in range(n_nodes):
+        v[k], _ = vasicek_paths(srng, n_inner, n_steps, r_nodes[k])
+    shock = np.random.default_rng(shock_seed).normal(1.0, 0.05, n_nodes)
+    return Workload(f"C4: {n:,} mixed policies x {n_nodes} annual nodes x {n_inner} inner Vasicek scenarios",
+                    Basis(q=q, v=v, shock=shock), pf, node_step_m=node_step_m,
+                    note=f"outer short rates {r_nodes[:3]}...")
+
+
+def random_small(rng, n: int, n_steps: int, n_scen: int = 1, n_nodes: int = 1,
+                 products=tuple(range(N_PRODUCTS)), n_tables: int = 2,
+                 random_q: bool = True, shock: bool = False) -> Workload:
+    """Small random case for parity: random q tables and random v."""
+    age_hi = 900
+    n_ages = age_hi + n_steps + 1
+    if random_q:
+        q = rng.uniform(0.0, 0.08, (n_tables, n_ages))
+        q[:, rng.integers(0, n_ages, 5)] = 0.0
+    else:
+        q = mortality_tables(n_ages, [1.0 + 0.1 * i for i in range(n_tables)])
+    v = rng.uniform(0.990, 1.0005, (n_nodes, n_scen, n_steps))
+    product = rng.choice(np.asarray(products, np.int32), n).astype(np.int32)
+    age1 = rng.integers(0, age_hi, n).astype(np.int32)
+    age2 = rng.integers(0, age_hi, n).astype(np.int32)
+    term = rng.integers(1, n_steps, n, endpoint=True).astype(np.int32)
+    t1 = rng.integers(0, n_tables, n).astype(np.int32)
+    t2 = rng.integers(0, n_tables, n).astype(np.int32)
+    timing = rng.integers(0, 2, n).astype(np.int32)
+    amount = rng.uniform(0.5, 2.0, n) * 1000.0
+    premium = rng.uniform(0.0, 5.0, n)
+    sh = rng.normal(1.0, 0.2, n_nodes) if shock else None
+    pf = Portfolio(product=product, age1_m=age1, age2_m=age2, term_m=term,
+                   table1=t1, table2=t2, timing=timing, amount=amount,
+                   premium=premium)
+    return Workload("random small", Basis(q=q, v=v, shock=sh), pf)

@@ -1,0 +1,405 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by the
+mathematics: closed forms, textbook identities between products, the
+transition matrices the paper prints, the summation definition (Eq. 3.5) on
+tiny inputs, structural invariants and the complexity shape (Sec. 5.1.2)."""
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import (ADVANCE, ARREARS, ENDOW, ENDOW_ASSUR, JL_ANN, LS_ANN,
+                   REV_ANN, SL_ANN, TERM, Basis, Portfolio)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def make_pf(product, age1, term, amount=12.0, premium=0.0, timing=ARREARS,
+            age2=0, table1=0, table2=0):
+    n = len(product)
+    arr = lambda x, dt: np.asarray(np.broadcast_to(x, (n,)), dt).copy()
+    return Portfolio(product=arr(product, np.int32), age1_m=arr(age1, np.int32),
+                     age2_m=arr(age2, np.int32), term_m=arr(term, np.int32),
+                     table1=arr(table1, np.int32), table2=arr(table2, np.int32),
+                     timing=arr(timing, np.int32), amount=arr(amount, np.float64),
+                     premium=arr(premium, np.float64))
+
+
+def basis(q_tables, v, shock=None):
+    q = np.atleast_2d(np.asarray(q_tables, np.float64))
+    v = np.asarray(v, np.float64)
+    if v.ndim == 1:
+        v = v[None, None, :]
+    elif v.ndim == 2:
+        v = v[None]
+    return Basis(q=q, v=v, shock=shock)
+
+
+def r0(b, pf, **kw):
+    return oracle.reserves(b, pf, **kw)["r_all"][0, :, 0, :]
+
+
+N_AGES = 2000
+V_FLAT = 1.03 ** (-1.0 / 12.0)
+
+
+def gm(load=1.0):
+    return synth.gm_monthly_q(N_AGES, load)
+
+
+# --------------------------------------------------------------------------
+# Closed forms with zero mortality (annuities certain) and v = 1
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 7, 120, 300, 600])
+def test_annuity_certain_arrears_and_advance(n):
+    b = basis(np.zeros(N_AGES), np.full(600, V_FLAT))
+    pf = make_pf([SL_ANN, SL_ANN], 700, n, amount=12.0, timing=[ARREARS, ADVANCE])
+    r = r0(b, pf)
+    v = V_FLAT
+    i_m = 1.0 / v - 1.0
+    d = 1.0 - v
+    assert r[0, 0] == pytest.approx((1 - v ** n) / i_m, rel=1e-13)
+    assert r[1, 0] == pytest.approx((1 - v ** n) / d, rel=1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 60, 600])
+def test_annuity_undiscounted_is_expected_number_of_payments(n):
+    q = gm(1.0)
+    b = basis(q, np.ones(600))
+    age = 800
+    pf = make_pf([SL_ANN, SL_ANN], age, n, amount=12.0, timing=[ARREARS, ADVANCE])
+    r = r0(b, pf)
+    p = 1.0 - q[age:age + n]
+    kp = np.cumprod(p)                         # P(alive at k), k = 1..n
+    assert r[0, 0] == pytest.approx(kp.sum(), rel=1e-13)
+    assert r[1, 0] == pytest.approx(1.0 + kp[:-1].sum(), rel=1e-13)
+
+
+def test_term_assurance_closed_forms():
+    q = gm(1.2)
+    n, age, SA, P = 240, 600, 1.0e5, 37.5
+    # v = 1, no premium: probability of death within the term
+    b = basis(q, np.ones(600))
+    r = r0(b, make_pf([TERM], age, n, amount=SA))
+    npx = np.prod(1.0 - q[age:age + n])
+    assert r[0, 0] == pytest.approx(SA * (1.0 - npx), rel=1e-12)
+    # zero mortality: only premiums, an annuity-certain due
+    b0 = basis(np.zeros(N_AGES), np.full(600, V_FLAT))
+    r = r0(b0, make_pf([TERM], age, n, amount=SA, premium=P))
+    d = 1.0 - V_FLAT
+    assert r[0, 0] == pytest.approx(-P * (1 - V_FLAT ** n) / d, rel=1e-13)
+    assert r[0, 1] == 0.0 and r[0, 2] == 0.0
+
+
+def test_endowment_closed_forms():
+    n, age, SA, P = 180, 500, 5.0e4, 200.0
+    b0 = basis(np.zeros(N_AGES), np.full(600, V_FLAT))
+    v = V_FLAT
+    r = r0(b0, make_pf([ENDOW, ENDOW], age, n, amount=SA, premium=[0.0, P]))
+    assert r[0, 0] == pytest.approx(SA * v ** n, rel=1e-13)
+    assert r[1, 0] == pytest.approx(SA * v ** n - P * (1 - v ** n) / (1 - v), rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Textbook identities between products, any mortality
+# --------------------------------------------------------------------------
+def test_arrears_equals_due_minus_one_plus_pure_endowment():
+    rng = np.random.default_rng(7)
+    q = gm(0.9)
+    v = rng.uniform(0.995, 1.0, 600)             # time-varying interest
+    b = basis(q, v)
+    age, n = 777, 333
+    pf = make_pf([SL_ANN, SL_ANN, ENDOW], age, n, amount=[12.0, 12.0, 1.0],
+                 timing=[ARREARS, ADVANCE, ARREARS])
+    r = r0(b, pf)
+    assert r[0, 0] == pytest.approx(r[1, 0] - 1.0 + r[2, 0], rel=1e-13)
+
+
+def test_endowment_assurance_is_one_minus_d_times_annuity_due():
+    q = gm(1.1)
+    b = basis(q, np.full(600, V_FLAT))
+    age, n = 400, 420
+    pf = make_pf([ENDOW_ASSUR, SL_ANN], age, n, amount=[1.0, 12.0], timing=ADVANCE)
+    r = r0(b, pf)
+    d = 1.0 - V_FLAT
+    assert r[0, 0] == pytest.approx(1.0 - d * r[1, 0], rel=1e-13)
+
+
+def test_term_plus_pure_endowment_is_endowment_assurance():
+    rng = np.random.default_rng(11)
+    q = gm(1.0)
+    b = basis(q, rng.uniform(0.996, 1.0, 600))
+    pf = make_pf([TERM, ENDOW, ENDOW_ASSUR], 300, 480, amount=2.0e5,
+                 premium=[55.0, 0.0, 55.0])
+    r = r0(b, pf)
+    assert r[2, 0] == pytest.approx(r[0, 0] + r[1, 0], rel=1e-12)
+
+
+def test_two_life_annuity_identities():
+    """a_xy(LS) = a_x + a_y - a_xy; a_x|y = a_y - a_xy; the reserve vectors
+    read as in Sec. 4.2.1: REV -> (a_x|y, 0, a_y, 0), LS -> (LS, a_x, a_y, 0)."""
+    rng = np.random.default_rng(3)
+    q = np.stack([gm(0.8), gm(1.3)])
+    b = basis(q, rng.uniform(0.996, 1.0, 600))
+    x, y, n = 820, 760, 500
+    for timing in (ARREARS, ADVANCE):
+        pf = make_pf([SL_ANN, SL_ANN, JL_ANN, REV_ANN, LS_ANN],
+                     [x, y, x, x, x], n, amount=1200.0, timing=timing,
+                     age2=[0, 0, y, y, y], table1=[0, 1, 0, 0, 0],
+                     table2=[0, 0, 1, 1, 1])
+        r = r0(b, pf)
+        ax, ay, axy, rev, ls = r[0, 0], r[1, 0], r[2, 0], r[3], r[4]
+        assert ls[0] == pytest.approx(ax + ay - axy, rel=1e-12)
+        assert rev[0] == pytest.approx(ay - axy, rel=1e-12)
+        assert rev[1] == 0.0 and rev[3] == 0.0
+        assert rev[2] == pytest.approx(ay, rel=1e-13)
+        assert ls[1] == pytest.approx(ax, rel=1e-13)
+        assert ls[2] == pytest.approx(ay, rel=1e-13)
+        assert ls[3] == 0.0
+        assert np.all(r[2, 1:] == 0.0)          # joint life: zero-reserve states
+
+
+def test_joint_life_with_immortal_second_life_is_single_life():
+    q1 = gm(1.0)
+    q = np.stack([q1, np.zeros(N_AGES)])
+    b = basis(q, np.full(600, V_FLAT))
+    pf = make_pf([SL_ANN, JL_ANN], 700, 400, amount=999.0, age2=[0, 100],
+                 table1=0, table2=1)
+    r = r0(b, pf)
+    assert r[1, 0] == r[0, 0]
+
+
+def test_joint_life_symmetric():
+    q = gm(1.0)
+    b = basis(q, np.full(600, V_FLAT))
+    pf = make_pf([JL_ANN, JL_ANN], [700, 850], 400, amount=999.0, age2=[850, 700])
+    r = r0(b, pf)
+    assert r[0, 0] == pytest.approx(r[1, 0], rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Boundaries (Sec. 4.1.1 - 4.1.3): reserve at expiry, limiting age
+# --------------------------------------------------------------------------
+def test_boundaries_at_expiry_and_limiting_age():
+    q = gm(1.0)
+    b = basis(q, np.full(600, V_FLAT))
+    n = 200
+    pf = make_pf([TERM, ENDOW, SL_ANN], 1300, n, amount=1000.0, premium=[3.0, 3.0, 0.0])
+    path, off = oracle.reserve_paths(b, pf)
+    assert path[off[0] + n] == 0.0              # term assurance: 0 at expiry
+    assert path[off[1] + n] == 1000.0           # endowment: sum assured at maturity
+    sl = path[off[2]:off[3]]
+    # life reaches 120 years (1440 months) at t = 140: q = 1 from then on, so
+    # an annuity in arrears has no value from t = 140 on.
+    assert np.all(sl[1440 - 1300:] == 0.0)
+    assert sl[1440 - 1300 - 1] > 0.0
+
+
+# --------------------------------------------------------------------------
+# Recurrence (Eq. 3.1) == summation (Eq. 3.5) on tiny random inputs
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_recurrence_equals_summation(seed):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=24, n_steps=60, n_scen=2, n_nodes=3, shock=True)
+    b, pf = w.basis, w.portfolio
+    for node in range(3):
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=1, node_step=12)
+        full = oracle.reserves(b, pf, node0=node, nnode=1, scen0=1, nscen=1, node_step=12)
+        for i in range(pf.n):
+            S = int(pf.term_m[i]) - 12 * node
+            if S <= 0:
+                assert path[off[i]] == 0.0
+                continue
+            summ = oracle.reserve_path_summation(b, pf, i, node=node, scen=1, node_step=12)
+            scale = np.abs(summ).max() + 1e-300
+            np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0],
+                                       rtol=0, atol=1e-12 * scale)
+            ns = summ.shape[1]
+            np.testing.assert_allclose(full["r_all"][0, i, 0, :min(ns, 4)], summ[0, :4],
+                                       rtol=0, atol=1e-12 * scale)
+
+
+# --------------------------------------------------------------------------
+# Transition matrices: the paper's printed matrices, invariants
+# --------------------------------------------------------------------------
+def _golden_matrices():
+    blocks, cur = [], None
+    with open(os.path.join(HERE, "golden", "transition_matrices.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("matrix"):
+                parts = line.split()
+                cur = {"name": parts[1], "lives": int(parts[2].split("=")[1]),
+                       "model": int(parts[3].split("=")[1]), "rows": []}
+                blocks.append(cur)
+            else:
+                cur["rows"].append(line.split())
+    return blocks
+
+
+@pytest.mark.parametrize("g", [1.0, 0.0])
+def test_kronecker_matrices_match_the_paper(g):
+    qx, qy = 0.013, 0.041
+    px, py = 1 - g * qx, 1 - g * qy
+    env = {"px": px, "qx": g * qx, "py": py, "qy": g * qy}
+    blocks = _golden_matrices()
+    assert len(blocks) == 4
+    for blk in blocks:
+        expect = np.array([[eval(e, {}, dict(env)) for e in row] for row in blk["rows"]], float)
+        got = oracle.build_w(blk["lives"], blk["model"], [qx, qy][: blk["lives"]], g)
+        np.testing.assert_allclose(got, expect, rtol=0, atol=1e-15, err_msg=blk["name"])
+
+
+def test_last_survivor_payment_probability_is_top_row():
+    qx, qy, f = 0.02, 0.05, 1.0
+    W = oracle.build_w(2, 2, [qx, qy], f)
+    assert W[0, :3].sum() == pytest.approx(1.0 - qx * qy, rel=1e-15)
+
+
+@pytest.mark.parametrize("lives,model,n,nnz", [(1, 2, 2, 3), (2, 2, 4, 9), (3, 2, 8, 27),
+                                               (1, 3, 3, 4), (2, 3, 9, 16)])
+def test_state_and_nonzero_counts(lives, model, n, nnz):
+    """2^m / 3^m states and 3^m / 4^m non-zeros (Sec. 4.3); rows sum to 1;
+    binary labelling makes W upper triangular (Sec. 2.4.2)."""
+    q = [0.01, 0.02, 0.03][:lives]
+    W = oracle.build_w(lives, model, q, 1.0)
+    assert W.shape == (n, n)
+    assert np.count_nonzero(W) == nnz
+    np.testing.assert_allclose(W.sum(axis=1), 1.0, atol=1e-15)
+    if model == 2:
+        assert np.all(np.tril(W, -1) == 0.0)
+
+
+# --------------------------------------------------------------------------
+# Linearity, node shift (Eq. 3.2), gross PV, totals, expiry
+# --------------------------------------------------------------------------
+def test_doubling_amounts_doubles_reserves_bitwise():
+    rng = np.random.default_rng(5)
+    w = synth.random_small(rng, n=40, n_steps=120, n_scen=2)
+    a = oracle.reserves(w.basis, w.portfolio)["r_all"]
+    b = oracle.reserves(w.basis, w.portfolio.scaled(2.0))["r_all"]
+    assert np.array_equal(b, 2.0 * a)
+
+
+def test_node_shift_equals_path_under_flat_rates():
+    q = gm(1.0)
+    v = np.full((5, 1, 600), V_FLAT)
+    b = Basis(q=np.atleast_2d(q), v=v)
+    pf = make_pf([SL_ANN, TERM, ENDOW, JL_ANN], [700, 400, 500, 650], [600, 500, 480, 550],
+                 amount=[1200.0, 1e5, 5e4, 900.0], premium=[0, 30.0, 120.0, 0],
+                 age2=[0, 0, 0, 720])
+    path, off = oracle.reserve_paths(b, pf, node=0)
+    full = oracle.reserves(b, pf, node_step=12)
+    for k in range(5):
+        for i in range(pf.n):
+            assert full["r_all"][k, i, 0, 0] == path[off[i] + 12 * k]
+
+
+def test_gross_bounds_reserve_and_equals_it_for_annuities():
+    rng = np.random.default_rng(9)
+    w = synth.random_small(rng, n=60, n_steps=100)
+    out = oracle.reserves(w.basis, w.portfolio)
+    r = out["r_all"][0, :, 0, 0]
+    g = out["gross"][0, :, 0]
+    assert np.all(g + 1e-9 >= np.abs(r))
+    ann = np.isin(w.portfolio.product, (SL_ANN, JL_ANN, REV_ANN, LS_ANN)) & (w.portfolio.premium == 0)
+    np.testing.assert_array_equal(g[ann], r[ann])
+
+
+def test_totals_are_accurately_rounded_sums_and_skip_expired():
+    rng = np.random.default_rng(13)
+    w = synth.random_small(rng, n=200, n_steps=48, n_scen=3, n_nodes=4)
+    out = oracle.reserves(w.basis, w.portfolio, node_step=12)
+    for k in range(4):
+        live = w.portfolio.term_m - 12 * k > 0
+        assert np.all(out["r_all"][k, ~live] == 0.0)
+        for s in range(3):
+            exact = math.fsum(out["r_all"][k, :, s, 0])
+            assert out["totals"][k, s] == pytest.approx(exact, rel=1e-15, abs=1e-300)
+
+
+def test_node_stats_quantile():
+    tot = np.arange(1000, dtype=float)[None, ::-1].copy()
+    mean, qv = oracle.node_stats(tot)
+    assert qv[0] == 995.0                          # 5th largest of 1,000
+    tot = np.arange(500, dtype=float)[None]
+    assert oracle.node_stats(tot)[1][0] == 497.0   # 3rd largest of 500
+    assert oracle.node_stats(tot)[0][0] == 249.5
+
+
+def test_oracle_rejects_invalid_input():
+    b = basis(gm(1.0), np.full(600, V_FLAT))
+    with pytest.raises(ValueError):
+        oracle.reserves(b, make_pf([SL_ANN], 700, 601))
+    with pytest.raises(ValueError):
+        oracle.reserves(b, make_pf([9], 700, 10))
+    with pytest.raises(ValueError):
+        oracle.reserves(b, make_pf([SL_ANN], N_AGES - 5, 10))
+
+
+# --------------------------------------------------------------------------
+# Complexity shape (Sec. 3.8, Fig. 1): linear vs quadratic in S
+# --------------------------------------------------------------------------
+def _min_time(fn, reps=5):
+    best = float("inf")
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        best = min(best, time.perf_counter() - t)
+    return best
+
+
+def test_complexity_linear_vs_quadratic():
+    q = gm(1.0)
+    b = basis(q, np.full(1200, V_FLAT))
+    S1, S2 = 150, 600
+    pf1 = make_pf([SL_ANN] * 400, 100, S1)
+    pf2 = make_pf([SL_ANN] * 400, 100, S2)
+    t1 = _min_time(lambda: oracle.reserves(b, pf1, want_gross=False, n_threads=1))
+    t2 = _min_time(lambda: oracle.reserves(b, pf2, want_gross=False, n_threads=1))
+    lin = math.log(t2 / t1) / math.log(S2 / S1)
+    one1 = make_pf([SL_ANN], 100, S1)
+    one2 = make_pf([SL_ANN], 100, S2)
+    s1 = _min_time(lambda: oracle.reserve_path_summation(b, one1, 0), reps=3)
+    s2 = _min_time(lambda: oracle.reserve_path_summation(b, one2, 0), reps=3)
+    quad = math.log(s2 / s1) / math.log(S2 / S1)
+    assert 0.7 < lin < 1.35, lin
+    assert 1.7 < quad < 2.3, quad
+
+
+def test_node_shock_equals_scaled_table_and_nodes_use_their_own_curves():
+    """Node k: ages + 12k, term - 12k, curve v[k], q scaled by m_k (capped)."""
+    rng = np.random.default_rng(21)
+    q = rng.uniform(0.0, 0.3, 1400)
+    v = rng.uniform(0.99, 1.0, (3, 2, 300))
+    shock = np.array([1.0, 1.7, 3.5])
+    pf = make_pf([SL_ANN, TERM, ENDOW_ASSUR, REV_ANN, LS_ANN], [100, 200, 300, 400, 500],
+                 [300, 250, 200, 280, 290], amount=[1200.0, 1e4, 1e4, 600.0, 600.0],
+                 premium=[0, 2.0, 9.0, 0, 0], age2=[0, 0, 0, 350, 450])
+    full = oracle.reserves(Basis(q=q[None], v=v, shock=shock), pf, node_step=12)
+    for k in range(3):
+        qk = np.minimum(1.0, shock[k] * q)
+        pk = pf.subset(np.arange(pf.n))
+        pk.age1_m = pf.age1_m + 12 * k
+        pk.age2_m = pf.age2_m + 12 * k
+        pk.term_m = pf.term_m - 12 * k
+        for s in range(2):
+            bk = Basis(q=qk[None], v=v[k:k + 1, s:s + 1, :])
+            ref = oracle.reserves(bk, pk)["r_all"][0, :, 0, :]
+            np.testing.assert_array_equal(full["r_all"][k, :, s, :], ref)
+
+
+def test_scenario_window_matches_single_scenario_basis():
+    rng = np.random.default_rng(23)
+    w = synth.random_small(rng, n=30, n_steps=50, n_scen=5)
+    part = oracle.reserves(w.basis, w.portfolio, scen0=2, nscen=2)["r_all"]
+    for s in (2, 3):
+        b1 = Basis(q=w.basis.q, v=w.basis.v[:, s:s + 1, :])
+        one = oracle.reserves(b1, w.portfolio)["r_all"]
+        np.testing.assert_array_equal(part[:, :, s - 2, :], one[:, :, 0, :])
