@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark: policy x scenario reserve valuations per second, exact FP64.
+
+Workload (one step = one full pass of the hot path): 10,000 mixed policies
+(40 % single-life annuities, 20 % joint-life annuities, 20 % term
+assurances, 20 % endowments; ages 20-85, remaining terms 60-600 months) x
+1,000 Vasicek inner scenarios, FP64 backward recurrence to t = 0 for every
+policy x scenario, per-policy reserves written to HBM, portfolio totals per
+scenario and the 1-in-200 tail statistic.  Inputs are seeded synthetic data
+resident in device memory before timing starts.
+
+Prints one JSON line.  Also measured: the recurrence kernel's duration with
+HIP events around every launch of a second timed region (roofline), the
+same workload's single-scenario and 60-node variants, and the CPU oracle on a
+bounded sample of the workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, FMA = 2 flops
+FP64_ISSUE_PEAK = 39.3e12      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one op per lane-cycle
+
+
+def scenario_step_work(pf, node=0, node_step=12):
+    """Algorithmic FP64 flops and VALU ops per scenario of one pass, summed over
+    policies: the per-scenario arithmetic of the zero-reserve-reduced
+    recurrence (per-policy work shared by all scenarios is not counted)."""
+    import synth
+    S = np.maximum(pf.term_m.astype(np.int64) - node * node_step, 0)
+    prod = pf.product
+    prem = pf.premium > 0
+    arrears = pf.timing == synth.ARREARS
+    flops = np.zeros(pf.n)
+    ops = np.zeros(pf.n)
+    # single-state recurrences: r = a0 + v (p r + c)
+    single = np.isin(prod, (synth.SL_ANN, synth.JL_ANN, synth.TERM, synth.ENDOW, synth.ENDOW_ASSUR))
+    c_nonzero = ((np.isin(prod, (synth.SL_ANN, synth.JL_ANN)) & arrears) |
+                 np.isin(prod, (synth.TERM, synth.ENDOW_ASSUR)))
+    a0_nonzero = prem | (np.isin(prod, (synth.SL_ANN, synth.JL_ANN)) & ~arrears)
+    flops[single] = (np.where(c_nonzero, 2, 1) + np.where(a0_nonzero, 2, 1))[single]
+    ops[single] = 2
+    rev = prod == synth.REV_ANN
+    flops[rev] = (4 + np.where(prem, 2, 1) + 2 + np.where(~arrears, 2, 1))[rev]
+    ops[rev] = 5
+    ls = prod == synth.LS_ANN
+    flops[ls] = (6 + np.where(prem | ~arrears, 2, 1) + 2 * (2 + np.where(~arrears, 2, 1)))[ls]
+    ops[ls] = 8
+    return float((flops * S).sum()), float((ops * S).sum()), int((S > 0).sum()), int(S.sum())
+
+
+def timed_steps(fn, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(w, seconds_target=15.0):
+    """The oracle as it stands, on a bounded sample of the workload."""
+    import oracle
+    threads = int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
+    b, pf = w.basis, w.portfolio
+    # calibrate on a small sample, then size the sample to ~seconds_target
+    n_pol, n_scen = min(pf.n, 2000), 2
+    t0 = time.perf_counter()
+    oracle.reserves(b, pf.subset(np.arange(n_pol)), 0, 1, 0, n_scen, want_gross=False, n_threads=threads)
+    dt = time.perf_counter() - t0
+    per_val = dt / (n_pol * n_scen)
+    n_scen2 = int(max(1, min(b.n_scen, seconds_target / (per_val * n_pol))))
+    t0 = time.perf_counter()
+    oracle.reserves(b, pf.subset(np.arange(n_pol)), 0, 1, 0, n_scen2, want_gross=False, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n_pol * n_scen2 / dt, "unit": "valuations/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n_pol} policies x first {n_scen2} scenarios of the workload "
+                      f"({dt:.1f} s, dense general-form recurrence, {threads} OpenMP threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the C2 / C4 variants")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (traffic counter calibration)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the timed region of the headline workload (for profiling)")
+    ap.add_argument("--block-k", type=int, default=0, help="pin scenarios per lane (0 = autotune)")
+    ap.add_argument("--wg", type=int, default=0, help="pin workgroups per CU (0 = autotune)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU available"}))
+        sys.exit(1)
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 8}))
+        return
+
+    import paper_1401_1757_amd as rr
+    import synth
+
+    sync = torch.cuda.synchronize
+    w = synth.config_c3()
+    b, pf = w.basis, w.portfolio
+    ctx = rr.Context(0)
+    t0 = time.perf_counter()
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    sync()
+    upload_s = time.perf_counter() - t0
+    out = ctx.alloc_outputs(1, b.n_scen, stats=True)
+    ctx.set_option(rr.OPT_BLOCK_K, args.block_k)
+    ctx.set_option(rr.OPT_WG_PER_CU, args.wg)
+
+    def step():
+        ctx.reserve_recurrence(0, 1, 0, b.n_scen, 12, out)
+
+    t0 = time.perf_counter()
+    step()                       # first call: autotune + plan + graph capture
+    sync()
+    first_call_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        step()
+    sync()
+    elapsed = timed_steps(step, args.steps, sync)
+    ms_per_step = 1e3 * elapsed / args.steps
+    flops, ops, live, vsteps = scenario_step_work(pf)
+    n_val = live * b.n_scen
+    value = n_val / (elapsed / args.steps)
+    if args.kernel_only:
+        print(json.dumps({"ms_per_step": ms_per_step, "value": value,
+                          "block_k": ctx.get_option(rr.OPT_LAST_K),
+                          "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG)}))
+        ctx.close()
+        return
+
+    # Second timed region: HIP events around every recurrence kernel launch.
+    ctx.set_option(rr.OPT_KERNEL_TIMING, 1)
+    ctx.kernel_times()
+    elapsed_direct = timed_steps(step, args.steps, sync)
+    kms = ctx.kernel_times()
+    ctx.set_option(rr.OPT_KERNEL_TIMING, 0)
+    kernel_ms = float(np.mean(kms))
+    achieved = flops * b.n_scen / (kernel_ms * 1e-3) / 1e12
+    issue_frac = ops * b.n_scen / (kernel_ms * 1e-3) / FP64_ISSUE_PEAK
+    k_opt = ctx.get_option(rr.OPT_LAST_K)
+    wg_opt = ctx.get_option(rr.OPT_LAST_WG)
+
+    result = {
+        "metric": "policy x scenario reserve valuations/s (exact FP64 backward recurrence)",
+        "value": value,
+        "unit": "valuations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded): GM mortality, Vasicek scenarios, mixed portfolio",
+        "config": {"workload": w.name, "policies": pf.n, "scenarios": b.n_scen,
+                   "max_steps": b.n_steps, "valuations_per_step": n_val,
+                   "valuation_steps_per_step": vsteps * b.n_scen,
+                   "outputs": "r0 [policy][scenario] + totals + tail statistic"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_recurrence", "kernel_ms": kernel_ms,
+                     "kernel_launches": len(kms),
+                     "algorithmic_flops_per_launch": flops * b.n_scen,
+                     "issue_frac": issue_frac,
+                     "flop_cap": flops / (2 * ops)},
+        "valuation_steps_per_s": vsteps * b.n_scen / (elapsed / args.steps),
+        "ms_per_step_direct_launch": 1e3 * elapsed_direct / args.steps,
+        "first_call_s": first_call_s,
+        "upload_s": upload_s,
+        "launch": {"block_k": k_opt, "wg_per_cu": wg_opt, "autotuned": args.block_k == 0},
+    }
+
+    if not args.no_secondary:
+        sec = {}
+        w2 = synth.config_c2()
+        ctx.basis_upload(w2.basis.q, w2.basis.v)
+        ctx.portfolio_upload(w2.portfolio)
+        o2 = ctx.alloc_outputs(1, 1)
+        f2 = lambda: ctx.reserve_recurrence(0, 1, 0, 1, 12, o2)
+        for _ in range(3):
+            f2()
+        e2 = timed_steps(f2, 20, sync)
+        sec["C2_single_scenario"] = {"valuations_per_s": w2.portfolio.n / (e2 / 20),
+                                     "ms_per_step": 1e3 * e2 / 20, "policies": w2.portfolio.n}
+        w4 = synth.config_c4()
+        ctx.basis_upload(w4.basis.q, w4.basis.v, w4.basis.shock)
+        ctx.portfolio_upload(w4.portfolio)
+        o4 = ctx.alloc_outputs(w4.basis.n_nodes, w4.basis.n_scen, r0=False, stats=True)
+        f4 = lambda: ctx.reserve_recurrence(0, w4.basis.n_nodes, 0, w4.basis.n_scen, 12, o4)
+        for _ in range(3):
+            f4()
+        e4 = timed_steps(f4, 10, sync)
+        live4 = sum(int((w4.portfolio.term_m - 12 * k > 0).sum()) for k in range(w4.basis.n_nodes))
+        sec["C4_nested_60_nodes"] = {"valuations_per_s": live4 * w4.basis.n_scen / (e4 / 10),
+                                     "ms_per_step": 1e3 * e4 / 10,
+                                     "live_valuations": live4 * w4.basis.n_scen,
+                                     "nominal_valuations": w4.portfolio.n * w4.basis.n_nodes * w4.basis.n_scen}
+        result["secondary"] = sec
+    ctx.close()
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,269 @@
+/*
+ * rr.h -- C ABI of the MI355X reserve-recurrence library.
+ *
+ * Computes prospective reserves of non-unit-linked life policies with the
+ * general backward vector recurrence of Tucker & Bull, "An efficient
+ * algorithm for the calculation of reserves for non-unit linked life
+ * policies" (arXiv 1401.1757), Eq. (3.1):
+ *
+ *     r_t = v_t^f W_{t,f} c_t + v_t W_{t,1} r_{t+1},
+ *
+ * run backward from a boundary condition (Sec. 3.8.2), for every policy x
+ * scenario (x outer node), in FP64 on one gfx950 GPU.  W is built on the
+ * device from the per-life monthly death probabilities (Sec. 3.5, Sec. 4),
+ * v from the uploaded scenario discount curves (Sec. 3.4), c from each
+ * policy's product, amounts and timing (Sec. 3.3, Sec. 4).  Zero-reserve
+ * states are dropped as in Sec. 3.6.4; their outputs are exactly 0.
+ *
+ * Conventions used by every call:
+ *   - monthly steps; step t covers [t, t+1) months after the valuation node;
+ *     the reserve r_t is held at time t, before the premium due at t;
+ *   - premiums are paid in advance (f = 0) while every life is alive;
+ *     annuity payments at f = 0 (RR_ADVANCE) or f = 1 (RR_ARREARS); death
+ *     benefits at the end of the month of death (f = 1);
+ *   - transition matrices are row = state at the start of the step; states
+ *     use the binary (two-state lives) or ternary (assurances) labels of
+ *     Sec. 2.4.2 and Sec. 4.1.3, life 1 being the most significant digit;
+ *   - at outer node k (0-based) every life is 12*k months older (node_step_m
+ *     months per node), the remaining term is term_m - k*node_step_m and the
+ *     node's curves and mortality shock apply; policies whose remaining term
+ *     is <= 0 at a node have expired: their outputs are 0 and they are left
+ *     out of totals.
+ *
+ * Ownership: uploads copy what they are given (host or device memory) into
+ * library-owned device memory; the caller may free its buffers on return.
+ * Output buffers of rr_reserve_recurrence / rr_surrogate_infer are
+ * caller-owned device memory (e.g. torch tensors), written asynchronously
+ * on the context's stream.
+ *
+ * Errors: every call returns an rr_status; no exception crosses the ABI.  On
+ * error, rr_last_error(ctx) gives a message naming the first bad argument or
+ * policy index, valid until the next call on the context.  A context must
+ * not be used from two host threads at once; calls on one context that
+ * overlap on the GPU (different streams) race.
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rr_ctx rr_ctx;
+
+/* Status codes. */
+#define RR_OK       0
+#define RR_EINVAL  (-1)   /* invalid argument or input data */
+#define RR_ENOMEM  (-2)   /* device or host allocation failed */
+#define RR_EDEVICE (-3)   /* HIP runtime error */
+#define RR_ERANGE  (-4)   /* output buffer too small / size limit exceeded */
+#define RR_ESTATE  (-5)   /* call out of order (no basis, portfolio or model) */
+
+/* Products (Sec. 4).  Amount = annual annuity (paid amount/12 each month)
+ * for the annuities, sum assured otherwise. */
+#define RR_SL_ANN       0  /* single-life annuity, 2-state model (Sec. 4.1.1) */
+#define RR_JL_ANN       1  /* joint-life annuity, 4-state model, c = (1,0,0,0) (Sec. 4.2.1 b) */
+#define RR_REV_ANN      2  /* reversionary annuity to life 2 after life 1 dies, c = (0,0,1,0) (Sec. 4.2.1 a) */
+#define RR_LS_ANN       3  /* last-survivor annuity, c = (1,1,1,0) (Sec. 4.2.1 c) */
+#define RR_TERM         4  /* term assurance, 3-state model, c = (0,1,0), r_S = 0 (Sec. 4.1.3) */
+#define RR_ENDOW        5  /* pure endowment, boundary r_S = (SA, 0) (Sec. 4.1.2) */
+#define RR_ENDOW_ASSUR  6  /* endowment assurance: term assurance with r_S = (SA, 0, 0) */
+
+#define RR_ADVANCE 0       /* annuity paid at the start of each month (f = 0) */
+#define RR_ARREARS 1       /* annuity paid at the end of each month (f = 1) */
+
+#define RR_HOST   0        /* input arrays are in host memory */
+#define RR_DEVICE 1        /* input arrays are in device memory */
+
+/* Output selection for rr_run.out_mask. */
+#define RR_OUT_R0          1u   /* reserve at t = 0 per (node, policy, scenario) */
+#define RR_OUT_TOTALS      2u   /* portfolio total per (node, scenario) */
+#define RR_OUT_PATH        4u   /* state-0 reserve at every t (one node, one scenario) */
+#define RR_OUT_ALL_STATES  8u   /* with RR_OUT_R0: all 4 state slots, not just state 0 */
+#define RR_OUT_STATS      16u   /* per-node mean and tail quantile of the totals */
+
+/*
+ * Valuation basis: mortality tables and scenario discount curves.
+ *   q[n_tables][n_ages]      monthly death probability by attained age in whole
+ *                            months, 0 <= q <= 1 (Sec. 3.5, 3.7.3).
+ *   v[n_nodes][n_scen][n_steps]  one-step discount factor of month t for the
+ *                            scenario's interest path, 0 < v, finite
+ *                            (Sec. 3.4, 3.7.2: any interest model).
+ *   shock[n_nodes] or NULL   per-node multiplier m >= 0 on every q (capped at 1).
+ */
+typedef struct {
+    int32_t n_tables;
+    int32_t n_ages;
+    const double *q;
+    int32_t n_nodes;
+    int32_t n_scen;
+    int32_t n_steps;
+    const double *v;
+    const double *shock;
+    int32_t mem_kind;        /* RR_HOST or RR_DEVICE, for all three arrays */
+} rr_basis;
+
+/*
+ * Portfolio, structure of arrays of length n (n >= 0).  age2_m/table2 are read
+ * for two-life products only.  timing may be NULL (all RR_ARREARS); premium
+ * may be NULL (all 0).  Requirements: 1 <= term_m <= n_steps of the basis,
+ * age + term_m <= n_ages - 1 for every life used, valid table indices, finite
+ * amount and premium >= 0.
+ */
+typedef struct {
+    int32_t n;
+    const int32_t *product;
+    const int32_t *age1_m;   /* attained age of life 1 at node 0, months */
+    const int32_t *age2_m;   /* attained age of life 2 at node 0, months */
+    const int32_t *term_m;   /* remaining term at node 0, months */
+    const int32_t *table1;
+    const int32_t *table2;
+    const int32_t *timing;   /* RR_ADVANCE / RR_ARREARS */
+    const double *amount;
+    const double *premium;   /* level monthly premium, paid in advance */
+    int32_t mem_kind;        /* RR_HOST or RR_DEVICE, for all arrays */
+} rr_portfolio;
+
+/* One valuation run over nodes [node_begin, node_begin + node_count) and
+ * scenarios [scen_begin, scen_begin + scen_count) of the uploaded basis. */
+typedef struct {
+    int32_t node_begin;
+    int32_t node_count;
+    int32_t scen_begin;
+    int32_t scen_count;
+    int32_t node_step_m;     /* months between consecutive nodes (12 for annual) */
+    uint32_t out_mask;       /* RR_OUT_* */
+    double tail;             /* RR_OUT_STATS: quantile tail, e.g. 0.005 -> ceil(0.005 K)-th largest */
+} rr_run;
+
+/*
+ * Caller-owned device outputs (NULL = not wanted; must be non-NULL when the
+ * matching out_mask bit is set).
+ *   r0[node_count][n][scen_count][S]  S = 4 with RR_OUT_ALL_STATES else 1;
+ *                                     policies in upload order.
+ *   totals[node_count][scen_count]    sum of state-0 reserves of live policies.
+ *   path[sum_i (max(S_i,0) + 1)]      RR_OUT_PATH (node_count = scen_count = 1):
+ *                                     policy i, step t at offset
+ *                                     off_i + t, off_i = sum_{j<i}(max(S_j,0)+1),
+ *                                     S_i = term_i - node*node_step_m; path_cap
+ *                                     is its length in doubles.
+ *   stats[node_count][2]              RR_OUT_STATS: mean over scenarios and the
+ *                                     ceil(tail*scen_count)-th largest total.
+ */
+typedef struct {
+    double *r0;
+    double *totals;
+    double *path;
+    int64_t path_cap;
+    double *stats;
+} rr_outputs;
+
+/* Context bound to one device and one HIP stream (0 = the null stream).  The
+ * stream may be torch.cuda.current_stream().cuda_stream.  rr_create returns
+ * RR_EDEVICE when no GPU is present. */
+int rr_create(rr_ctx **out, int device, uint64_t stream);
+int rr_destroy(rr_ctx *ctx);
+const char *rr_last_error(const rr_ctx *ctx);
+int rr_set_stream(rr_ctx *ctx, uint64_t stream);
+int rr_sync(rr_ctx *ctx);   /* waits for the context's stream */
+
+/* Host-only validation (no device work); msg receives the reason. */
+int rr_check_basis(const rr_basis *b, char *msg, size_t msg_len);
+int rr_check_portfolio(const rr_portfolio *p, int32_t n_steps, int32_t n_ages,
+                       int32_t n_tables, char *msg, size_t msg_len);
+
+/* Copy the basis into device memory (curves re-laid out month-major so a
+ * wavefront reads consecutive scenarios of one month).  Replaces any
+ * previous basis; a loaded portfolio is re-checked against it. */
+int rr_basis_upload(rr_ctx *ctx, const rr_basis *b);
+
+/* Copy, check, sort (by state model, remaining term descending, age) and tile
+ * the portfolio (Sec. 3.8.2's per-policy inputs; the paper balances uneven
+ * terms with a dynamic schedule, Sec. 5.1.1). */
+int rr_portfolio_upload(rr_ctx *ctx, const rr_portfolio *p);
+
+/* Length in doubles of the RR_OUT_PATH buffer for a node. */
+int rr_path_size(rr_ctx *ctx, int32_t node, int32_t node_step_m, int64_t *n_out);
+
+/*
+ * The hot call: the backward recurrence, Eq. (3.1), for every policy x
+ * scenario x node of the run, from the boundary condition at the end of each
+ * term (Sec. 4.1.1-4.2.1) down to t = 0 (Sec. 3.8.2), plus the requested
+ * reductions.  Asynchronous on the context's stream.  RR_ESTATE without a
+ * basis and a portfolio; RR_ERANGE if path_cap is too small.
+ */
+int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out);
+
+/* Options (rr_set_option). */
+#define RR_OPT_BLOCK_K      1   /* scenarios per lane: 0 = autotune, or 1,2,4,8,16,32 */
+#define RR_OPT_WG_PER_CU    2   /* persistent workgroups per CU: 0 = autotune, 1..8 */
+#define RR_OPT_USE_GRAPH    3   /* 1 = replay captured hipGraphs (default), 0 = direct launches */
+#define RR_OPT_KERNEL_TIMING 4  /* 1 = record HIP events around each recurrence kernel */
+#define RR_OPT_XCD_QUEUES   5   /* 1 = per-XCD work queues with stealing (default), 0 = one queue */
+#define RR_OPT_LAST_K       6   /* read-only: scenarios per lane of the last launch */
+#define RR_OPT_LAST_WG      7   /* read-only: workgroups per CU of the last launch */
+int rr_set_option(rr_ctx *ctx, int32_t option, int64_t value);
+int rr_get_option(rr_ctx *ctx, int32_t option, int64_t *value);
+
+/* Durations (ms) of the recurrence kernels launched since the previous call,
+ * recorded when RR_OPT_KERNEL_TIMING is on; waits for them to finish. */
+int rr_kernel_times(rr_ctx *ctx, double *ms, int32_t cap, int32_t *count);
+
+/* ------------------------------------------------------------------------
+ * Learned reserve surrogate (an MLP, not part of the paper's method): it is
+ * trained on samples of the exact recurrence above and inferred with an
+ * exact FP64 fallback for inputs outside its training box.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n_policies;       /* training policies (uploaded with rr_surrogate_train) */
+    int32_t epochs;
+    int32_t batch;            /* rows per optimiser step, multiple of 256 */
+    float lr;                 /* Adam step size */
+    float lr_final;           /* cosine decay target */
+    uint64_t seed;            /* weight init and shuffling */
+} rr_train_cfg;
+
+typedef struct {
+    int64_t n_samples;
+    float final_loss;         /* mean squared error of the normalised target, last epoch */
+    float holdout_rel_rmse;   /* on the last 1/64 of samples (not trained on) */
+    double train_ms;
+} rr_train_report;
+
+typedef struct {
+    int64_t n_in_range;
+    int64_t n_fallback;
+} rr_infer_report;
+
+/*
+ * Train the surrogate on the GPU: the current portfolio and basis are the
+ * training set (every policy x scenario of node 0 is a sample, produced by
+ * rr_reserve_recurrence's kernels); features, normalisation, range box,
+ * yield-curve factors, forward/backward BF16 MFMA kernels and Adam all run on
+ * the device.  Replaces any loaded model.
+ */
+int rr_surrogate_train(rr_ctx *ctx, const rr_train_cfg *cfg, rr_train_report *rep);
+
+/* Model blob (versioned): weights, normalisation, range box, curve factors. */
+int rr_surrogate_get_weights(rr_ctx *ctx, void *host, size_t bytes, size_t *needed);
+int rr_surrogate_set_weights(rr_ctx *ctx, const void *host, size_t bytes);
+
+/*
+ * Same outputs as rr_reserve_recurrence (RR_OUT_R0 state 0, RR_OUT_TOTALS,
+ * RR_OUT_STATS), with the MLP where every feature of a (policy, scenario) is
+ * inside the training box and the exact FP64 recurrence otherwise.
+ * RR_ESTATE if no model is loaded.  rep may be NULL; when given, the call
+ * waits for the counts.
+ */
+int rr_surrogate_infer(rr_ctx *ctx, const rr_run *run, const rr_outputs *out,
+                       rr_infer_report *rep);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RR_H */

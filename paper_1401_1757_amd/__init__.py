@@ -1,0 +1,328 @@
+"""MI355X reserve-recurrence library: thin Python binding of librr.so.
+
+Argument marshalling only.  Every step of the valuation runs in the HIP
+kernels behind the C ABI declared in include/rr.h; torch is used for device
+memory and the stream.  Loading fails loudly when librr.so is missing or no
+GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librr.so")
+
+RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ERANGE, RR_ESTATE = 0, -1, -2, -3, -4, -5
+SL_ANN, JL_ANN, REV_ANN, LS_ANN, TERM, ENDOW, ENDOW_ASSUR = range(7)
+ADVANCE, ARREARS = 0, 1
+HOST, DEVICE = 0, 1
+OUT_R0, OUT_TOTALS, OUT_PATH, OUT_ALL_STATES, OUT_STATS = 1, 2, 4, 8, 16
+OPT_BLOCK_K, OPT_WG_PER_CU, OPT_USE_GRAPH, OPT_KERNEL_TIMING, OPT_XCD_QUEUES = 1, 2, 3, 4, 5
+OPT_LAST_K, OPT_LAST_WG = 6, 7
+
+# Every symbol include/rr.h declares.
+EXPORTS = (
+    "rr_create", "rr_destroy", "rr_last_error", "rr_set_stream", "rr_sync",
+    "rr_check_basis", "rr_check_portfolio", "rr_basis_upload", "rr_portfolio_upload",
+    "rr_path_size", "rr_reserve_recurrence", "rr_set_option", "rr_get_option",
+    "rr_kernel_times", "rr_surrogate_train", "rr_surrogate_get_weights",
+    "rr_surrogate_set_weights", "rr_surrogate_infer",
+)
+
+
+class RRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rr error {code}: {msg}")
+        self.code = code
+
+
+class Basis(ctypes.Structure):
+    _fields_ = [("n_tables", ctypes.c_int32), ("n_ages", ctypes.c_int32),
+                ("q", ctypes.c_void_p), ("n_nodes", ctypes.c_int32),
+                ("n_scen", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("v", ctypes.c_void_p), ("shock", ctypes.c_void_p),
+                ("mem_kind", ctypes.c_int32)]
+
+
+class Portfolio(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("product", ctypes.c_void_p),
+                ("age1_m", ctypes.c_void_p), ("age2_m", ctypes.c_void_p),
+                ("term_m", ctypes.c_void_p), ("table1", ctypes.c_void_p),
+                ("table2", ctypes.c_void_p), ("timing", ctypes.c_void_p),
+                ("amount", ctypes.c_void_p), ("premium", ctypes.c_void_p),
+                ("mem_kind", ctypes.c_int32)]
+
+
+class Run(ctypes.Structure):
+    _fields_ = [("node_begin", ctypes.c_int32), ("node_count", ctypes.c_int32),
+                ("scen_begin", ctypes.c_int32), ("scen_count", ctypes.c_int32),
+                ("node_step_m", ctypes.c_int32), ("out_mask", ctypes.c_uint32),
+                ("tail", ctypes.c_double)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("r0", ctypes.c_void_p), ("totals", ctypes.c_void_p),
+                ("path", ctypes.c_void_p), ("path_cap", ctypes.c_int64),
+                ("stats", ctypes.c_void_p)]
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("n_policies", ctypes.c_int32), ("epochs", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("lr_final", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int64), ("final_loss", ctypes.c_float),
+                ("holdout_rel_rmse", ctypes.c_float), ("train_ms", ctypes.c_double)]
+
+
+class InferReport(ctypes.Structure):
+    _fields_ = [("n_in_range", ctypes.c_int64), ("n_fallback", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """dlopen librr.so and declare argument types (no GPU needed to load)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1401_1757_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, u64, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64
+    sig = {
+        "rr_create": ([ctypes.POINTER(vp), ctypes.c_int, u64], ctypes.c_int),
+        "rr_destroy": ([vp], ctypes.c_int),
+        "rr_last_error": ([vp], ctypes.c_char_p),
+        "rr_set_stream": ([vp, u64], ctypes.c_int),
+        "rr_sync": ([vp], ctypes.c_int),
+        "rr_check_basis": ([ctypes.POINTER(Basis), ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+        "rr_check_portfolio": ([ctypes.POINTER(Portfolio), i32, i32, i32, ctypes.c_char_p,
+                                ctypes.c_size_t], ctypes.c_int),
+        "rr_basis_upload": ([vp, ctypes.POINTER(Basis)], ctypes.c_int),
+        "rr_portfolio_upload": ([vp, ctypes.POINTER(Portfolio)], ctypes.c_int),
+        "rr_path_size": ([vp, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
+        "rr_reserve_recurrence": ([vp, ctypes.POINTER(Run), ctypes.POINTER(Outputs)], ctypes.c_int),
+        "rr_set_option": ([vp, i32, i64], ctypes.c_int),
+        "rr_get_option": ([vp, i32, ctypes.POINTER(i64)], ctypes.c_int),
+        "rr_kernel_times": ([vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "rr_surrogate_train": ([vp, ctypes.POINTER(TrainCfg), ctypes.POINTER(TrainReport)], ctypes.c_int),
+        "rr_surrogate_get_weights": ([vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "rr_surrogate_set_weights": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "rr_surrogate_infer": ([vp, ctypes.POINTER(Run), ctypes.POINTER(Outputs),
+                                ctypes.POINTER(InferReport)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _np(x, dt):
+    return np.ascontiguousarray(x, dtype=dt)
+
+
+def basis_struct(q, v, shock=None, keep=None):
+    """Host-memory rr_basis; `keep` collects the arrays that must outlive it."""
+    q = _np(q, np.float64)
+    v = _np(v, np.float64)
+    sh = None if shock is None else _np(shock, np.float64)
+    if keep is not None:
+        keep.extend([q, v, sh])
+    return Basis(q.shape[0], q.shape[1], q.ctypes.data, v.shape[0], v.shape[1], v.shape[2],
+                 v.ctypes.data, None if sh is None else sh.ctypes.data, HOST)
+
+
+def portfolio_struct(pf, keep=None):
+    arrs = [_np(pf.product, np.int32), _np(pf.age1_m, np.int32), _np(pf.age2_m, np.int32),
+            _np(pf.term_m, np.int32), _np(pf.table1, np.int32), _np(pf.table2, np.int32),
+            _np(pf.timing, np.int32), _np(pf.amount, np.float64), _np(pf.premium, np.float64)]
+    if keep is not None:
+        keep.extend(arrs)
+    return Portfolio(arrs[0].shape[0], *[a.ctypes.data for a in arrs], HOST)
+
+
+def check_portfolio(pf, n_steps, n_ages, n_tables):
+    """Host-only validation; returns '' or the reason."""
+    lib = load_library()
+    keep = []
+    st = portfolio_struct(pf, keep)
+    buf = ctypes.create_string_buffer(512)
+    rc = lib.rr_check_portfolio(ctypes.byref(st), n_steps, n_ages, n_tables, buf, 512)
+    return "" if rc == RR_OK else buf.value.decode()
+
+
+def check_basis(q, v, shock=None):
+    lib = load_library()
+    keep = []
+    st = basis_struct(q, v, shock, keep)
+    buf = ctypes.create_string_buffer(512)
+    rc = lib.rr_check_basis(ctypes.byref(st), buf, 512)
+    return "" if rc == RR_OK else buf.value.decode()
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Context:
+    """One rr_ctx on a CUDA (HIP) device, bound to torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the reserve library runs only on a HIP device")
+        self._torch = torch
+        self.lib = load_library()
+        self.device = device
+        with torch.cuda.device(device):
+            s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        h = ctypes.c_void_p()
+        rc = self.lib.rr_create(ctypes.byref(h), device, s.cuda_stream)
+        if rc != RR_OK:
+            raise RRError(rc, "rr_create failed")
+        self.h = h
+        self.n = 0
+        self.n_nodes = self.n_scen = self.n_steps = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != RR_OK:
+            raise RRError(rc, self.lib.rr_last_error(self.h).decode())
+
+    def set_option(self, opt, value):
+        self._check(self.lib.rr_set_option(self.h, opt, int(value)))
+
+    def get_option(self, opt):
+        v = ctypes.c_int64()
+        self._check(self.lib.rr_get_option(self.h, opt, ctypes.byref(v)))
+        return v.value
+
+    def basis_upload(self, q, v, shock=None):
+        keep = []
+        st = basis_struct(q, v, shock, keep)
+        self._check(self.lib.rr_basis_upload(self.h, ctypes.byref(st)))
+        self.n_nodes, self.n_scen, self.n_steps = st.n_nodes, st.n_scen, st.n_steps
+
+    def portfolio_upload(self, pf):
+        keep = []
+        st = portfolio_struct(pf, keep)
+        self._check(self.lib.rr_portfolio_upload(self.h, ctypes.byref(st)))
+        self.n = st.n
+
+    def path_size(self, node=0, node_step=12):
+        n = ctypes.c_int64()
+        self._check(self.lib.rr_path_size(self.h, node, node_step, ctypes.byref(n)))
+        return n.value
+
+    def alloc_outputs(self, node_count, scen_count, r0=True, totals=True, all_states=False,
+                      stats=False, path_node=None, node_step=12):
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        out = {}
+        if r0:
+            shape = (node_count, self.n, scen_count) + ((4,) if all_states else ())
+            out["r0"] = torch.empty(shape, dtype=torch.float64, device=dev)
+        if totals:
+            out["totals"] = torch.empty((node_count, scen_count), dtype=torch.float64, device=dev)
+        if stats:
+            out["stats"] = torch.empty((node_count, 2), dtype=torch.float64, device=dev)
+        if path_node is not None:
+            out["path"] = torch.empty(self.path_size(path_node, node_step), dtype=torch.float64,
+                                      device=dev)
+        return out
+
+    def reserve_recurrence(self, node_begin=0, node_count=None, scen_begin=0, scen_count=None,
+                           node_step=12, outputs=None, all_states=False, tail=0.005):
+        """Run the recurrence; outputs is a dict of preallocated device tensors
+        (keys r0, totals, path, stats) or None to allocate r0 + totals."""
+        node_count = self.n_nodes - node_begin if node_count is None else node_count
+        scen_count = self.n_scen - scen_begin if scen_count is None else scen_count
+        if outputs is None:
+            outputs = self.alloc_outputs(node_count, scen_count, all_states=all_states)
+        mask = 0
+        if outputs.get("r0") is not None:
+            mask |= OUT_R0
+            if outputs["r0"].dim() == 4:
+                mask |= OUT_ALL_STATES
+        if outputs.get("totals") is not None:
+            mask |= OUT_TOTALS
+        if outputs.get("path") is not None:
+            mask |= OUT_PATH
+        if outputs.get("stats") is not None:
+            mask |= OUT_STATS
+        run = Run(node_begin, node_count, scen_begin, scen_count, node_step, mask, tail)
+        path = outputs.get("path")
+        o = Outputs(_ptr(outputs.get("r0")), _ptr(outputs.get("totals")), _ptr(path),
+                    0 if path is None else path.numel(), _ptr(outputs.get("stats")))
+        self._check(self.lib.rr_reserve_recurrence(self.h, ctypes.byref(run), ctypes.byref(o)))
+        return outputs
+
+    def sync(self):
+        self._check(self.lib.rr_sync(self.h))
+
+    def kernel_times(self, cap=4096):
+        buf = (ctypes.c_double * cap)()
+        n = ctypes.c_int32()
+        self._check(self.lib.rr_kernel_times(self.h, buf, cap, ctypes.byref(n)))
+        return [buf[i] for i in range(min(n.value, cap))]
+
+    # -- surrogate ----------------------------------------------------------
+    def surrogate_train(self, epochs=20, batch=4096, lr=2e-3, lr_final=1e-5, seed=7):
+        cfg = TrainCfg(0, epochs, batch, lr, lr_final, seed)
+        rep = TrainReport()
+        self._check(self.lib.rr_surrogate_train(self.h, ctypes.byref(cfg), ctypes.byref(rep)))
+        return {"n_samples": rep.n_samples, "final_loss": rep.final_loss,
+                "holdout_rel_rmse": rep.holdout_rel_rmse, "train_ms": rep.train_ms}
+
+    def surrogate_get_weights(self) -> bytes:
+        need = ctypes.c_size_t()
+        self.lib.rr_surrogate_get_weights(self.h, None, 0, ctypes.byref(need))
+        buf = ctypes.create_string_buffer(need.value)
+        self._check(self.lib.rr_surrogate_get_weights(self.h, buf, need.value, ctypes.byref(need)))
+        return buf.raw
+
+    def surrogate_set_weights(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self.lib.rr_surrogate_set_weights(self.h, buf, len(blob)))
+
+    def surrogate_infer(self, node_begin=0, node_count=None, scen_begin=0, scen_count=None,
+                        node_step=12, outputs=None, tail=0.005, report=True):
+        node_count = self.n_nodes - node_begin if node_count is None else node_count
+        scen_count = self.n_scen - scen_begin if scen_count is None else scen_count
+        if outputs is None:
+            outputs = self.alloc_outputs(node_count, scen_count)
+        mask = 0
+        if outputs.get("r0") is not None:
+            mask |= OUT_R0
+        if outputs.get("totals") is not None:
+            mask |= OUT_TOTALS
+        if outputs.get("stats") is not None:
+            mask |= OUT_STATS
+        run = Run(node_begin, node_count, scen_begin, scen_count, node_step, mask, tail)
+        o = Outputs(_ptr(outputs.get("r0")), _ptr(outputs.get("totals")), None, 0,
+                    _ptr(outputs.get("stats")))
+        rep = InferReport()
+        self._check(self.lib.rr_surrogate_infer(self.h, ctypes.byref(run), ctypes.byref(o),
+                                                ctypes.byref(rep) if report else None))
+        outputs["report"] = {"n_in_range": rep.n_in_range, "n_fallback": rep.n_fallback}
+        return outputs

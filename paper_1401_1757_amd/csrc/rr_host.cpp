@@ -1,0 +1,1038 @@
+// Host side of the reserve-recurrence library: the C ABI of include/rr.h,
+// input checks, the planner (sort, tiles, work queues), the autotuner, HIP
+// graph replay and kernel timing.
+#include "rr.h"
+#include "rr_internal.h"
+#include "rr_surrogate.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace rr;
+
+namespace {
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(size_t count)
+    {
+        if (count <= n && p) return hipSuccess;
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+        if (e == hipSuccess) n = count;
+        else p = nullptr;
+        return e;
+    }
+};
+
+struct Plan {
+    int K = 1;
+    int wg_per_cu = 2;
+    int grid = 1;
+    int n_items = 0;
+    int n_queues = 1;
+    DevBuf<Item> items;
+    DevBuf<int> qbeg;
+};
+
+struct PlanKey {
+    int node_begin, node_count, scen_begin, scen_count, node_step, K, queues, gen;
+    bool operator<(const PlanKey &o) const
+    {
+        return std::tie(node_begin, node_count, scen_begin, scen_count, node_step, K, queues, gen) <
+               std::tie(o.node_begin, o.node_count, o.scen_begin, o.scen_count, o.node_step, o.K,
+                        o.queues, o.gen);
+    }
+};
+
+struct TuneKey {
+    int node_count, scen_count, r0_states, has_path, gen;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(node_count, scen_count, r0_states, has_path, gen) <
+               std::tie(o.node_count, o.scen_count, o.r0_states, o.has_path, o.gen);
+    }
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;
+};
+
+}  // namespace
+
+struct rr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+    int n_cu = 256;
+    size_t lds_per_block = 65536;
+
+    // basis
+    bool has_basis = false;
+    int n_tables = 0, n_ages = 0, n_nodes = 0, n_scen = 0, n_steps = 0, scen_pad = 0;
+    std::vector<double> q_host;          // [n_tables][n_ages]
+    DevBuf<double> v;                    // [n_nodes][n_steps][scen_pad]
+    DevBuf<double> shock;                // [n_nodes]
+    DevBuf<double> q_stage;              // [n_tables][n_ages_stage]
+    int n_ages_stage = 0;
+    std::vector<double> shock_host;
+
+    // portfolio
+    bool has_pf = false;
+    int n_user = 0, n_pad = 0, n_tiles = 0;
+    int max_age_needed = 0;
+    std::vector<int32_t> h_product, h_age1, h_age2, h_term, h_table1, h_table2, h_timing;
+    std::vector<double> h_amount, h_premium;
+    std::vector<Tile> tiles_host;
+    std::vector<int> slot_of_user;       // user index -> sorted slot
+    DevBuf<int> age1, age2, term, qoff1, qoff2, uidx;
+    DevBuf<double> coef;
+    DevBuf<Tile> tiles;
+    int gen = 0;                          // bumps on every upload
+
+    // run resources
+    DevBuf<int> counters;
+    DevBuf<double> partial;
+    DevBuf<double> totals_tmp;
+    DevBuf<long long> path_off;
+    int path_off_node = -1, path_off_step = -1, path_off_gen = -1;
+    std::map<PlanKey, std::unique_ptr<Plan>> plans;
+    std::map<TuneKey, std::pair<int, int>> tuned;   // -> (K, wg_per_cu)
+
+    // options
+    int opt_k = 0, opt_wg = 0, opt_graph = 1, opt_timing = 0, opt_xcd = 1;
+    int last_k = 0, last_wg = 0;          // configuration of the last recurrence launch
+
+    // timing
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+
+    // graphs
+    std::vector<GraphEntry> graphs;
+
+    // surrogate
+    rr::Surrogate *sur = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Error helpers
+// ---------------------------------------------------------------------------
+static int fail(rr_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e__ = (expr);                                                              \
+        if (e__ != hipSuccess)                                                                \
+            return fail(ctx, e__ == hipErrorOutOfMemory ? RR_ENOMEM : RR_EDEVICE, "%s: %s", #expr, \
+                        hipGetErrorString(e__));                                              \
+    } while (0)
+
+static void set_msg(char *msg, size_t len, const std::string &s)
+{
+    if (msg && len) {
+        size_t n = std::min(len - 1, s.size());
+        memcpy(msg, s.data(), n);
+        msg[n] = 0;
+    }
+}
+
+static bool is_two_life(int product)
+{
+    return product == RR_JL_ANN || product == RR_REV_ANN || product == RR_LS_ANN;
+}
+
+static int kind_of(int product)
+{
+    switch (product) {
+    case RR_JL_ANN: return KIND_JOINT;
+    case RR_REV_ANN: return KIND_REV;
+    case RR_LS_ANN: return KIND_LAST;
+    default: return KIND_SINGLE;
+    }
+}
+
+// VALU operations per scenario-step of each model (for cost estimates).
+static int ops_of_kind(int kind)
+{
+    switch (kind) {
+    case KIND_SINGLE: return 2;
+    case KIND_JOINT: return 2;
+    case KIND_REV: return 5;
+    default: return 8;
+    }
+}
+static int overhead_of_kind(int kind) { return kind == KIND_SINGLE ? 6 : 12; }
+
+// Copy n elements of T from host or device memory to a host vector.
+template <typename T>
+static int fetch(rr_ctx *c, const T *src, size_t n, int mem_kind, std::vector<T> &dst)
+{
+    dst.resize(n);
+    if (n == 0) return RR_OK;
+    if (mem_kind == RR_DEVICE) {
+        HIPCHK(c, hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
+    } else {
+        memcpy(dst.data(), src, n * sizeof(T));
+    }
+    return RR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Validation (host only)
+// ---------------------------------------------------------------------------
+static std::string check_basis_arrays(int n_tables, int n_ages, const double *q, int n_nodes,
+                                      int n_scen, int n_steps, const double *v,
+                                      const double *shock)
+{
+    char b[256];
+    if (n_tables < 1 || n_ages < 2) return "basis: need n_tables >= 1 and n_ages >= 2";
+    if (n_nodes < 1 || n_scen < 1 || n_steps < 1) return "basis: need n_nodes, n_scen, n_steps >= 1";
+    if ((long long)n_nodes * n_steps * (((long long)n_scen + 31) / 32 * 32 + 32) > (1LL << 31))
+        return "basis: curve array exceeds 2^31 values";
+    if (!q || !v) return "basis: q and v must not be NULL";
+    for (long long i = 0; i < (long long)n_tables * n_ages; ++i) {
+        double x = q[i];
+        if (!(x >= 0.0 && x <= 1.0)) {
+            snprintf(b, sizeof b, "basis: q[%lld] = %g is not a probability in [0, 1]", i, x);
+            return b;
+        }
+    }
+    for (long long i = 0; i < (long long)n_nodes * n_scen * n_steps; ++i) {
+        double x = v[i];
+        if (!(x > 0.0) || !std::isfinite(x)) {
+            snprintf(b, sizeof b, "basis: v[%lld] = %g is not a positive finite discount factor", i, x);
+            return b;
+        }
+    }
+    if (shock)
+        for (int i = 0; i < n_nodes; ++i)
+            if (!(shock[i] >= 0.0) || !std::isfinite(shock[i])) {
+                snprintf(b, sizeof b, "basis: shock[%d] = %g must be finite and >= 0", i, shock[i]);
+                return b;
+            }
+    return "";
+}
+
+static std::string check_portfolio_arrays(int n, const int32_t *product, const int32_t *age1,
+                                          const int32_t *age2, const int32_t *term,
+                                          const int32_t *table1, const int32_t *table2,
+                                          const int32_t *timing, const double *amount,
+                                          const double *premium, int n_steps, int n_ages,
+                                          int n_tables)
+{
+    char b[256];
+    if (n < 0) return "portfolio: n must be >= 0";
+    if (n > (1 << 28)) return "portfolio: n too large";
+    if (n > 0 && (!product || !age1 || !term || !table1 || !amount))
+        return "portfolio: product, age1_m, term_m, table1 and amount must not be NULL";
+    for (int i = 0; i < n; ++i) {
+        int pr = product[i];
+        if (pr < RR_SL_ANN || pr > RR_ENDOW_ASSUR) {
+            snprintf(b, sizeof b, "portfolio: policy %d has unknown product %d", i, pr);
+            return b;
+        }
+        if (term[i] < 1 || term[i] > n_steps) {
+            snprintf(b, sizeof b, "portfolio: policy %d term %d outside [1, n_steps=%d]", i, term[i], n_steps);
+            return b;
+        }
+        if (age1[i] < 0 || (long long)age1[i] + term[i] > n_ages - 1) {
+            snprintf(b, sizeof b, "portfolio: policy %d age %d + term %d exceeds the tables (n_ages=%d)",
+                     i, age1[i], term[i], n_ages);
+            return b;
+        }
+        if (table1[i] < 0 || table1[i] >= n_tables) {
+            snprintf(b, sizeof b, "portfolio: policy %d table1 %d outside [0, %d)", i, table1[i], n_tables);
+            return b;
+        }
+        if (is_two_life(pr)) {
+            if (!age2 || !table2) return "portfolio: two-life products need age2_m and table2";
+            if (age2[i] < 0 || (long long)age2[i] + term[i] > n_ages - 1) {
+                snprintf(b, sizeof b, "portfolio: policy %d second age %d + term %d exceeds the tables",
+                         i, age2[i], term[i]);
+                return b;
+            }
+            if (table2[i] < 0 || table2[i] >= n_tables) {
+                snprintf(b, sizeof b, "portfolio: policy %d table2 %d outside [0, %d)", i, table2[i], n_tables);
+                return b;
+            }
+        }
+        if (timing && timing[i] != RR_ADVANCE && timing[i] != RR_ARREARS) {
+            snprintf(b, sizeof b, "portfolio: policy %d timing %d is not 0 or 1", i, timing[i]);
+            return b;
+        }
+        if (!std::isfinite(amount[i]) || amount[i] < 0.0) {
+            snprintf(b, sizeof b, "portfolio: policy %d amount %g must be finite and >= 0", i, amount[i]);
+            return b;
+        }
+        if (premium && (!std::isfinite(premium[i]) || premium[i] < 0.0)) {
+            snprintf(b, sizeof b, "portfolio: policy %d premium %g must be finite and >= 0", i, premium[i]);
+            return b;
+        }
+    }
+    return "";
+}
+
+extern "C" int rr_check_basis(const rr_basis *b, char *msg, size_t msg_len)
+{
+    if (!b) { set_msg(msg, msg_len, "basis is NULL"); return RR_EINVAL; }
+    if (b->mem_kind != RR_HOST) { set_msg(msg, msg_len, "rr_check_basis needs host arrays"); return RR_EINVAL; }
+    std::string s = check_basis_arrays(b->n_tables, b->n_ages, b->q, b->n_nodes, b->n_scen,
+                                       b->n_steps, b->v, b->shock);
+    set_msg(msg, msg_len, s);
+    return s.empty() ? RR_OK : RR_EINVAL;
+}
+
+extern "C" int rr_check_portfolio(const rr_portfolio *p, int32_t n_steps, int32_t n_ages,
+                                  int32_t n_tables, char *msg, size_t msg_len)
+{
+    if (!p) { set_msg(msg, msg_len, "portfolio is NULL"); return RR_EINVAL; }
+    if (p->mem_kind != RR_HOST) { set_msg(msg, msg_len, "rr_check_portfolio needs host arrays"); return RR_EINVAL; }
+    std::string s = check_portfolio_arrays(p->n, p->product, p->age1_m, p->age2_m, p->term_m,
+                                           p->table1, p->table2, p->timing, p->amount,
+                                           p->premium, n_steps, n_ages, n_tables);
+    set_msg(msg, msg_len, s);
+    return s.empty() ? RR_OK : RR_EINVAL;
+}
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+extern "C" int rr_create(rr_ctx **out, int device, uint64_t stream)
+{
+    if (!out) return RR_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return RR_EDEVICE;
+    if (device < 0 || device >= ndev) return RR_EINVAL;
+    std::unique_ptr<rr_ctx> c(new rr_ctx());
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) return RR_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RR_EDEVICE;
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    c->stream = (hipStream_t)(uintptr_t)stream;   // 0 = the null stream
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) return RR_EDEVICE;
+    if (c->counters.alloc(MAX_QUEUES + 1) != hipSuccess) return RR_ENOMEM;
+    if (hipMemset(c->counters.p, 0, sizeof(int) * (MAX_QUEUES + 1)) != hipSuccess) return RR_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return RR_EDEVICE;
+    *out = c.release();
+    return RR_OK;
+}
+
+static void drop_graphs(rr_ctx *c)
+{
+    for (auto &g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
+extern "C" int rr_destroy(rr_ctx *c)
+{
+    if (!c) return RR_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (auto &e : c->ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto &e : c->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    rr::surrogate_destroy(c->sur);
+    c->sur = nullptr;
+    c->plans.clear();
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return RR_OK;
+}
+
+extern "C" const char *rr_last_error(const rr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int rr_set_stream(rr_ctx *c, uint64_t stream)
+{
+    if (!c) return RR_EINVAL;
+    drop_graphs(c);
+    c->stream = (hipStream_t)(uintptr_t)stream;
+    return RR_OK;
+}
+
+extern "C" int rr_sync(rr_ctx *c)
+{
+    if (!c) return RR_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RR_OK;
+}
+
+extern "C" int rr_set_option(rr_ctx *c, int32_t option, int64_t value)
+{
+    if (!c) return RR_EINVAL;
+    switch (option) {
+    case RR_OPT_BLOCK_K:
+        if (value != 0 && !supported_k((int)value)) return fail(c, RR_EINVAL, "K must be 0 (auto) or 1,2,4,8,16,32");
+        c->opt_k = (int)value;
+        return RR_OK;
+    case RR_OPT_WG_PER_CU:
+        if (value < 0 || value > 8) return fail(c, RR_EINVAL, "workgroups per CU must be 0..8");
+        c->opt_wg = (int)value;
+        return RR_OK;
+    case RR_OPT_USE_GRAPH: c->opt_graph = value ? 1 : 0; return RR_OK;
+    case RR_OPT_KERNEL_TIMING: c->opt_timing = value ? 1 : 0; return RR_OK;
+    case RR_OPT_XCD_QUEUES:
+        c->opt_xcd = value ? 1 : 0;
+        return RR_OK;
+    default: return fail(c, RR_EINVAL, "unknown option %d", option);
+    }
+}
+
+extern "C" int rr_get_option(rr_ctx *c, int32_t option, int64_t *value)
+{
+    if (!c || !value) return RR_EINVAL;
+    switch (option) {
+    case RR_OPT_BLOCK_K: *value = c->opt_k; return RR_OK;
+    case RR_OPT_WG_PER_CU: *value = c->opt_wg; return RR_OK;
+    case RR_OPT_USE_GRAPH: *value = c->opt_graph; return RR_OK;
+    case RR_OPT_KERNEL_TIMING: *value = c->opt_timing; return RR_OK;
+    case RR_OPT_XCD_QUEUES: *value = c->opt_xcd; return RR_OK;
+    case RR_OPT_LAST_K: *value = c->last_k; return RR_OK;
+    case RR_OPT_LAST_WG: *value = c->last_wg; return RR_OK;
+    default: return fail(c, RR_EINVAL, "unknown option %d", option);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Uploads
+// ---------------------------------------------------------------------------
+static int stage_tables(rr_ctx *c)
+{
+    // Keep only the ages the portfolio can reach, so the tables fit in LDS.
+    int need = c->has_pf ? c->max_age_needed + 1 : c->n_ages;
+    need = std::max(2, std::min(need, c->n_ages));
+    c->n_ages_stage = need;
+    std::vector<double> st((size_t)c->n_tables * need);
+    for (int t = 0; t < c->n_tables; ++t)
+        memcpy(&st[(size_t)t * need], &c->q_host[(size_t)t * c->n_ages], sizeof(double) * need);
+    HIPCHK(c, c->q_stage.alloc(st.size()));
+    HIPCHK(c, hipMemcpy(c->q_stage.p, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
+    return RR_OK;
+}
+
+extern "C" int rr_basis_upload(rr_ctx *c, const rr_basis *b)
+{
+    if (!c) return RR_EINVAL;
+    if (!b) return fail(c, RR_EINVAL, "basis is NULL");
+    if (b->mem_kind != RR_HOST && b->mem_kind != RR_DEVICE) return fail(c, RR_EINVAL, "bad mem_kind");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (b->n_tables < 1 || b->n_ages < 2 || b->n_nodes < 1 || b->n_scen < 1 || b->n_steps < 1)
+        return fail(c, RR_EINVAL, "basis: sizes must be positive (n_ages >= 2)");
+    std::vector<double> q, v, sh;
+    int rc;
+    size_t nv = (size_t)b->n_nodes * b->n_scen * b->n_steps;
+    if ((rc = fetch(c, b->q, (size_t)b->n_tables * b->n_ages, b->mem_kind, q))) return rc;
+    if ((rc = fetch(c, b->v, nv, b->mem_kind, v))) return rc;
+    if (b->shock && (rc = fetch(c, b->shock, (size_t)b->n_nodes, b->mem_kind, sh))) return rc;
+    std::string s = check_basis_arrays(b->n_tables, b->n_ages, q.data(), b->n_nodes, b->n_scen,
+                                       b->n_steps, v.data(), b->shock ? sh.data() : nullptr);
+    if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
+    if (c->has_pf) {
+        for (int i = 0; i < c->n_user; ++i) {
+            int two = is_two_life(c->h_product[i]);
+            int amax = std::max(c->h_age1[i], two ? c->h_age2[i] : 0) + c->h_term[i];
+            int tmax = std::max(c->h_table1[i], two ? c->h_table2[i] : 0);
+            if (c->h_term[i] > b->n_steps || amax > b->n_ages - 1 || tmax >= b->n_tables) {
+                c->has_pf = false;
+                return fail(c, RR_EINVAL, "basis does not cover loaded policy %d; upload the portfolio again", i);
+            }
+        }
+    }
+    drop_graphs(c);
+    c->plans.clear();
+    c->tuned.clear();
+    c->has_basis = false;
+    c->n_tables = b->n_tables;
+    c->n_ages = b->n_ages;
+    c->n_nodes = b->n_nodes;
+    c->n_scen = b->n_scen;
+    c->n_steps = b->n_steps;
+    c->scen_pad = (b->n_scen + 31) / 32 * 32 + 32;   // a block of up to 32 may overrun the last scenario
+    c->q_host.swap(q);
+    c->shock_host.assign((size_t)b->n_nodes, 1.0);
+    if (b->shock) c->shock_host = sh;
+    // curves: upload as given, transpose to month-major on the device
+    DevBuf<double> tmp;
+    HIPCHK(c, tmp.alloc(nv));
+    HIPCHK(c, hipMemcpy(tmp.p, v.data(), nv * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, c->v.alloc((size_t)b->n_nodes * b->n_steps * c->scen_pad));
+    HIPCHK(c, launch_transpose_curves(tmp.p, c->v.p, b->n_nodes, b->n_scen, b->n_steps, c->scen_pad,
+                                      c->stream));
+    HIPCHK(c, c->shock.alloc((size_t)b->n_nodes));
+    HIPCHK(c, hipMemcpy(c->shock.p, c->shock_host.data(), sizeof(double) * b->n_nodes,
+                        hipMemcpyHostToDevice));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if ((rc = stage_tables(c))) return rc;
+    c->has_basis = true;
+    ++c->gen;
+    return RR_OK;
+}
+
+template <typename T>
+static int upload_vec(rr_ctx *c, DevBuf<T> &d, const std::vector<T> &h)
+{
+    HIPCHK(c, d.alloc(h.size()));
+    if (!h.empty()) HIPCHK(c, hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return RR_OK;
+}
+
+extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
+{
+    if (!c) return RR_EINVAL;
+    if (!p) return fail(c, RR_EINVAL, "portfolio is NULL");
+    if (!c->has_basis) return fail(c, RR_ESTATE, "upload a basis before the portfolio");
+    if (p->mem_kind != RR_HOST && p->mem_kind != RR_DEVICE) return fail(c, RR_EINVAL, "bad mem_kind");
+    if (p->n < 0) return fail(c, RR_EINVAL, "portfolio: n must be >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n = (size_t)p->n;
+    std::vector<int32_t> product, age1, age2, term, table1, table2, timing;
+    std::vector<double> amount, premium;
+    int rc;
+    if (n > 0 && (!p->product || !p->age1_m || !p->term_m || !p->table1 || !p->amount))
+        return fail(c, RR_EINVAL, "portfolio: product, age1_m, term_m, table1 and amount must not be NULL");
+    if ((rc = fetch(c, p->product, n, p->mem_kind, product))) return rc;
+    if ((rc = fetch(c, p->age1_m, n, p->mem_kind, age1))) return rc;
+    if ((rc = fetch(c, p->term_m, n, p->mem_kind, term))) return rc;
+    if ((rc = fetch(c, p->table1, n, p->mem_kind, table1))) return rc;
+    if ((rc = fetch(c, p->amount, n, p->mem_kind, amount))) return rc;
+    if (p->age2_m) { if ((rc = fetch(c, p->age2_m, n, p->mem_kind, age2))) return rc; }
+    else age2.assign(n, 0);
+    if (p->table2) { if ((rc = fetch(c, p->table2, n, p->mem_kind, table2))) return rc; }
+    else table2.assign(n, 0);
+    if (p->timing) { if ((rc = fetch(c, p->timing, n, p->mem_kind, timing))) return rc; }
+    else timing.assign(n, RR_ARREARS);
+    if (p->premium) { if ((rc = fetch(c, p->premium, n, p->mem_kind, premium))) return rc; }
+    else premium.assign(n, 0.0);
+    bool any_two = false;
+    for (size_t i = 0; i < n; ++i) any_two |= is_two_life(product[i]);
+    std::string s = check_portfolio_arrays(p->n, product.data(), age1.data(),
+                                           (p->age2_m || !any_two) ? age2.data() : nullptr,
+                                           term.data(), table1.data(),
+                                           (p->table2 || !any_two) ? table2.data() : nullptr,
+                                           timing.data(), amount.data(), premium.data(),
+                                           c->n_steps, c->n_ages, c->n_tables);
+    if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
+
+    drop_graphs(c);
+    c->plans.clear();
+    c->tuned.clear();
+    c->has_pf = false;
+
+    // Sort: state model, remaining term descending, age (stable on index).
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        int ka = kind_of(product[a]), kb = kind_of(product[b]);
+        if (ka != kb) return ka < kb;
+        if (term[a] != term[b]) return term[a] > term[b];
+        return age1[a] < age1[b];
+    });
+    // Slots: each model's run padded to whole tiles.
+    std::vector<int> s_age1, s_age2, s_term, s_qoff1, s_qoff2, s_uidx;
+    std::vector<Tile> tiles;
+    std::vector<int> slot_user;
+    size_t i0 = 0;
+    int max_age = 1;
+    while (i0 < n) {
+        int kind = kind_of(product[order[i0]]);
+        size_t i1 = i0;
+        while (i1 < n && kind_of(product[order[i1]]) == kind) ++i1;
+        for (size_t a = i0; a < i1; a += TILE) {
+            Tile T;
+            T.kind = kind;
+            T.first = (int)s_uidx.size();
+            T.smax = 0;
+            T.smin = 1 << 30;
+            for (int l = 0; l < TILE; ++l) {
+                size_t j = a + l;
+                if (j < i1) {
+                    int u = order[j];
+                    s_uidx.push_back(u);
+                    s_age1.push_back(age1[u]);
+                    bool two = is_two_life(product[u]);
+                    s_age2.push_back(two ? age2[u] : 0);
+                    s_term.push_back(term[u]);
+                    s_qoff1.push_back(table1[u]);   // scaled below
+                    s_qoff2.push_back(two ? table2[u] : 0);
+                    T.smax = std::max(T.smax, term[u]);
+                    T.smin = std::min(T.smin, term[u]);
+                    max_age = std::max(max_age, age1[u] + term[u]);
+                    if (two) max_age = std::max(max_age, age2[u] + term[u]);
+                } else {
+                    s_uidx.push_back(-1);
+                    s_age1.push_back(0);
+                    s_age2.push_back(0);
+                    s_term.push_back(0);
+                    s_qoff1.push_back(0);
+                    s_qoff2.push_back(0);
+                }
+            }
+            tiles.push_back(T);
+        }
+        i0 = i1;
+    }
+    const int n_pad = (int)s_uidx.size();
+    c->max_age_needed = max_age;
+    c->has_pf = true;          // stage_tables reads max_age_needed
+    if ((rc = stage_tables(c))) { c->has_pf = false; return rc; }
+    for (int j = 0; j < n_pad; ++j) {
+        s_qoff1[j] *= c->n_ages_stage;
+        s_qoff2[j] *= c->n_ages_stage;
+    }
+    // Coefficients.
+    std::vector<double> coef((size_t)N_COEF * std::max(n_pad, 1), 0.0);
+    auto C = [&](int row, int slot) -> double & { return coef[(size_t)row * n_pad + slot]; };
+    for (int j = 0; j < n_pad; ++j) {
+        int u = s_uidx[j];
+        if (u < 0) continue;
+        const int pr = product[u];
+        const double pay = amount[u] / 12.0;
+        const bool adv = timing[u] == RR_ADVANCE;
+        const double P = premium[u];
+        switch (pr) {
+        case RR_SL_ANN:
+        case RR_JL_ANN:
+            C(0, j) = (adv ? pay : 0.0) - P;
+            C(1, j) = adv ? 0.0 : pay;
+            break;
+        case RR_TERM:
+            C(0, j) = -P;
+            C(2, j) = amount[u];
+            break;
+        case RR_ENDOW:
+            C(0, j) = -P;
+            C(3, j) = amount[u];
+            break;
+        case RR_ENDOW_ASSUR:
+            C(0, j) = -P;
+            C(2, j) = amount[u];
+            C(3, j) = amount[u];
+            break;
+        case RR_REV_ANN:
+            C(0, j) = -P;
+            C(4, j) = adv ? pay : 0.0;
+            C(5, j) = adv ? 0.0 : pay;
+            break;
+        case RR_LS_ANN:
+            C(0, j) = (adv ? pay : 0.0) - P;
+            C(1, j) = adv ? 0.0 : pay;
+            C(2, j) = adv ? pay : 0.0;
+            C(3, j) = adv ? 0.0 : pay;
+            C(4, j) = adv ? pay : 0.0;
+            C(5, j) = adv ? 0.0 : pay;
+            break;
+        }
+    }
+    if ((rc = upload_vec(c, c->age1, s_age1))) return rc;
+    if ((rc = upload_vec(c, c->age2, s_age2))) return rc;
+    if ((rc = upload_vec(c, c->term, s_term))) return rc;
+    if ((rc = upload_vec(c, c->qoff1, s_qoff1))) return rc;
+    if ((rc = upload_vec(c, c->qoff2, s_qoff2))) return rc;
+    if ((rc = upload_vec(c, c->uidx, s_uidx))) return rc;
+    if ((rc = upload_vec(c, c->coef, coef))) return rc;
+    if ((rc = upload_vec(c, c->tiles, tiles))) return rc;
+    c->n_user = (int)n;
+    c->n_pad = n_pad;
+    c->n_tiles = (int)tiles.size();
+    c->tiles_host = tiles;
+    c->h_product.swap(product);
+    c->h_age1.swap(age1);
+    c->h_age2.swap(age2);
+    c->h_term.swap(term);
+    c->h_table1.swap(table1);
+    c->h_table2.swap(table2);
+    c->h_timing.swap(timing);
+    c->h_amount.swap(amount);
+    c->h_premium.swap(premium);
+    c->slot_of_user.assign(n, -1);
+    for (int j = 0; j < n_pad; ++j)
+        if (s_uidx[j] >= 0) c->slot_of_user[s_uidx[j]] = j;
+    ++c->gen;
+    return RR_OK;
+}
+
+extern "C" int rr_path_size(rr_ctx *c, int32_t node, int32_t node_step_m, int64_t *n_out)
+{
+    if (!c || !n_out) return RR_EINVAL;
+    if (!c->has_pf) return fail(c, RR_ESTATE, "no portfolio loaded");
+    int64_t s = 0;
+    for (int i = 0; i < c->n_user; ++i) s += std::max(c->h_term[i] - node * node_step_m, 0) + 1;
+    *n_out = s;
+    return RR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Planner: work items and per-XCD queues, longest first
+// ---------------------------------------------------------------------------
+static int build_plan(rr_ctx *c, const rr_run *run, int K, int wg_per_cu, Plan **out)
+{
+    const int queues = c->opt_xcd ? MAX_QUEUES : 1;
+    PlanKey key{run->node_begin, run->node_count, run->scen_begin, run->scen_count,
+                run->node_step_m, K, queues, c->gen};
+    auto it = c->plans.find(key);
+    Plan *pl;
+    if (it == c->plans.end()) {
+        std::unique_ptr<Plan> np(new Plan());
+        const int nsb = (run->scen_count + K - 1) / K;
+        struct W { long long cost; Item item; };
+        std::vector<std::vector<W>> qs(queues);
+        for (int nr = 0; nr < run->node_count; ++nr) {
+            const int shift = (run->node_begin + nr) * run->node_step_m;
+            for (int t = 0; t < c->n_tiles; ++t) {
+                const Tile &T = c->tiles_host[t];
+                const long long steps = std::max(T.smax - shift, 0);
+                const long long cost = steps * (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind)) + 64;
+                for (int b = 0; b < nsb; ++b) {
+                    const int qid = queues > 1 ? (int)(((long long)nr * nsb + b) % queues) : 0;
+                    qs[qid].push_back({cost, Item{nr, t, b * K, 0}});
+                }
+            }
+        }
+        std::vector<Item> items;
+        std::vector<int> qbeg(queues + 1, 0);
+        for (int qi = 0; qi < queues; ++qi) {
+            std::stable_sort(qs[qi].begin(), qs[qi].end(),
+                             [](const W &a, const W &b) { return a.cost > b.cost; });
+            qbeg[qi] = (int)items.size();
+            for (auto &w : qs[qi]) items.push_back(w.item);
+        }
+        qbeg[queues] = (int)items.size();
+        np->K = K;
+        np->n_items = (int)items.size();
+        np->n_queues = queues;
+        int rc;
+        if ((rc = upload_vec(c, np->items, items))) return rc;
+        if ((rc = upload_vec(c, np->qbeg, qbeg))) return rc;
+        pl = np.get();
+        c->plans[key] = std::move(np);
+    } else {
+        pl = it->second.get();
+    }
+    const int waves_per_wg = WG_THREADS / 64;
+    pl->wg_per_cu = wg_per_cu;
+    pl->grid = std::max(1, std::min(c->n_cu * wg_per_cu, (pl->n_items + waves_per_wg - 1) / waves_per_wg));
+    *out = pl;
+    return RR_OK;
+}
+
+static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out, const Plan *pl,
+                             double *partial)
+{
+    RecParams P;
+    memset(&P, 0, sizeof P);
+    P.q = c->q_stage.p;
+    P.n_ages_stage = c->n_ages_stage;
+    P.n_q = c->n_tables * c->n_ages_stage;
+    P.q_in_lds = (P.n_q <= max_lds_tables_doubles() && (size_t)P.n_q * 8 <= c->lds_per_block) ? 1 : 0;
+    P.v = c->v.p;
+    P.n_steps = c->n_steps;
+    P.scen_pad = c->scen_pad;
+    P.shock = c->shock.p;
+    P.age1 = c->age1.p;
+    P.age2 = c->age2.p;
+    P.term = c->term.p;
+    P.qoff1 = c->qoff1.p;
+    P.qoff2 = c->qoff2.p;
+    P.uidx = c->uidx.p;
+    P.coef = c->coef.p;
+    P.n_pad = c->n_pad;
+    P.n_user = c->n_user;
+    P.tiles = c->tiles.p;
+    P.n_tiles = c->n_tiles;
+    P.has_vector = 0;
+    for (const Tile &T : c->tiles_host) P.has_vector |= (T.kind == KIND_REV || T.kind == KIND_LAST);
+    P.items = pl->items.p;
+    P.qbeg = pl->qbeg.p;
+    P.counters = c->counters.p;
+    P.n_queues = pl->n_queues;
+    P.node_begin = run->node_begin;
+    P.scen_begin = run->scen_begin;
+    P.scen_count = run->scen_count;
+    P.node_step = run->node_step_m;
+    const bool want_r0 = (run->out_mask & RR_OUT_R0) != 0;
+    P.r0 = want_r0 ? out->r0 : nullptr;
+    P.r0_states = (run->out_mask & RR_OUT_ALL_STATES) ? 4 : 1;
+    P.partial = partial;
+    P.path = (run->out_mask & RR_OUT_PATH) ? out->path : nullptr;
+    P.path_off = (run->out_mask & RR_OUT_PATH) ? c->path_off.p : nullptr;
+    return P;
+}
+
+static int enqueue_run(rr_ctx *c, const rr_run *run, const rr_outputs *out, Plan *pl,
+                       double *partial, double *totals, hipStream_t s, bool timed)
+{
+    RecParams P = make_params(c, run, out, pl, partial);
+    const size_t lds = P.q_in_lds ? (size_t)P.n_q * sizeof(double) : 0;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (timed) {
+        if (!c->ev_free.empty()) {
+            ev = c->ev_free.back();
+            c->ev_free.pop_back();
+        } else {
+            HIPCHK(c, hipEventCreate(&ev.first));
+            HIPCHK(c, hipEventCreate(&ev.second));
+        }
+        HIPCHK(c, hipEventRecord(ev.first, s));
+    }
+    HIPCHK(c, launch_recurrence(pl->K, P, pl->grid, lds, s));
+    if (timed) {
+        HIPCHK(c, hipEventRecord(ev.second, s));
+        c->ev_pending.push_back(ev);
+    }
+    if (totals) {
+        HIPCHK(c, launch_totals(partial, run->node_count, c->n_tiles, run->scen_count, totals, s));
+    }
+    if ((run->out_mask & RR_OUT_STATS) && out->stats) {
+        double tail = run->tail > 0.0 ? run->tail : 0.005;
+        int rank = (int)std::ceil(tail * run->scen_count - 1e-9);
+        rank = std::max(1, std::min(rank, run->scen_count));
+        HIPCHK(c, launch_stats(totals, run->node_count, run->scen_count, rank, out->stats, s));
+    }
+    return RR_OK;
+}
+
+// Time one configuration (3 launches, min) for the autotuner.
+static int time_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, int K, int wg,
+                       double *partial, double *totals, float *ms)
+{
+    Plan *pl;
+    int rc;
+    if ((rc = build_plan(c, run, K, wg, &pl))) return rc;
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+        HIPCHK(c, hipEventRecord(a, c->stream));
+        if ((rc = enqueue_run(c, run, out, pl, partial, totals, c->stream, false))) return rc;
+        HIPCHK(c, hipEventRecord(b, c->stream));
+        HIPCHK(c, hipEventSynchronize(b));
+        float t = 0;
+        HIPCHK(c, hipEventElapsedTime(&t, a, b));
+        best = std::min(best, t);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = best;
+    return RR_OK;
+}
+
+static int choose_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, double *partial,
+                         double *totals, int *K_out, int *wg_out)
+{
+    const bool path = (run->out_mask & RR_OUT_PATH) != 0;
+    int Kfix = c->opt_k, wgfix = c->opt_wg;
+    if (path) Kfix = 1;
+    if (run->scen_count == 1 && Kfix == 0) Kfix = 1;
+    if (Kfix && wgfix) { *K_out = Kfix; *wg_out = wgfix; return RR_OK; }
+    TuneKey key{run->node_count, run->scen_count, (run->out_mask & RR_OUT_ALL_STATES) ? 4 : 1,
+                path ? 1 : 0, c->gen};
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end() && (!Kfix || it->second.first == Kfix) && (!wgfix || it->second.second == wgfix)) {
+        *K_out = it->second.first;
+        *wg_out = it->second.second;
+        return RR_OK;
+    }
+    std::vector<int> ks;
+    if (Kfix) ks.push_back(Kfix);
+    else for (int k : {4, 8, 16, 32}) if (k <= std::max(4, run->scen_count)) ks.push_back(k);
+    std::vector<int> wgs;
+    if (wgfix) wgs.push_back(wgfix);
+    else wgs = {1, 2, 4};
+    int bestK = ks[0], bestW = wgs.size() > 1 ? 2 : wgs[0];
+    float best = 1e30f;
+    int rc;
+    for (int k : ks) {   // K at the default workgroup count first
+        float ms;
+        if ((rc = time_config(c, run, out, k, bestW, partial, totals, &ms))) return rc;
+        if (ms < best) { best = ms; bestK = k; }
+    }
+    for (int w : wgs) {
+        if (w == bestW && best < 1e29f) continue;
+        float ms;
+        if ((rc = time_config(c, run, out, bestK, w, partial, totals, &ms))) return rc;
+        if (ms < best) { best = ms; bestW = w; }
+    }
+    c->tuned[key] = {bestK, bestW};
+    *K_out = bestK;
+    *wg_out = bestW;
+    return RR_OK;
+}
+
+extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outputs *out)
+{
+    if (!c) return RR_EINVAL;
+    if (!run || !out) return fail(c, RR_EINVAL, "run and outputs must not be NULL");
+    if (!c->has_basis || !c->has_pf) return fail(c, RR_ESTATE, "upload a basis and a portfolio first");
+    HIPCHK(c, hipSetDevice(c->device));
+    const uint32_t mask = run->out_mask;
+    if (mask & ~(RR_OUT_R0 | RR_OUT_TOTALS | RR_OUT_PATH | RR_OUT_ALL_STATES | RR_OUT_STATS))
+        return fail(c, RR_EINVAL, "unknown bits in out_mask");
+    if (run->node_count < 0 || run->scen_count < 0) return fail(c, RR_EINVAL, "negative counts");
+    if (run->node_begin < 0 || run->node_begin + run->node_count > c->n_nodes)
+        return fail(c, RR_EINVAL, "node range [%d, %d) outside the basis (%d nodes)", run->node_begin,
+                    run->node_begin + run->node_count, c->n_nodes);
+    if (run->scen_begin < 0 || run->scen_begin + run->scen_count > c->n_scen)
+        return fail(c, RR_EINVAL, "scenario range [%d, %d) outside the basis (%d scenarios)",
+                    run->scen_begin, run->scen_begin + run->scen_count, c->n_scen);
+    if (run->node_step_m < 0) return fail(c, RR_EINVAL, "node_step_m must be >= 0");
+    if ((long long)(run->node_begin + run->node_count) * run->node_step_m > (1 << 24))
+        return fail(c, RR_EINVAL, "node_step_m too large");
+    if ((mask & RR_OUT_R0) && !out->r0 && c->n_user > 0)   // an empty portfolio has nothing to write
+        return fail(c, RR_EINVAL, "RR_OUT_R0 needs outputs.r0");
+    if ((mask & RR_OUT_TOTALS) && !out->totals) return fail(c, RR_EINVAL, "RR_OUT_TOTALS needs outputs.totals");
+    if ((mask & RR_OUT_STATS) && !out->stats) return fail(c, RR_EINVAL, "RR_OUT_STATS needs outputs.stats");
+    if ((mask & RR_OUT_ALL_STATES) && !(mask & RR_OUT_R0))
+        return fail(c, RR_EINVAL, "RR_OUT_ALL_STATES needs RR_OUT_R0");
+    if (mask & RR_OUT_STATS && !(run->tail >= 0.0 && run->tail < 1.0))
+        return fail(c, RR_EINVAL, "tail must be in [0, 1)");
+    if (mask & RR_OUT_PATH) {
+        if (run->node_count != 1 || run->scen_count != 1)
+            return fail(c, RR_EINVAL, "RR_OUT_PATH needs node_count == 1 and scen_count == 1");
+        if (!out->path) return fail(c, RR_EINVAL, "RR_OUT_PATH needs outputs.path");
+        int64_t need;
+        rr_path_size(c, run->node_begin, run->node_step_m, &need);
+        if (out->path_cap < need)
+            return fail(c, RR_ERANGE, "path_cap %lld < %lld doubles needed", (long long)out->path_cap,
+                        (long long)need);
+        if (c->path_off_node != run->node_begin || c->path_off_step != run->node_step_m ||
+            c->path_off_gen != c->gen) {
+            std::vector<long long> off((size_t)c->n_user + 1, 0);
+            for (int i = 0; i < c->n_user; ++i)
+                off[i + 1] = off[i] + std::max(c->h_term[i] - run->node_begin * run->node_step_m, 0) + 1;
+            int rc = upload_vec(c, c->path_off, off);
+            if (rc) return rc;
+            c->path_off_node = run->node_begin;
+            c->path_off_step = run->node_step_m;
+            c->path_off_gen = c->gen;
+            drop_graphs(c);
+        }
+    }
+    if (run->node_count == 0 || run->scen_count == 0) return RR_OK;
+    const bool need_tot = (mask & (RR_OUT_TOTALS | RR_OUT_STATS)) != 0;
+    double *totals = nullptr;
+    if (need_tot) {
+        if (mask & RR_OUT_TOTALS) totals = out->totals;
+        else {
+            HIPCHK(c, c->totals_tmp.alloc((size_t)run->node_count * run->scen_count));
+            totals = c->totals_tmp.p;
+        }
+    }
+    if (c->n_user == 0) {   // nothing to value: zero totals and statistics
+        if (totals) HIPCHK(c, launch_fill(totals, (long long)run->node_count * run->scen_count, 0.0, c->stream));
+        if ((mask & RR_OUT_STATS)) HIPCHK(c, launch_fill(out->stats, 2LL * run->node_count, 0.0, c->stream));
+        return RR_OK;
+    }
+    double *partial = nullptr;
+    if (need_tot) {
+        size_t np = (size_t)run->node_count * c->n_tiles * run->scen_count;
+        if (np > c->partial.n) drop_graphs(c);
+        HIPCHK(c, c->partial.alloc(np));
+        partial = c->partial.p;
+    }
+    int K, wg, rc;
+    if ((rc = choose_config(c, run, out, partial, totals, &K, &wg))) return rc;
+    Plan *pl;
+    if ((rc = build_plan(c, run, K, wg, &pl))) return rc;
+    c->last_k = K;
+    c->last_wg = wg;
+
+    if (c->opt_graph && !c->opt_timing) {
+        std::vector<uint64_t> key = {
+            (uint64_t)(uintptr_t)pl, (uint64_t)pl->grid, (uint64_t)run->node_begin,
+            (uint64_t)run->node_count, (uint64_t)run->scen_begin, (uint64_t)run->scen_count,
+            (uint64_t)run->node_step_m, (uint64_t)mask, (uint64_t)(uintptr_t)out->r0,
+            (uint64_t)(uintptr_t)out->totals, (uint64_t)(uintptr_t)out->path,
+            (uint64_t)(uintptr_t)out->stats, (uint64_t)(uintptr_t)partial,
+            (uint64_t)(uintptr_t)totals, (uint64_t)c->gen};
+        uint64_t tail_bits;
+        memcpy(&tail_bits, &run->tail, 8);
+        key.push_back(tail_bits);
+        GraphEntry *ge = nullptr;
+        for (auto &g : c->graphs)
+            if (g.key == key) { ge = &g; break; }
+        if (!ge) {
+            if (c->graphs.size() >= 8) drop_graphs(c);
+            GraphEntry g;
+            g.key = key;
+            HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_run(c, run, out, pl, partial, totals, c->cap_stream, false);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+            if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+            HIPCHK(c, e);
+            g.graph = graph;
+            HIPCHK(c, hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+            c->graphs.push_back(g);
+            ge = &c->graphs.back();
+        }
+        HIPCHK(c, hipGraphLaunch(ge->exec, c->stream));
+        return RR_OK;
+    }
+    return enqueue_run(c, run, out, pl, partial, totals, c->stream, c->opt_timing != 0);
+}
+
+extern "C" int rr_kernel_times(rr_ctx *c, double *ms, int32_t cap, int32_t *count)
+{
+    if (!c || !count) return RR_EINVAL;
+    int n = 0;
+    for (auto &e : c->ev_pending) {
+        HIPCHK(c, hipEventSynchronize(e.second));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, e.first, e.second));
+        if (ms && n < cap) ms[n] = t;
+        ++n;
+        c->ev_free.push_back(e);
+    }
+    c->ev_pending.clear();
+    *count = n;
+    return RR_OK;
+}
+
+// Accessors used by the surrogate module (same library).
+namespace rr {
+int ctx_device(rr_ctx *c) { return c->device; }
+hipStream_t ctx_stream(rr_ctx *c) { return c->stream; }
+int ctx_fail(rr_ctx *c, int code, const char *msg) { return fail(c, code, "%s", msg); }
+rr::Surrogate *&ctx_surrogate(rr_ctx *c) { return c->sur; }
+}  // namespace rr

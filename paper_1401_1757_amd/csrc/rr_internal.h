@@ -1,0 +1,103 @@
+// Internal declarations shared by the host side of the library (rr_host.cpp)
+// and its device kernels (rr_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rr {
+
+// State models a tile of 64 policies runs (Sec. 3.6.4: zero-reserve states
+// removed).  Every policy in a tile shares its model.
+enum Kind : int {
+    KIND_SINGLE = 0,   // one life, scalar reserve (annuity, assurance, endowment)
+    KIND_JOINT = 1,    // two lives, joint-life annuity: scalar reserve, p = px * py
+    KIND_REV = 2,      // two lives, states {00, 10} of the 4-state model
+    KIND_LAST = 3,     // two lives, states {00, 01, 10}
+    N_KINDS = 4
+};
+
+constexpr int TILE = 64;          // policies per tile = lanes per wavefront
+constexpr int N_COEF = 6;         // per-policy cash-flow coefficients
+constexpr int MAX_QUEUES = 8;     // one work queue per XCD
+constexpr int WG_THREADS = 256;   // 4 wavefronts per workgroup
+
+// Per-policy coefficients (rows of coef[N_COEF][n_pad]):
+//  KIND_SINGLE / KIND_JOINT:  0: a0 advance amount in state 0 (annuity due - premium)
+//                             1: a1 arrears amount paid if alive at the end of the step
+//                             2: b1 death benefit paid at the end of the step of death
+//                             3: boundary reserve r_S of state 0
+//  KIND_REV / KIND_LAST:      0/1: advance/arrears amount in state 00
+//                             2/3: advance/arrears amount in state 01
+//                             4/5: advance/arrears amount in state 10
+
+struct Tile {
+    int kind;
+    int first;    // first sorted slot (multiple of TILE)
+    int smax;     // largest remaining term at node 0 among valid lanes
+    int smin;     // smallest remaining term at node 0 among valid lanes
+};
+
+struct Item {
+    int node_rel;  // node - node_begin
+    int tile;
+    int sblock;    // first scenario of the block, relative to scen_begin
+    int pad;
+};
+
+struct RecParams {
+    // basis
+    const double *q;          // [n_tables][n_ages_stage]
+    int n_ages_stage;
+    int n_q;                  // n_tables * n_ages_stage
+    int q_in_lds;
+    int has_vector;           // some tile is KIND_REV or KIND_LAST
+    const double *v;          // [n_nodes][n_steps][scen_pad] month-major
+    int n_steps;
+    int scen_pad;
+    const double *shock;      // [n_nodes]: multiplier on q (1.0 when none)
+    // portfolio, sorted and padded to whole tiles
+    const int *age1;          // attained age at node 0 (padding: 0)
+    const int *age2;
+    const int *term;          // remaining term at node 0 (padding: 0)
+    const int *qoff1;         // table1 * n_ages_stage
+    const int *qoff2;
+    const int *uidx;          // upload index, -1 for padding
+    const double *coef;       // [N_COEF][n_pad]
+    int n_pad;
+    int n_user;
+    const Tile *tiles;
+    int n_tiles;
+    // work
+    const Item *items;
+    const int *qbeg;          // [n_queues + 1]
+    int *counters;            // [MAX_QUEUES + 1]: queue heads, then finished-wave count
+    int n_queues;
+    // run
+    int node_begin;
+    int scen_begin;
+    int scen_count;
+    int node_step;
+    // outputs
+    double *r0;               // [node_count][n_user][scen_count][r0_states] or null
+    int r0_states;
+    double *partial;          // [node_count][n_tiles][scen_count] or null
+    double *path;             // or null
+    const long long *path_off;  // [n_user + 1] (path mode)
+};
+
+// Launchers (rr_kernels.hip).  All are asynchronous on `stream`.
+hipError_t launch_recurrence(int K, const RecParams &p, int grid, size_t lds_bytes,
+                             hipStream_t stream);
+hipError_t launch_totals(const double *partial, int node_count, int n_tiles, int scen_count,
+                         double *totals, hipStream_t stream);
+hipError_t launch_stats(const double *totals, int node_count, int scen_count, int rank,
+                        double *stats, hipStream_t stream);
+hipError_t launch_fill(double *dst, long long n, double value, hipStream_t stream);
+hipError_t launch_fill_int(int *dst, int n, int value, hipStream_t stream);
+hipError_t launch_transpose_curves(const double *src, double *dst, int n_nodes, int n_scen,
+                                   int n_steps, int scen_pad, hipStream_t stream);
+int max_lds_tables_doubles();
+bool supported_k(int K);
+
+}  // namespace rr
