@@ -101,6 +101,8 @@ def main():
                     help="only the timed region of the headline workload (for profiling)")
     ap.add_argument("--block-k", type=int, default=0, help="pin scenarios per lane (0 = autotune)")
     ap.add_argument("--wg", type=int, default=0, help="pin workgroups per CU (0 = autotune)")
+    ap.add_argument("--block-j", type=int, default=0, help="pin policies per lane (0 = autotune)")
+    ap.add_argument("--term-bucket", type=int, default=0, help="months per term bucket (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -127,6 +129,8 @@ def main():
     w = synth.config_c3()
     b, pf = w.basis, w.portfolio
     ctx = rr.Context(0)
+    if args.term_bucket:
+        ctx.set_option(rr.OPT_TERM_BUCKET, args.term_bucket)
     t0 = time.perf_counter()
     ctx.basis_upload(b.q, b.v, b.shock)
     ctx.portfolio_upload(pf)
@@ -135,6 +139,7 @@ def main():
     out = ctx.alloc_outputs(1, b.n_scen, stats=True)
     ctx.set_option(rr.OPT_BLOCK_K, args.block_k)
     ctx.set_option(rr.OPT_WG_PER_CU, args.wg)
+    ctx.set_option(rr.OPT_BLOCK_J, args.block_j)
 
     def step():
         ctx.reserve_recurrence(0, 1, 0, b.n_scen, 12, out)
@@ -154,6 +159,7 @@ def main():
     if args.kernel_only:
         print(json.dumps({"ms_per_step": ms_per_step, "value": value,
                           "block_k": ctx.get_option(rr.OPT_LAST_K),
+                          "block_j": ctx.get_option(rr.OPT_LAST_J),
                           "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG)}))
         ctx.close()
         return
@@ -169,6 +175,7 @@ def main():
     issue_frac = ops * b.n_scen / (kernel_ms * 1e-3) / FP64_ISSUE_PEAK
     k_opt = ctx.get_option(rr.OPT_LAST_K)
     wg_opt = ctx.get_option(rr.OPT_LAST_WG)
+    j_opt = ctx.get_option(rr.OPT_LAST_J)
 
     result = {
         "metric": "policy x scenario reserve valuations/s (exact FP64 backward recurrence)",
@@ -198,11 +205,14 @@ def main():
         "ms_per_step_direct_launch": 1e3 * elapsed_direct / args.steps,
         "first_call_s": first_call_s,
         "upload_s": upload_s,
-        "launch": {"block_k": k_opt, "wg_per_cu": wg_opt, "autotuned": args.block_k == 0},
+        "launch": {"block_k": k_opt, "block_j": j_opt, "wg_per_cu": wg_opt,
+                   "autotuned": args.block_k == 0},
     }
 
     if not args.no_secondary:
         sec = {}
+        ctx.close()
+        ctx = rr.Context(0)
         w2 = synth.config_c2()
         ctx.basis_upload(w2.basis.q, w2.basis.v)
         ctx.portfolio_upload(w2.portfolio)
@@ -213,6 +223,8 @@ def main():
         e2 = timed_steps(f2, 20, sync)
         sec["C2_single_scenario"] = {"valuations_per_s": w2.portfolio.n / (e2 / 20),
                                      "ms_per_step": 1e3 * e2 / 20, "policies": w2.portfolio.n}
+        ctx.close()
+        ctx = rr.Context(0)
         w4 = synth.config_c4()
         ctx.basis_upload(w4.basis.q, w4.basis.v, w4.basis.shock)
         ctx.portfolio_upload(w4.portfolio)

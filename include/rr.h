@@ -177,7 +177,9 @@ int rr_check_portfolio(const rr_portfolio *p, int32_t n_steps, int32_t n_ages,
 
 /* Copy the basis into device memory (curves re-laid out month-major so a
  * wavefront reads consecutive scenarios of one month).  Replaces any
- * previous basis; a loaded portfolio is re-checked against it. */
+ * previous basis.  A loaded portfolio that the new basis does not cover
+ * (terms, ages or table indices) is dropped: rr_reserve_recurrence then
+ * returns RR_ESTATE until a portfolio is uploaded again. */
 int rr_basis_upload(rr_ctx *ctx, const rr_basis *b);
 
 /* Copy, check, sort (by state model, remaining term descending, age) and tile
@@ -205,6 +207,10 @@ int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out)
 #define RR_OPT_XCD_QUEUES   5   /* 1 = per-XCD work queues with stealing (default), 0 = one queue */
 #define RR_OPT_LAST_K       6   /* read-only: scenarios per lane of the last launch */
 #define RR_OPT_LAST_WG      7   /* read-only: workgroups per CU of the last launch */
+#define RR_OPT_BLOCK_J      8   /* policies per lane (scalar-reserve models): 0 = autotune, 1, 2, 4 */
+#define RR_OPT_LAST_J       9   /* read-only: policies per lane of the last launch */
+#define RR_OPT_TERM_BUCKET 10   /* months per remaining-term bucket when tiling (default 16);
+                                   applies from the next rr_portfolio_upload */
 int rr_set_option(rr_ctx *ctx, int32_t option, int64_t value);
 int rr_get_option(rr_ctx *ctx, int32_t option, int64_t *value);
 

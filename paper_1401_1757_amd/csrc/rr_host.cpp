@@ -49,6 +49,7 @@ struct DevBuf {
 
 struct Plan {
     int K = 1;
+    int J = 1;
     int wg_per_cu = 2;
     int grid = 1;
     int n_items = 0;
@@ -58,13 +59,17 @@ struct Plan {
 };
 
 struct PlanKey {
-    int node_begin, node_count, scen_begin, scen_count, node_step, K, queues, gen;
+    int node_begin, node_count, scen_begin, scen_count, node_step, K, J, queues, gen;
     bool operator<(const PlanKey &o) const
     {
-        return std::tie(node_begin, node_count, scen_begin, scen_count, node_step, K, queues, gen) <
+        return std::tie(node_begin, node_count, scen_begin, scen_count, node_step, K, J, queues, gen) <
                std::tie(o.node_begin, o.node_count, o.scen_begin, o.scen_count, o.node_step, o.K,
-                        o.queues, o.gen);
+                        o.J, o.queues, o.gen);
     }
+};
+
+struct LaunchCfg {
+    int K = 1, J = 1, wg = 2;
 };
 
 struct TuneKey {
@@ -106,6 +111,7 @@ struct rr_ctx {
     bool has_pf = false;
     int n_user = 0, n_pad = 0, n_tiles = 0;
     int max_age_needed = 0;
+    int head_pad = 0;                     // largest ragged head of an item (steps)
     std::vector<int32_t> h_product, h_age1, h_age2, h_term, h_table1, h_table2, h_timing;
     std::vector<double> h_amount, h_premium;
     std::vector<Tile> tiles_host;
@@ -122,11 +128,12 @@ struct rr_ctx {
     DevBuf<long long> path_off;
     int path_off_node = -1, path_off_step = -1, path_off_gen = -1;
     std::map<PlanKey, std::unique_ptr<Plan>> plans;
-    std::map<TuneKey, std::pair<int, int>> tuned;   // -> (K, wg_per_cu)
+    std::map<TuneKey, LaunchCfg> tuned;
 
     // options
-    int opt_k = 0, opt_wg = 0, opt_graph = 1, opt_timing = 0, opt_xcd = 1;
-    int last_k = 0, last_wg = 0;          // configuration of the last recurrence launch
+    int opt_k = 0, opt_j = 0, opt_wg = 0, opt_graph = 1, opt_timing = 0, opt_xcd = 1;
+    int opt_term_bucket = 16;             // months per remaining-term bucket in the sort
+    int last_k = 0, last_j = 0, last_wg = 0;   // configuration of the last recurrence launch
 
     // timing
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
@@ -409,6 +416,15 @@ extern "C" int rr_set_option(rr_ctx *c, int32_t option, int64_t value)
         if (value < 0 || value > 8) return fail(c, RR_EINVAL, "workgroups per CU must be 0..8");
         c->opt_wg = (int)value;
         return RR_OK;
+    case RR_OPT_TERM_BUCKET:
+        if (value < 1 || value > 1200) return fail(c, RR_EINVAL, "term bucket must be 1..1200 months");
+        c->opt_term_bucket = (int)value;   // applies from the next portfolio upload
+        return RR_OK;
+    case RR_OPT_BLOCK_J:
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return fail(c, RR_EINVAL, "J must be 0 (auto) or 1, 2, 4");
+        c->opt_j = (int)value;
+        return RR_OK;
     case RR_OPT_USE_GRAPH: c->opt_graph = value ? 1 : 0; return RR_OK;
     case RR_OPT_KERNEL_TIMING: c->opt_timing = value ? 1 : 0; return RR_OK;
     case RR_OPT_XCD_QUEUES:
@@ -427,7 +443,10 @@ extern "C" int rr_get_option(rr_ctx *c, int32_t option, int64_t *value)
     case RR_OPT_USE_GRAPH: *value = c->opt_graph; return RR_OK;
     case RR_OPT_KERNEL_TIMING: *value = c->opt_timing; return RR_OK;
     case RR_OPT_XCD_QUEUES: *value = c->opt_xcd; return RR_OK;
+    case RR_OPT_BLOCK_J: *value = c->opt_j; return RR_OK;
+    case RR_OPT_TERM_BUCKET: *value = c->opt_term_bucket; return RR_OK;
     case RR_OPT_LAST_K: *value = c->last_k; return RR_OK;
+    case RR_OPT_LAST_J: *value = c->last_j; return RR_OK;
     case RR_OPT_LAST_WG: *value = c->last_wg; return RR_OK;
     default: return fail(c, RR_EINVAL, "unknown option %d", option);
     }
@@ -438,13 +457,19 @@ extern "C" int rr_get_option(rr_ctx *c, int32_t option, int64_t *value)
 // ---------------------------------------------------------------------------
 static int stage_tables(rr_ctx *c)
 {
-    // Keep only the ages the portfolio can reach, so the tables fit in LDS.
-    int need = c->has_pf ? c->max_age_needed + 1 : c->n_ages;
-    need = std::max(2, std::min(need, c->n_ages));
+    // Keep only the ages the portfolio can reach, so the tables fit in LDS,
+    // plus head_pad entries: a policy that has not started yet (ragged head of
+    // an item) reads up to head_pad ages past its last one; those values are
+    // never used.
+    int used = c->has_pf ? c->max_age_needed + 1 : c->n_ages;
+    used = std::max(2, std::min(used, c->n_ages));
+    const int need = used + (c->has_pf ? c->head_pad : 0);
     c->n_ages_stage = need;
-    std::vector<double> st((size_t)c->n_tables * need);
+    // The kernels read one-step survival probabilities p = 1 - q.
+    std::vector<double> st((size_t)c->n_tables * need, 0.0);
     for (int t = 0; t < c->n_tables; ++t)
-        memcpy(&st[(size_t)t * need], &c->q_host[(size_t)t * c->n_ages], sizeof(double) * need);
+        for (int a = 0; a < used; ++a)
+            st[(size_t)t * need + a] = 1.0 - c->q_host[(size_t)t * c->n_ages + a];
     HIPCHK(c, c->q_stage.alloc(st.size()));
     HIPCHK(c, hipMemcpy(c->q_stage.p, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
     return RR_OK;
@@ -467,17 +492,17 @@ extern "C" int rr_basis_upload(rr_ctx *c, const rr_basis *b)
     std::string s = check_basis_arrays(b->n_tables, b->n_ages, q.data(), b->n_nodes, b->n_scen,
                                        b->n_steps, v.data(), b->shock ? sh.data() : nullptr);
     if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
-    if (c->has_pf) {
-        for (int i = 0; i < c->n_user; ++i) {
+    // A loaded portfolio that the new basis does not cover is dropped.
+    bool keep_pf = c->has_pf;
+    if (keep_pf) {
+        for (int i = 0; i < c->n_user && keep_pf; ++i) {
             int two = is_two_life(c->h_product[i]);
             int amax = std::max(c->h_age1[i], two ? c->h_age2[i] : 0) + c->h_term[i];
             int tmax = std::max(c->h_table1[i], two ? c->h_table2[i] : 0);
-            if (c->h_term[i] > b->n_steps || amax > b->n_ages - 1 || tmax >= b->n_tables) {
-                c->has_pf = false;
-                return fail(c, RR_EINVAL, "basis does not cover loaded policy %d; upload the portfolio again", i);
-            }
+            if (c->h_term[i] > b->n_steps || amax > b->n_ages - 1 || tmax >= b->n_tables) keep_pf = false;
         }
     }
+    c->has_pf = keep_pf;
     drop_graphs(c);
     c->plans.clear();
     c->tuned.clear();
@@ -561,11 +586,19 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     // Sort: state model, remaining term descending, age (stable on index).
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
+    // Within a model, remaining terms are bucketed (width term_bucket months,
+    // longest first) and each bucket is ordered by table and age, so that the
+    // 64 lanes of a tile read neighbouring entries of the mortality table (few
+    // LDS bank conflicts) at the price of at most term_bucket ragged steps.
+    const int tb = std::max(1, c->opt_term_bucket);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         int ka = kind_of(product[a]), kb = kind_of(product[b]);
         if (ka != kb) return ka < kb;
-        if (term[a] != term[b]) return term[a] > term[b];
-        return age1[a] < age1[b];
+        const int ba = (term[a] - 1) / tb, bb = (term[b] - 1) / tb;
+        if (ba != bb) return ba > bb;
+        if (table1[a] != table1[b]) return table1[a] < table1[b];
+        if (age1[a] != age1[b]) return age1[a] < age1[b];
+        return term[a] > term[b];
     });
     // Slots: each model's run padded to whole tiles.
     std::vector<int> s_age1, s_age2, s_term, s_qoff1, s_qoff2, s_uidx;
@@ -613,6 +646,17 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     }
     const int n_pad = (int)s_uidx.size();
     c->max_age_needed = max_age;
+    // Ragged head of the widest item: up to 4 consecutive tiles of one model.
+    int head_pad = 0;
+    for (size_t t0 = 0; t0 < tiles.size(); ++t0) {
+        int smax = 0, smin = 1 << 30;
+        for (size_t t1 = t0; t1 < tiles.size() && t1 < t0 + 4 && tiles[t1].kind == tiles[t0].kind; ++t1) {
+            smax = std::max(smax, tiles[t1].smax);
+            smin = std::min(smin, tiles[t1].smin);
+            head_pad = std::max(head_pad, smax - smin);
+        }
+    }
+    c->head_pad = head_pad;
     c->has_pf = true;          // stage_tables reads max_age_needed
     if ((rc = stage_tables(c))) { c->has_pf = false; return rc; }
     for (int j = 0; j < n_pad; ++j) {
@@ -704,11 +748,12 @@ extern "C" int rr_path_size(rr_ctx *c, int32_t node, int32_t node_step_m, int64_
 // ---------------------------------------------------------------------------
 // Planner: work items and per-XCD queues, longest first
 // ---------------------------------------------------------------------------
-static int build_plan(rr_ctx *c, const rr_run *run, int K, int wg_per_cu, Plan **out)
+static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan **out)
 {
     const int queues = c->opt_xcd ? MAX_QUEUES : 1;
+    const int K = cfg.K, J = cfg.J;
     PlanKey key{run->node_begin, run->node_count, run->scen_begin, run->scen_count,
-                run->node_step_m, K, queues, c->gen};
+                run->node_step_m, K, J, queues, c->gen};
     auto it = c->plans.find(key);
     Plan *pl;
     if (it == c->plans.end()) {
@@ -716,15 +761,29 @@ static int build_plan(rr_ctx *c, const rr_run *run, int K, int wg_per_cu, Plan *
         const int nsb = (run->scen_count + K - 1) / K;
         struct W { long long cost; Item item; };
         std::vector<std::vector<W>> qs(queues);
+        // Items: up to J consecutive tiles of one scalar model (one tile for the
+        // vector models) x a block of K scenarios x a node.
+        std::vector<std::pair<int, int>> groups;   // (first tile, count)
+        for (int t = 0; t < c->n_tiles;) {
+            const int kind = c->tiles_host[t].kind;
+            const int jmax = (kind == KIND_SINGLE || kind == KIND_JOINT) ? J : 1;
+            int count = 1;
+            while (count < jmax && t + count < c->n_tiles && c->tiles_host[t + count].kind == kind) ++count;
+            groups.push_back({t, count});
+            t += count;
+        }
         for (int nr = 0; nr < run->node_count; ++nr) {
             const int shift = (run->node_begin + nr) * run->node_step_m;
-            for (int t = 0; t < c->n_tiles; ++t) {
-                const Tile &T = c->tiles_host[t];
-                const long long steps = std::max(T.smax - shift, 0);
-                const long long cost = steps * (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind)) + 64;
+            for (const auto &g : groups) {
+                const Tile &T = c->tiles_host[g.first];
+                int smax = T.smax;
+                for (int j = 1; j < g.second; ++j) smax = std::max(smax, c->tiles_host[g.first + j].smax);
+                const long long steps = std::max(smax - shift, 0);
+                const long long cost =
+                    steps * g.second * (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind)) + 64;
                 for (int b = 0; b < nsb; ++b) {
                     const int qid = queues > 1 ? (int)(((long long)nr * nsb + b) % queues) : 0;
-                    qs[qid].push_back({cost, Item{nr, t, b * K, 0}});
+                    qs[qid].push_back({cost, Item{nr, g.first, b * K, g.second}});
                 }
             }
         }
@@ -738,6 +797,7 @@ static int build_plan(rr_ctx *c, const rr_run *run, int K, int wg_per_cu, Plan *
         }
         qbeg[queues] = (int)items.size();
         np->K = K;
+        np->J = J;
         np->n_items = (int)items.size();
         np->n_queues = queues;
         int rc;
@@ -749,8 +809,8 @@ static int build_plan(rr_ctx *c, const rr_run *run, int K, int wg_per_cu, Plan *
         pl = it->second.get();
     }
     const int waves_per_wg = WG_THREADS / 64;
-    pl->wg_per_cu = wg_per_cu;
-    pl->grid = std::max(1, std::min(c->n_cu * wg_per_cu, (pl->n_items + waves_per_wg - 1) / waves_per_wg));
+    pl->wg_per_cu = cfg.wg;
+    pl->grid = std::max(1, std::min(c->n_cu * cfg.wg, (pl->n_items + waves_per_wg - 1) / waves_per_wg));
     *out = pl;
     return RR_OK;
 }
@@ -814,7 +874,7 @@ static int enqueue_run(rr_ctx *c, const rr_run *run, const rr_outputs *out, Plan
         }
         HIPCHK(c, hipEventRecord(ev.first, s));
     }
-    HIPCHK(c, launch_recurrence(pl->K, P, pl->grid, lds, s));
+    HIPCHK(c, launch_recurrence(pl->K, pl->J, P, pl->grid, lds, s));
     if (timed) {
         HIPCHK(c, hipEventRecord(ev.second, s));
         c->ev_pending.push_back(ev);
@@ -832,12 +892,12 @@ static int enqueue_run(rr_ctx *c, const rr_run *run, const rr_outputs *out, Plan
 }
 
 // Time one configuration (3 launches, min) for the autotuner.
-static int time_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, int K, int wg,
+static int time_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, const LaunchCfg &cfg,
                        double *partial, double *totals, float *ms)
 {
     Plan *pl;
     int rc;
-    if ((rc = build_plan(c, run, K, wg, &pl))) return rc;
+    if ((rc = build_plan(c, run, cfg, &pl))) return rc;
     hipEvent_t a, b;
     HIPCHK(c, hipEventCreate(&a));
     HIPCHK(c, hipEventCreate(&b));
@@ -857,45 +917,54 @@ static int time_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, int 
     return RR_OK;
 }
 
+// Launch shape: pinned options, else the autotuner's choice for this run shape
+// (every candidate produces bitwise-identical results, so tuning runs write
+// the real outputs).
 static int choose_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, double *partial,
-                         double *totals, int *K_out, int *wg_out)
+                         double *totals, LaunchCfg *cfg_out)
 {
     const bool path = (run->out_mask & RR_OUT_PATH) != 0;
-    int Kfix = c->opt_k, wgfix = c->opt_wg;
-    if (path) Kfix = 1;
-    if (run->scen_count == 1 && Kfix == 0) Kfix = 1;
-    if (Kfix && wgfix) { *K_out = Kfix; *wg_out = wgfix; return RR_OK; }
+    int Kfix = c->opt_k, Jfix = c->opt_j, wgfix = c->opt_wg;
+    if (path || run->scen_count == 1) { Kfix = 1; Jfix = 1; }
+    if (Kfix && Jfix && !supported_kj(Kfix, Jfix)) Jfix = 1;
+    if (Kfix && Jfix && wgfix) { *cfg_out = LaunchCfg{Kfix, Jfix, wgfix}; return RR_OK; }
     TuneKey key{run->node_count, run->scen_count, (run->out_mask & RR_OUT_ALL_STATES) ? 4 : 1,
                 path ? 1 : 0, c->gen};
     auto it = c->tuned.find(key);
-    if (it != c->tuned.end() && (!Kfix || it->second.first == Kfix) && (!wgfix || it->second.second == wgfix)) {
-        *K_out = it->second.first;
-        *wg_out = it->second.second;
+    if (it != c->tuned.end() && (!Kfix || it->second.K == Kfix) && (!Jfix || it->second.J == Jfix) &&
+        (!wgfix || it->second.wg == wgfix)) {
+        *cfg_out = it->second;
         return RR_OK;
     }
-    std::vector<int> ks;
-    if (Kfix) ks.push_back(Kfix);
-    else for (int k : {4, 8, 16, 32}) if (k <= std::max(4, run->scen_count)) ks.push_back(k);
-    std::vector<int> wgs;
-    if (wgfix) wgs.push_back(wgfix);
-    else wgs = {1, 2, 4};
-    int bestK = ks[0], bestW = wgs.size() > 1 ? 2 : wgs[0];
-    float best = 1e30f;
+    static const int kj_list[][2] = {{8, 4}, {16, 4}, {16, 2}, {8, 2}, {4, 4}, {32, 1}, {16, 1}, {8, 1}};
+    std::vector<LaunchCfg> cands;
+    for (auto &kj : kj_list) {
+        if (Kfix && kj[0] != Kfix) continue;
+        if (Jfix && kj[1] != Jfix) continue;
+        if (kj[0] > std::max(4, run->scen_count)) continue;
+        cands.push_back(LaunchCfg{kj[0], kj[1], wgfix ? wgfix : 2});
+    }
+    if (cands.empty()) cands.push_back(LaunchCfg{Kfix ? Kfix : 8, Jfix ? Jfix : 1, wgfix ? wgfix : 2});
+    LaunchCfg best = cands[0];
+    float best_ms = 1e30f;
     int rc;
-    for (int k : ks) {   // K at the default workgroup count first
+    for (const LaunchCfg &cf : cands) {   // scenarios x policies per lane at the default workgroups
+        if (!supported_kj(cf.K, cf.J)) continue;
         float ms;
-        if ((rc = time_config(c, run, out, k, bestW, partial, totals, &ms))) return rc;
-        if (ms < best) { best = ms; bestK = k; }
+        if ((rc = time_config(c, run, out, cf, partial, totals, &ms))) return rc;
+        if (ms < best_ms) { best_ms = ms; best = cf; }
     }
-    for (int w : wgs) {
-        if (w == bestW && best < 1e29f) continue;
-        float ms;
-        if ((rc = time_config(c, run, out, bestK, w, partial, totals, &ms))) return rc;
-        if (ms < best) { best = ms; bestW = w; }
+    if (!wgfix) {
+        for (int w : {1, 3, 4}) {
+            LaunchCfg cf = best;
+            cf.wg = w;
+            float ms;
+            if ((rc = time_config(c, run, out, cf, partial, totals, &ms))) return rc;
+            if (ms < best_ms) { best_ms = ms; best = cf; }
+        }
     }
-    c->tuned[key] = {bestK, bestW};
-    *K_out = bestK;
-    *wg_out = bestW;
+    c->tuned[key] = best;
+    *cfg_out = best;
     return RR_OK;
 }
 
@@ -970,12 +1039,14 @@ extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outp
         HIPCHK(c, c->partial.alloc(np));
         partial = c->partial.p;
     }
-    int K, wg, rc;
-    if ((rc = choose_config(c, run, out, partial, totals, &K, &wg))) return rc;
+    LaunchCfg cfg;
+    int rc;
+    if ((rc = choose_config(c, run, out, partial, totals, &cfg))) return rc;
     Plan *pl;
-    if ((rc = build_plan(c, run, K, wg, &pl))) return rc;
-    c->last_k = K;
-    c->last_wg = wg;
+    if ((rc = build_plan(c, run, cfg, &pl))) return rc;
+    c->last_k = cfg.K;
+    c->last_j = cfg.J;
+    c->last_wg = cfg.wg;
 
     if (c->opt_graph && !c->opt_timing) {
         std::vector<uint64_t> key = {

@@ -40,14 +40,14 @@ struct Tile {
 
 struct Item {
     int node_rel;  // node - node_begin
-    int tile;
+    int tile;      // first tile of the item
     int sblock;    // first scenario of the block, relative to scen_begin
-    int pad;
+    int count;     // consecutive tiles of one model in the item (1..J)
 };
 
 struct RecParams {
     // basis
-    const double *q;          // [n_tables][n_ages_stage]
+    const double *q;          // [n_tables][n_ages_stage] one-step survival p = 1 - q
     int n_ages_stage;
     int n_q;                  // n_tables * n_ages_stage
     int q_in_lds;
@@ -87,7 +87,7 @@ struct RecParams {
 };
 
 // Launchers (rr_kernels.hip).  All are asynchronous on `stream`.
-hipError_t launch_recurrence(int K, const RecParams &p, int grid, size_t lds_bytes,
+hipError_t launch_recurrence(int K, int J, const RecParams &p, int grid, size_t lds_bytes,
                              hipStream_t stream);
 hipError_t launch_totals(const double *partial, int node_count, int n_tiles, int scen_count,
                          double *totals, hipStream_t stream);
@@ -99,5 +99,6 @@ hipError_t launch_transpose_curves(const double *src, double *dst, int n_nodes, 
                                    int n_steps, int scen_pad, hipStream_t stream);
 int max_lds_tables_doubles();
 bool supported_k(int K);
+bool supported_kj(int K, int J);   // (scenarios, policies) per lane
 
 }  // namespace rr

@@ -66,11 +66,13 @@ def run_and_compare(ctx, w, node0=0, nnode=None, scen0=0, nscen=None, K=None, al
     return out, ref
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8, 16, 32])
-def test_all_products_random_small(ctx, K):
-    rng = np.random.default_rng(100 + K)
-    w = synth.random_small(rng, n=150, n_steps=90, n_scen=37, n_nodes=3, shock=True)
-    _say(f"random small K={K}")
+@pytest.mark.parametrize("K,J", [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (32, 1), (4, 2),
+                                 (8, 2), (16, 2), (2, 4), (4, 4), (8, 4)])
+def test_all_products_random_small(ctx, K, J):
+    rng = np.random.default_rng(100 + K + 7 * J)
+    w = synth.random_small(rng, n=450, n_steps=90, n_scen=37, n_nodes=3, shock=True)
+    ctx.set_option(8, J)
+    _say(f"random small K={K} J={J}")
     run_and_compare(ctx, w, K=K)
 
 
@@ -181,13 +183,15 @@ def test_deterministic_and_invariant_to_tuning(ctx):
     ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
     ctx.portfolio_upload(w.portfolio)
     results = []
-    for K, wg, xcd, graph in [(8, 2, 1, 1), (8, 2, 1, 1), (4, 1, 0, 0), (16, 4, 1, 0), (32, 2, 0, 1),
-                              (1, 1, 1, 1), (2, 8, 1, 1)]:
+    for K, J, wg, xcd, graph in [(8, 1, 2, 1, 1), (8, 1, 2, 1, 1), (4, 1, 1, 0, 0), (16, 1, 4, 1, 0),
+                                 (32, 1, 2, 0, 1), (1, 1, 1, 1, 1), (2, 1, 8, 1, 1), (8, 2, 2, 1, 1),
+                                 (16, 2, 3, 1, 0), (4, 4, 2, 0, 1), (8, 4, 1, 1, 1)]:
         ctx.set_option(1, K)
+        ctx.set_option(8, J)
         ctx.set_option(2, wg)
         ctx.set_option(5, xcd)
         ctx.set_option(3, graph)
-        _say(f"tuning K={K} wg={wg} xcd={xcd} graph={graph}")
+        _say(f"tuning K={K} J={J} wg={wg} xcd={xcd} graph={graph}")
         out = ctx.alloc_outputs(2, 100, all_states=True)
         for _ in range(2):
             ctx.reserve_recurrence(0, 2, 0, 100, 12, out)
@@ -262,6 +266,8 @@ def test_invalid_calls_raise(ctx, rr):
     ctx.basis_upload(q, v)
     w = synth.random_small(np.random.default_rng(0), n=10, n_steps=100)
     bad = w.portfolio.subset(np.arange(10))
+    bad.table1[:] = 0
+    bad.table2[:] = 0
     bad.term_m[4] = 101
     with pytest.raises(rr.RRError) as e:
         ctx.portfolio_upload(bad)
@@ -281,3 +287,8 @@ def test_invalid_calls_raise(ctx, rr):
     assert e.value.code == rr.RR_ERANGE
     with pytest.raises(rr.RRError):
         ctx.set_option(1, 3)
+    # a basis that no longer covers the portfolio drops it
+    ctx.basis_upload(q[:, :120], v)
+    with pytest.raises(rr.RRError) as e:
+        ctx.reserve_recurrence(0, 1, 0, 1, 12)
+    assert e.value.code == rr.RR_ESTATE
