@@ -372,3 +372,44 @@ def random_small(rng, n: int, n_steps: int, n_scen: int = 1, n_nodes: int = 1,
                    table1=t1, table2=t2, timing=timing, amount=amount,
                    premium=premium)
     return Workload("random small", Basis(q=q, v=v, shock=sh), pf)
+
+
+# ----------------------------------------------------------------------------
+# Surrogate inputs
+# ----------------------------------------------------------------------------
+def surrogate_training_workload(seed: int = 1005, n: int = 5000, n_nodes: int = 20,
+                                n_scen: int = 100, n_steps: int = 600,
+                                shock_sd: float = 0.05, horizon_y: float = 60.0) -> Workload:
+    """Training inputs for the reserve surrogate: C2-law policies; each node is
+    an independent draw of an inner short rate from the outer Vasicek law at a
+    uniform horizon in [0, horizon_y] years, a mortality shock N(1, shock_sd)
+    and n_scen inner scenarios from that rate.  Nodes share the valuation date
+    (use node_step_m = 0)."""
+    rng = np.random.default_rng(seed)
+    pf = portfolio_mixed(rng, n)
+    q = mortality_tables(max_attained_age(pf) + 1, C2_LOADINGS)
+    T = rng.uniform(0.0, horizon_y, n_nodes)
+    m = VAS_B + (VAS_R0 - VAS_B) * np.exp(-VAS_A * T)
+    sd = VAS_SIGMA * np.sqrt((1.0 - np.exp(-2.0 * VAS_A * T)) / (2.0 * VAS_A))
+    r0 = m + sd * rng.standard_normal(n_nodes)
+    v = np.empty((n_nodes, n_scen, n_steps))
+    for k in range(n_nodes):
+        v[k], _ = vasicek_paths(rng, n_scen, n_steps, r0[k])
+    shock = rng.normal(1.0, shock_sd, n_nodes)
+    return Workload(f"surrogate training: {n:,} C2-law policies x {n_nodes} nodes x {n_scen} scenarios",
+                    Basis(q=q, v=v, shock=shock), pf, node_step_m=0,
+                    note=f"node short rates {np.round(r0[:4], 4)}...")
+
+
+def random_mlp_params(rng, n_feat: int = 17, k_in: int = 32, hidden: int = 256,
+                      bias_sd: float = 0.1) -> dict:
+    """Random surrogate weights: W1 [k_in][hidden] (rows >= n_feat zero),
+    b1, W2 [hidden][hidden], b2, W3 [hidden], b3 (FP32)."""
+    W1 = np.zeros((k_in, hidden), np.float32)
+    W1[:n_feat] = rng.normal(0.0, 1.0 / np.sqrt(n_feat), (n_feat, hidden))
+    return {"W1": W1,
+            "b1": rng.normal(0.0, bias_sd, hidden).astype(np.float32),
+            "W2": rng.normal(0.0, 1.0 / np.sqrt(hidden), (hidden, hidden)).astype(np.float32),
+            "b2": rng.normal(0.0, bias_sd, hidden).astype(np.float32),
+            "W3": rng.normal(0.0, 1.0 / np.sqrt(hidden), hidden).astype(np.float32),
+            "b3": np.float32(rng.normal(0.0, bias_sd))}
