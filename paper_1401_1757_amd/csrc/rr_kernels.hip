@@ -677,12 +677,14 @@ hipError_t launch_totals(const double *partial, int node_count, int n_tiles, int
 // ---------------------------------------------------------------------------
 // Per-node statistics of the scenario totals: mean (fixed-order tree over
 // the scenarios) and the rank-th largest total (the paper's 1-in-200
-// liability: the 5th largest of 1,000 scenarios, Sec. 2.1).  The node's
-// totals are sorted in LDS by a bitonic network (descending); beyond
-// STATS_LDS_MAX scenarios a rank count over global memory is used instead.
+// liability: the 5th largest of 1,000 scenarios, Sec. 2.1).
+//
+// The rank-th largest is found by a most-significant-digit radix select on
+// an order-preserving 64-bit key of each total: eight passes of 8-bit digits,
+// each a 256-bin LDS histogram of the keys that match the digits chosen so
+// far, a suffix scan of the bins and the choice of the bin holding the rank.
+// The answer is the unique rank-th largest value, whatever the order of ties.
 // ---------------------------------------------------------------------------
-constexpr int STATS_LDS_MAX = 8192;
-
 __device__ double block_sum_fixed(double x, double *sh)
 {
     sh[threadIdx.x] = x;
@@ -696,77 +698,80 @@ __device__ double block_sum_fixed(double x, double *sh)
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_stats_sort(const double *__restrict__ totals,
-                                                    int scen_count, int npow2, int rank,
-                                                    double *__restrict__ stats)
+__device__ inline unsigned long long order_key(double x)
 {
-    extern __shared__ double sv[];   // npow2 values
-    __shared__ double red[256];
-    const int node = blockIdx.x;
-    const double *x = totals + (size_t)node * scen_count;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < scen_count; i += 256) acc += x[i];
-    const double total = block_sum_fixed(acc, red);
-    for (int i = threadIdx.x; i < npow2; i += 256) sv[i] = i < scen_count ? x[i] : -INFINITY;
-    __syncthreads();
-    for (int k = 2; k <= npow2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < npow2; i += 256) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const double a = sv[i], b = sv[l];
-                    const bool desc = (i & k) == 0;
-                    if (desc ? (a < b) : (a > b)) {
-                        sv[i] = b;
-                        sv[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    if (threadIdx.x == 0) {
-        stats[2 * node] = total / (double)scen_count;
-        stats[2 * node + 1] = sv[rank - 1];
-    }
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
-__global__ void __launch_bounds__(256) k_stats_count(const double *__restrict__ totals,
-                                                     int scen_count, int rank,
-                                                     double *__restrict__ stats)
+__device__ inline double key_value(unsigned long long k)
+{
+    const unsigned long long u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)u);
+}
+
+__global__ void __launch_bounds__(256) k_stats_select(const double *__restrict__ totals,
+                                                      int scen_count, int rank,
+                                                      double *__restrict__ stats)
 {
     __shared__ double red[256];
+    __shared__ unsigned int hist[256];
+    __shared__ unsigned int scan[256];
+    __shared__ unsigned long long sel_prefix;
+    __shared__ unsigned int sel_rank;
     const int node = blockIdx.x;
+    const int tid = threadIdx.x;
     const double *x = totals + (size_t)node * scen_count;
+
     double acc = 0.0;
-    for (int i = threadIdx.x; i < scen_count; i += 256) acc += x[i];
+    for (int i = tid; i < scen_count; i += 256) acc += x[i];
     const double total = block_sum_fixed(acc, red);
-    if (threadIdx.x == 0) stats[2 * node] = total / (double)scen_count;
-    // Ties are broken by scenario index, so exactly one scenario has each rank.
-    for (int i = threadIdx.x; i < scen_count; i += 256) {
-        const double xi = x[i];
-        int above = 0;
-        for (int j = 0; j < scen_count; ++j) {
-            const double xj = x[j];
-            above += (xj > xi) || (xj == xi && j < i);
-        }
-        if (above == rank - 1) stats[2 * node + 1] = xi;
+    if (tid == 0) {
+        stats[2 * node] = total / (double)scen_count;
+        sel_prefix = 0ull;
+        sel_rank = (unsigned int)rank;
     }
+
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hist[tid] = 0u;
+        __syncthreads();
+        const unsigned long long prefix = sel_prefix;
+        // Keys agree with the prefix on every bit above `shift + 8`.
+        const unsigned long long hi_mask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+        for (int i = tid; i < scen_count; i += 256) {
+            const unsigned long long k = order_key(x[i]);
+            if ((k & hi_mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        // Suffix sums: scan[b] = number of matching keys with digit >= b.
+        scan[tid] = hist[tid];
+        __syncthreads();
+        for (int w = 1; w < 256; w <<= 1) {
+            const unsigned int add = tid + w < 256 ? scan[tid + w] : 0u;
+            __syncthreads();
+            scan[tid] += add;
+            __syncthreads();
+        }
+        const unsigned int r = sel_rank;
+        const unsigned int above = tid < 255 ? scan[tid + 1] : 0u;
+        const unsigned int here = scan[tid];
+        __syncthreads();
+        if (above < r && r <= here) {
+            sel_prefix = prefix | ((unsigned long long)tid << shift);
+            sel_rank = r - above;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) stats[2 * node + 1] = key_value(sel_prefix);
 }
 
 hipError_t launch_stats(const double *totals, int node_count, int scen_count, int rank,
                         double *stats, hipStream_t stream)
 {
     if (node_count <= 0 || scen_count <= 0) return hipSuccess;
-    if (scen_count <= STATS_LDS_MAX) {
-        int npow2 = 1;
-        while (npow2 < scen_count) npow2 <<= 1;
-        hipLaunchKernelGGL(k_stats_sort, dim3(node_count), dim3(256), npow2 * sizeof(double),
-                           stream, totals, scen_count, npow2, rank, stats);
-    } else {
-        hipLaunchKernelGGL(k_stats_count, dim3(node_count), dim3(256), 0, stream, totals,
-                           scen_count, rank, stats);
-    }
+    if (rank < 1 || rank > scen_count) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stats_select, dim3(node_count), dim3(256), 0, stream, totals,
+                       scen_count, rank, stats);
     return hipGetLastError();
 }
 
