@@ -358,9 +358,9 @@ def _min_time(fn, reps=7):
 def test_complexity_linear_vs_quadratic():
     q = gm(1.0)
     b = basis(q, np.full(1200, V_FLAT))
-    S1, S2 = 150, 600
-    pf1 = make_pf([SL_ANN] * 1000, 100, S1)
-    pf2 = make_pf([SL_ANN] * 1000, 100, S2)
+    S1, S2 = 120, 960
+    pf1 = make_pf([SL_ANN] * 2000, 100, S1)
+    pf2 = make_pf([SL_ANN] * 2000, 100, S2)
     t1 = _min_time(lambda: oracle.reserves(b, pf1, want_gross=False, n_threads=1))
     t2 = _min_time(lambda: oracle.reserves(b, pf2, want_gross=False, n_threads=1))
     lin = math.log(t2 / t1) / math.log(S2 / S1)
