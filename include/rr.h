@@ -219,54 +219,139 @@ int rr_get_option(rr_ctx *ctx, int32_t option, int64_t *value);
 int rr_kernel_times(rr_ctx *ctx, double *ms, int32_t cap, int32_t *count);
 
 /* ------------------------------------------------------------------------
- * Learned reserve surrogate (an MLP, not part of the paper's method): it is
- * trained on samples of the exact recurrence above and inferred with an
- * exact FP64 fallback for inputs outside its training box.
+ * Learned reserve surrogate.  Not part of the paper's method: a multilayer
+ * perceptron fitted on the GPU to reserves that rr_reserve_recurrence
+ * computes, inferred with the exact FP64 recurrence as fallback for inputs
+ * outside its training box.
+ *
+ * Features of a row (node k, scenario s, policy i, reserve-vector state j),
+ * raw values in FP64:
+ *    0 age of life 1 in years at the node, (age1_m + k node_step_m) / 12
+ *    1 remaining term in years, (term_m - k node_step_m) / 12
+ *    2..5 one-hot of the product: single-life annuity, joint-life annuity,
+ *         term assurance, pure endowment (other products are outside the
+ *         model's domain)
+ *    6 log amount;  7 annual premium per unit amount, 12 premium / amount
+ *    8 short rate -12 log v[k][s][0]
+ *    9..11 scores of the scenario's zero-rate curve on the model's three
+ *         principal components; zero rates at tenors T = 1..50 years are
+ *         z_T = -(12 / m_T) sum_{t < m_T} log v[k][s][t], m_T = min(12 T, n_steps)
+ *   12 mortality shock of the node (1 without shocks)
+ *   13..15 one-hot of the state j (0, 1, 2)
+ *   16 age of life 2 in years at the node (joint-life annuity; else 0)
+ * Target: reserve of state j / amount.  Features and target are
+ * standardised with the training mean and population standard deviation.
+ * A row is inside the box when every raw feature lies within the training
+ * [min, max] and the policy's tables and annuity timing are those the
+ * training policies of its product had.
+ *
+ * Network: 32 inputs (features, zero-padded) -> 256 -> GELU -> 256 -> GELU
+ * -> 1, GELU in the tanh form (Hendrycks and Gimpel, 2016); weights and
+ * activations bfloat16 (round to nearest even), sums FP32 (MFMA); FP32
+ * master weights updated by Adam (beta 0.9, 0.999, eps 1e-8); loss = mean
+ * squared error of the standardised target.
  * ------------------------------------------------------------------------ */
 
+#define RR_SG_FEATURES 17
+#define RR_SG_INPUTS   32
+#define RR_SG_HIDDEN   256
+#define RR_SG_TENORS   50
+#define RR_SG_FACTORS  3
+/* FP32 parameter vector: W1[32][256] (input, unit), b1[256], W2[256][256]
+ * (unit in, unit out), b2[256], W3[256], b3. */
+#define RR_SG_PARAMS   74497
+
 typedef struct {
-    int32_t n_policies;       /* training policies (uploaded with rr_surrogate_train) */
-    int32_t epochs;
-    int32_t batch;            /* rows per optimiser step, multiple of 256 */
-    float lr;                 /* Adam step size */
-    float lr_final;           /* cosine decay target */
-    uint64_t seed;            /* weight init and shuffling */
+    rr_run run;              /* the samples: every live (node, scenario, policy,
+                                state) of this run of the loaded basis and
+                                portfolio, states 0-2 for joint-life annuities
+                                and 0 otherwise; out_mask and tail are ignored */
+    int32_t epochs;          /* >= 1 */
+    int32_t batch;           /* rows per Adam step, multiple of 64 */
+    float lr;                /* Adam step size at the first step (> 0) */
+    float lr_final;          /* cosine decay to this at the last step (>= 0) */
+    float holdout;           /* fraction of samples held out, in [0, 0.5] */
+    int32_t init;            /* 1: new weights from seed and new standardisation,
+                                curve factors and box from these samples;
+                                0: continue training the loaded model on them */
+    uint64_t seed;           /* weight initialisation and sample order */
 } rr_train_cfg;
 
 typedef struct {
     int64_t n_samples;
-    float final_loss;         /* mean squared error of the normalised target, last epoch */
-    float holdout_rel_rmse;   /* on the last 1/64 of samples (not trained on) */
-    double train_ms;
+    int64_t n_train;         /* a multiple of batch; the rest is the holdout */
+    int64_t n_holdout;
+    int32_t steps;
+    float first_loss;        /* mean loss over the first epoch */
+    float final_loss;        /* mean loss over the last epoch */
+    float holdout_loss;      /* loss on the holdout after training */
+    double holdout_rmse;     /* RMS of (prediction - reserve) / amount on the holdout */
+    double data_ms;          /* exact reserves, features, statistics, dataset */
+    double train_ms;         /* epochs */
 } rr_train_report;
 
 typedef struct {
-    int64_t n_in_range;
-    int64_t n_fallback;
+    int64_t n_in_range;      /* (node, scenario, policy) rows from the network */
+    int64_t n_fallback;      /* live rows from the exact recurrence */
 } rr_infer_report;
 
 /*
- * Train the surrogate on the GPU: the current portfolio and basis are the
- * training set (every policy x scenario of node 0 is a sample, produced by
- * rr_reserve_recurrence's kernels); features, normalisation, range box,
- * yield-curve factors, forward/backward BF16 MFMA kernels and Adam all run on
- * the device.  Replaces any loaded model.
+ * Train on the GPU (synchronous).  Samples come from the exact recurrence
+ * (rr_reserve_recurrence's kernels) on cfg->run; features, the principal
+ * components of the curves (fitted on the host from the device-computed
+ * zero rates), standardisation, the bfloat16 MFMA forward and backward
+ * kernels and Adam run on the device.  RR_ESTATE without a basis and a
+ * portfolio (or, with init = 0, without a model); RR_EINVAL for bad
+ * settings, for fewer samples than one batch, or when the training policies
+ * of one product use several (table, timing) combinations.
  */
 int rr_surrogate_train(rr_ctx *ctx, const rr_train_cfg *cfg, rr_train_report *rep);
 
-/* Model blob (versioned): weights, normalisation, range box, curve factors. */
+/*
+ * Model blob, little-endian: a 96-byte header (char magic[8] = "RRSURR01";
+ * int32 version = 1, features = 17, inputs = 32, hidden = 256, tenors = 50,
+ * factors = 3, params = 74497, adam_step, signature[4][3] = per one-hot
+ * product (table1, table2 or -1, timing or -1; table1 = -1: product not
+ * trained), 2 reserved), then FP64 mean[17], sd[17], lo[17], hi[17],
+ * target_mean, target_sd, curve_mean[50], components[3][50], then FP32
+ * params[74497], adam_m[74497], adam_v[74497].  get_weights writes the
+ * blob to host memory (bytes >= *needed, else RR_ERANGE with *needed set;
+ * host may be NULL to query); set_weights loads one (RR_EINVAL if malformed).
+ */
 int rr_surrogate_get_weights(rr_ctx *ctx, void *host, size_t bytes, size_t *needed);
 int rr_surrogate_set_weights(rr_ctx *ctx, const void *host, size_t bytes);
 
 /*
- * Same outputs as rr_reserve_recurrence (RR_OUT_R0 state 0, RR_OUT_TOTALS,
- * RR_OUT_STATS), with the MLP where every feature of a (policy, scenario) is
- * inside the training box and the exact FP64 recurrence otherwise.
- * RR_ESTATE if no model is loaded.  rep may be NULL; when given, the call
- * waits for the counts.
+ * Same outputs as rr_reserve_recurrence for RR_OUT_R0 (state 0),
+ * RR_OUT_TOTALS and RR_OUT_STATS: rows inside the box from the network
+ * (FP32 prediction, scaled back in FP64), the others from the exact FP64
+ * recurrence; expired policies 0.  Waits for the range flags on the first
+ * call of a run shape.  RR_ESTATE without a model, basis or portfolio.
+ * rep may be NULL.
  */
 int rr_surrogate_infer(rr_ctx *ctx, const rr_run *run, const rr_outputs *out,
                        rr_infer_report *rep);
+
+/*
+ * Layer-level calls on the loaded model (device pointers, asynchronous on
+ * the context's stream):
+ *   forward:   y[n] = network(z[n][32]) for standardised inputs z (FP32,
+ *              rounded to bfloat16 inside);
+ *   gradients: grad[RR_SG_PARAMS] of the mean squared error over the n rows
+ *              against targets t[n]; loss[1] (may be NULL) = that error;
+ *   adam_step: one Adam step of the FP32 master weights with gradient grad;
+ *   features:  raw policy features pol[node_count][n][9] (features 0-7 and
+ *              16), raw scenario features scen[node_count][scen_count][5]
+ *              (features 8-12), policy flags pflag[node_count][n] (1 inside
+ *              the box, 0 outside, 2 expired) and scenario flags
+ *              sflag[node_count][scen_count] (1 inside); any may be NULL.
+ */
+int rr_surrogate_forward(rr_ctx *ctx, const float *z, int64_t n, float *y);
+int rr_surrogate_gradients(rr_ctx *ctx, const float *z, const float *t, int64_t n,
+                           float *grad, float *loss);
+int rr_surrogate_adam_step(rr_ctx *ctx, const float *grad, float lr);
+int rr_surrogate_features(rr_ctx *ctx, const rr_run *run, double *pol, double *scen,
+                          int32_t *pflag, int32_t *sflag);
 
 #ifdef __cplusplus
 }

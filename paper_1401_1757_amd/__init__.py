@@ -29,8 +29,12 @@ EXPORTS = (
     "rr_check_basis", "rr_check_portfolio", "rr_basis_upload", "rr_portfolio_upload",
     "rr_path_size", "rr_reserve_recurrence", "rr_set_option", "rr_get_option",
     "rr_kernel_times", "rr_surrogate_train", "rr_surrogate_get_weights",
-    "rr_surrogate_set_weights", "rr_surrogate_infer",
+    "rr_surrogate_set_weights", "rr_surrogate_infer", "rr_surrogate_forward",
+    "rr_surrogate_gradients", "rr_surrogate_adam_step", "rr_surrogate_features",
 )
+
+# Surrogate dimensions (include/rr.h).
+SG_FEATURES, SG_INPUTS, SG_HIDDEN, SG_TENORS, SG_FACTORS, SG_PARAMS = 17, 32, 256, 50, 3, 74497
 
 
 class RRError(RuntimeError):
@@ -70,18 +74,66 @@ class Outputs(ctypes.Structure):
 
 
 class TrainCfg(ctypes.Structure):
-    _fields_ = [("n_policies", ctypes.c_int32), ("epochs", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
-                ("lr_final", ctypes.c_float), ("seed", ctypes.c_uint64)]
+    _fields_ = [("run", Run), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("lr_final", ctypes.c_float),
+                ("holdout", ctypes.c_float), ("init", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class TrainReport(ctypes.Structure):
-    _fields_ = [("n_samples", ctypes.c_int64), ("final_loss", ctypes.c_float),
-                ("holdout_rel_rmse", ctypes.c_float), ("train_ms", ctypes.c_double)]
+    _fields_ = [("n_samples", ctypes.c_int64), ("n_train", ctypes.c_int64),
+                ("n_holdout", ctypes.c_int64), ("steps", ctypes.c_int32),
+                ("first_loss", ctypes.c_float), ("final_loss", ctypes.c_float),
+                ("holdout_loss", ctypes.c_float), ("holdout_rmse", ctypes.c_double),
+                ("data_ms", ctypes.c_double), ("train_ms", ctypes.c_double)]
 
 
 class InferReport(ctypes.Structure):
     _fields_ = [("n_in_range", ctypes.c_int64), ("n_fallback", ctypes.c_int64)]
+
+
+# Model blob layout (include/rr.h): header, FP64 statistics, FP32 arrays.
+_BLOB_HEADER = np.dtype([("magic", "S8"), ("version", "<i4"), ("n_feat", "<i4"),
+                         ("k_in", "<i4"), ("hidden", "<i4"), ("n_tenors", "<i4"),
+                         ("n_factors", "<i4"), ("n_params", "<i4"), ("adam_step", "<i4"),
+                         ("signature", "<i4", (4, 3)), ("reserved", "<i4", (2,))])
+_BLOB_F64 = [("mu", SG_FEATURES), ("sd", SG_FEATURES), ("lo", SG_FEATURES), ("hi", SG_FEATURES),
+             ("tmu", 1), ("tsd", 1), ("zbar", SG_TENORS), ("evec", SG_FACTORS * SG_TENORS)]
+
+
+def pack_surrogate_blob(params, mu, sd, lo, hi, tmu, tsd, zbar, evec, signature,
+                        adam_m=None, adam_v=None, adam_step=0) -> bytes:
+    """Serialise a model into the blob rr_surrogate_set_weights reads.
+    params: FP32 vector [SG_PARAMS]; evec: [3][50]; signature: [4][3]."""
+    h = np.zeros((), _BLOB_HEADER)
+    h["magic"] = b"RRSURR01"
+    for k, v in (("version", 1), ("n_feat", SG_FEATURES), ("k_in", SG_INPUTS),
+                 ("hidden", SG_HIDDEN), ("n_tenors", SG_TENORS), ("n_factors", SG_FACTORS),
+                 ("n_params", SG_PARAMS), ("adam_step", adam_step)):
+        h[k] = v
+    h["signature"] = np.asarray(signature, np.int32).reshape(4, 3)
+    vals = dict(mu=mu, sd=sd, lo=lo, hi=hi, tmu=tmu, tsd=tsd, zbar=zbar, evec=evec)
+    f64 = np.concatenate([np.asarray(vals[k], np.float64).reshape(-1) for k, _ in _BLOB_F64])
+    zeros = np.zeros(SG_PARAMS, np.float32)
+    f32 = np.concatenate([np.asarray(params, np.float32).reshape(-1),
+                          zeros if adam_m is None else np.asarray(adam_m, np.float32).reshape(-1),
+                          zeros if adam_v is None else np.asarray(adam_v, np.float32).reshape(-1)])
+    return h.tobytes() + f64.astype("<f8").tobytes() + f32.astype("<f4").tobytes()
+
+
+def unpack_surrogate_blob(blob: bytes) -> dict:
+    h = np.frombuffer(blob[:_BLOB_HEADER.itemsize], _BLOB_HEADER)[0]
+    off = _BLOB_HEADER.itemsize
+    out = {"adam_step": int(h["adam_step"]), "signature": np.array(h["signature"])}
+    for k, size in _BLOB_F64:
+        a = np.frombuffer(blob[off:off + 8 * size], "<f8").copy()
+        out[k] = a[0] if size == 1 else a
+        off += 8 * size
+    out["evec"] = out["evec"].reshape(SG_FACTORS, SG_TENORS)
+    for k in ("params", "adam_m", "adam_v"):
+        out[k] = np.frombuffer(blob[off:off + 4 * SG_PARAMS], "<f4").copy()
+        off += 4 * SG_PARAMS
+    return out
 
 
 _lib = None
@@ -117,6 +169,10 @@ def load_library(path: str = LIB_PATH):
         "rr_surrogate_set_weights": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "rr_surrogate_infer": ([vp, ctypes.POINTER(Run), ctypes.POINTER(Outputs),
                                 ctypes.POINTER(InferReport)], ctypes.c_int),
+        "rr_surrogate_forward": ([vp, vp, i64, vp], ctypes.c_int),
+        "rr_surrogate_gradients": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
+        "rr_surrogate_adam_step": ([vp, vp, ctypes.c_float], ctypes.c_int),
+        "rr_surrogate_features": ([vp, ctypes.POINTER(Run), vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -287,16 +343,20 @@ class Context:
         return [buf[i] for i in range(min(n.value, cap))]
 
     # -- surrogate ----------------------------------------------------------
-    def surrogate_train(self, epochs=20, batch=4096, lr=2e-3, lr_final=1e-5, seed=7):
-        cfg = TrainCfg(0, epochs, batch, lr, lr_final, seed)
+    def surrogate_train(self, node_begin=0, node_count=None, scen_begin=0, scen_count=None,
+                        node_step=0, epochs=20, batch=4096, lr=2e-3, lr_final=1e-5,
+                        holdout=0.02, init=True, seed=7):
+        node_count = self.n_nodes - node_begin if node_count is None else node_count
+        scen_count = self.n_scen - scen_begin if scen_count is None else scen_count
+        run = Run(node_begin, node_count, scen_begin, scen_count, node_step, 0, 0.0)
+        cfg = TrainCfg(run, epochs, batch, lr, lr_final, holdout, 1 if init else 0, seed)
         rep = TrainReport()
         self._check(self.lib.rr_surrogate_train(self.h, ctypes.byref(cfg), ctypes.byref(rep)))
-        return {"n_samples": rep.n_samples, "final_loss": rep.final_loss,
-                "holdout_rel_rmse": rep.holdout_rel_rmse, "train_ms": rep.train_ms}
+        return {k: getattr(rep, k) for k, _ in TrainReport._fields_}
 
     def surrogate_get_weights(self) -> bytes:
         need = ctypes.c_size_t()
-        self.lib.rr_surrogate_get_weights(self.h, None, 0, ctypes.byref(need))
+        self._check(self.lib.rr_surrogate_get_weights(self.h, None, 0, ctypes.byref(need)))
         buf = ctypes.create_string_buffer(need.value)
         self._check(self.lib.rr_surrogate_get_weights(self.h, buf, need.value, ctypes.byref(need)))
         return buf.raw
@@ -324,5 +384,40 @@ class Context:
         rep = InferReport()
         self._check(self.lib.rr_surrogate_infer(self.h, ctypes.byref(run), ctypes.byref(o),
                                                 ctypes.byref(rep) if report else None))
-        outputs["report"] = {"n_in_range": rep.n_in_range, "n_fallback": rep.n_fallback}
+        if report:
+            outputs["report"] = {"n_in_range": rep.n_in_range, "n_fallback": rep.n_fallback}
         return outputs
+
+    def surrogate_forward(self, z):
+        """z: device float32 [n][32] standardised inputs -> device float32 [n]."""
+        z = z.contiguous()
+        y = self._torch.empty(z.shape[0], dtype=self._torch.float32, device=z.device)
+        self._check(self.lib.rr_surrogate_forward(self.h, _ptr(z), z.shape[0], _ptr(y)))
+        return y
+
+    def surrogate_gradients(self, z, t):
+        z, t = z.contiguous(), t.contiguous()
+        torch = self._torch
+        g = torch.empty(SG_PARAMS, dtype=torch.float32, device=z.device)
+        loss = torch.empty(1, dtype=torch.float32, device=z.device)
+        self._check(self.lib.rr_surrogate_gradients(self.h, _ptr(z), _ptr(t), z.shape[0],
+                                                     _ptr(g), _ptr(loss)))
+        return g, loss
+
+    def surrogate_adam_step(self, grad, lr):
+        self._check(self.lib.rr_surrogate_adam_step(self.h, _ptr(grad.contiguous()), float(lr)))
+
+    def surrogate_features(self, node_begin=0, node_count=None, scen_begin=0, scen_count=None,
+                           node_step=12):
+        node_count = self.n_nodes - node_begin if node_count is None else node_count
+        scen_count = self.n_scen - scen_begin if scen_count is None else scen_count
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        pol = torch.empty((node_count, self.n, 9), dtype=torch.float64, device=dev)
+        scen = torch.empty((node_count, scen_count, 5), dtype=torch.float64, device=dev)
+        pflag = torch.empty((node_count, self.n), dtype=torch.int32, device=dev)
+        sflag = torch.empty((node_count, scen_count), dtype=torch.int32, device=dev)
+        run = Run(node_begin, node_count, scen_begin, scen_count, node_step, 0, 0.0)
+        self._check(self.lib.rr_surrogate_features(self.h, ctypes.byref(run), _ptr(pol),
+                                                   _ptr(scen), _ptr(pflag), _ptr(sflag)))
+        return {"pol": pol, "scen": scen, "pflag": pflag, "sflag": sflag}
