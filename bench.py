@@ -117,6 +117,65 @@ def cpu_baseline(w, seconds_target=15.0):
                       f"({dt:.1f} s, dense general-form recurrence, {threads} OpenMP threads)"}
 
 
+SURROGATE_TRAIN = dict(seed=1005, n=5000, n_nodes=20, n_scen=100)
+SURROGATE_FIT = dict(epochs=24, batch=8192, lr=2e-3, lr_final=1e-5, holdout=0.01, seed=11)
+MLP_FLOPS_PER_ROW = 2 * (17 * 256 + 256 * 256 + 256)   # algorithmic: 17 inputs, two 256-wide layers, head
+
+
+def surrogate_leg(rr, synth, ctx, w, exact_totals, n_val, exact_ms, steps, sync, profile_only=False):
+    """Train the MLP surrogate on GPU-generated exact samples, then time its
+    inference over the same workload (same outputs as the exact step)."""
+    tw = synth.surrogate_training_workload(**SURROGATE_TRAIN)
+    ctx.basis_upload(tw.basis.q, tw.basis.v, tw.basis.shock)
+    ctx.portfolio_upload(tw.portfolio)
+    t0 = time.perf_counter()
+    rep = ctx.surrogate_train(node_step=0, **SURROGATE_FIT)
+    train_s = time.perf_counter() - t0
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    out = ctx.alloc_outputs(1, b.n_scen, stats=True)
+    ctx.surrogate_infer(0, 1, 0, b.n_scen, 12, out)
+    sync()
+    counts = out.pop("report")
+    step = lambda: ctx.surrogate_infer(0, 1, 0, b.n_scen, 12, out, report=False)
+    for _ in range(3):
+        step()
+    elapsed = timed_steps(step, steps, sync)
+    if profile_only:
+        return {"ms_per_step": 1e3 * elapsed / steps}
+    ctx.set_option(rr.OPT_KERNEL_TIMING, 1)
+    ctx.kernel_times()
+    timed_steps(step, steps, sync)
+    kms = float(np.mean(ctx.kernel_times()))
+    ctx.set_option(rr.OPT_KERNEL_TIMING, 0)
+    sur_totals = out["totals"].cpu().numpy()[0]
+    ms = 1e3 * elapsed / steps
+    flops = MLP_FLOPS_PER_ROW * counts["n_in_range"]
+    k = int(np.ceil(0.005 * b.n_scen))
+    q = lambda x: np.sort(x)[::-1][k - 1]
+    return {
+        "valuations_per_s": n_val / (elapsed / steps),
+        "ms_per_step": ms,
+        "speedup_vs_exact": exact_ms / ms,
+        "dtype": "bf16 (fp32 accumulate), fp64 fallback",
+        "rows_network": counts["n_in_range"], "rows_fallback": counts["n_fallback"],
+        "portfolio_reserve_rel_err": float(abs(sur_totals.mean() - exact_totals.mean()) /
+                                           abs(exact_totals.mean())),
+        "per_scenario_rms_rel_err": float(np.sqrt(np.mean(((sur_totals - exact_totals) / exact_totals) ** 2))),
+        "tail_rel_err": float((q(sur_totals) - q(exact_totals)) / q(exact_totals)),
+        "error_reference": "exact FP64 GPU recurrence of the same step",
+        "roofline": {"bound": "mfma", "kernel": "k_infer", "kernel_ms": kms,
+                     "achieved": flops / (kms * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flops / (kms * 1e-3) / 2.5e15,
+                     "algorithmic_flops_per_launch": float(flops)},
+        "train": {"workload": tw.name, "samples": rep["n_samples"], "steps": rep["steps"],
+                  "seconds": train_s, "data_ms": rep["data_ms"], "train_ms": rep["train_ms"],
+                  "first_loss": rep["first_loss"], "final_loss": rep["final_loss"],
+                  "holdout_loss": rep["holdout_loss"]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +183,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="skip the C2 / C4 variants")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the surrogate")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only the surrogate's timed inference region (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (traffic counter calibration)")
     ap.add_argument("--kernel-only", action="store_true",
@@ -185,6 +247,14 @@ def main():
     flops, ops, live, vsteps = scenario_step_work(pf)
     n_val = live * b.n_scen
     value = n_val / (elapsed / args.steps)
+    if args.surrogate_only:
+        ctx.close()
+        ctx = rr.Context(0)
+        r = surrogate_leg(rr, synth, ctx, w, None, n_val, ms_per_step, args.steps, sync,
+                          profile_only=True)
+        print(json.dumps(r))
+        ctx.close()
+        return
     if args.kernel_only:
         print(json.dumps({"ms_per_step": ms_per_step, "value": value,
                           "block_k": ctx.get_option(rr.OPT_LAST_K),
@@ -239,6 +309,13 @@ def main():
         "launch": {"block_k": k_opt, "block_j": j_opt, "wg_per_cu": wg_opt,
                    "autotuned": args.block_k == 0},
     }
+
+    exact_totals = out["totals"].cpu().numpy()[0]
+    if not args.no_surrogate:
+        ctx.close()
+        ctx = rr.Context(0)
+        result["surrogate"] = surrogate_leg(rr, synth, ctx, w, exact_totals, n_val, ms_per_step,
+                                            args.steps, sync)
 
     if not args.no_secondary:
         sec = {}

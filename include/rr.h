@@ -203,7 +203,8 @@ int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out)
 #define RR_OPT_BLOCK_K      1   /* scenarios per lane: 0 = autotune, or 1,2,4,8,16,32 */
 #define RR_OPT_WG_PER_CU    2   /* persistent workgroups per CU: 0 = autotune, 1..8 */
 #define RR_OPT_USE_GRAPH    3   /* 1 = replay captured hipGraphs (default), 0 = direct launches */
-#define RR_OPT_KERNEL_TIMING 4  /* 1 = record HIP events around each recurrence kernel */
+#define RR_OPT_KERNEL_TIMING 4  /* 1 = record HIP events around each recurrence kernel
+                                   (and each fused surrogate inference kernel) */
 #define RR_OPT_XCD_QUEUES   5   /* 1 = per-XCD work queues with stealing (default), 0 = one queue */
 #define RR_OPT_LAST_K       6   /* read-only: scenarios per lane of the last launch */
 #define RR_OPT_LAST_WG      7   /* read-only: workgroups per CU of the last launch */
@@ -239,8 +240,9 @@ int rr_kernel_times(rr_ctx *ctx, double *ms, int32_t cap, int32_t *count);
  *   12 mortality shock of the node (1 without shocks)
  *   13..15 one-hot of the state j (0, 1, 2)
  *   16 age of life 2 in years at the node (joint-life annuity; else 0)
- * Target: reserve of state j / amount.  Features and target are
- * standardised with the training mean and population standard deviation.
+ * Target: reserve of state j / amount.  Features are standardised with the
+ * training mean and population standard deviation, the target with those of
+ * the training rows of the same product.
  * A row is inside the box when every raw feature lies within the training
  * [min, max] and the policy's tables and annuity timing are those the
  * training policies of its product had.
@@ -284,8 +286,10 @@ typedef struct {
     int32_t steps;
     float first_loss;        /* mean loss over the first epoch */
     float final_loss;        /* mean loss over the last epoch */
-    float holdout_loss;      /* loss on the holdout after training */
-    double holdout_rmse;     /* RMS of (prediction - reserve) / amount on the holdout */
+    float holdout_loss;      /* loss on the holdout after the epochs */
+    float calibration[4];    /* per one-hot product: mean residual of the trained
+                                network over the training rows (standardised
+                                units), added to the product's target mean */
     double data_ms;          /* exact reserves, features, statistics, dataset */
     double train_ms;         /* epochs */
 } rr_train_report;
@@ -300,7 +304,9 @@ typedef struct {
  * (rr_reserve_recurrence's kernels) on cfg->run; features, the principal
  * components of the curves (fitted on the host from the device-computed
  * zero rates), standardisation, the bfloat16 MFMA forward and backward
- * kernels and Adam run on the device.  RR_ESTATE without a basis and a
+ * kernels and Adam run on the device.  After the epochs each product's
+ * target mean is shifted by the network's mean residual over that product's
+ * training rows (an output calibration; see rr_train_report.calibration).  RR_ESTATE without a basis and a
  * portfolio (or, with init = 0, without a model); RR_EINVAL for bad
  * settings, for fewer samples than one batch, or when the training policies
  * of one product use several (table, timing) combinations.
@@ -313,7 +319,8 @@ int rr_surrogate_train(rr_ctx *ctx, const rr_train_cfg *cfg, rr_train_report *re
  * factors = 3, params = 74497, adam_step, signature[4][3] = per one-hot
  * product (table1, table2 or -1, timing or -1; table1 = -1: product not
  * trained), 2 reserved), then FP64 mean[17], sd[17], lo[17], hi[17],
- * target_mean, target_sd, curve_mean[50], components[3][50], then FP32
+ * target_mean[4], target_sd[4] (per one-hot product), curve_mean[50],
+ * components[3][50], then FP32
  * params[74497], adam_m[74497], adam_v[74497].  get_weights writes the
  * blob to host memory (bytes >= *needed, else RR_ERANGE with *needed set;
  * host may be NULL to query); set_weights loads one (RR_EINVAL if malformed).

@@ -30,10 +30,11 @@ Definitions (the same ones the GPU library documents):
   the eigenvectors of the population covariance of the training curves for
   the three largest eigenvalues, each signed so that its component of
   largest magnitude is positive.
-* Target: reserve of state j divided by the amount; features and target are
+* Target: reserve of state j divided by the amount.  Features are
   standardised with the training mean and population standard deviation
-  (1 where that is 0); a row is in range when every raw feature lies in the
-  training [min, max] box.
+  (1 where that is 0), the target with the mean and population standard
+  deviation of the training rows of the same product; a row is in range
+  when every raw feature lies in the training [min, max] box.
 * Network: z (17 features, zero-padded to 32) -> 256 -> GELU -> 256 -> GELU
   -> 1, GELU in the tanh form of Hendrycks and Gimpel (2016); loss = mean
   squared error of the standardised target.
@@ -227,10 +228,24 @@ def normalisation(X, t):
     mu = X.mean(axis=0)
     sd = np.sqrt(((X - mu) ** 2).mean(axis=0))
     sd = np.where(sd > 0, sd, 1.0)
-    tmu = t.mean()
-    tsd = np.sqrt(((t - tmu) ** 2).mean())
-    tsd = tsd if tsd > 0 else 1.0
+    tmu, tsd = np.zeros(4), np.ones(4)
+    for j in range(4):
+        sel = X[:, F_PROD + j] == 1.0
+        if sel.any():
+            tmu[j] = t[sel].mean()
+            s = np.sqrt(((t[sel] - tmu[j]) ** 2).mean())
+            tsd[j] = s if s > 0 else 1.0
     return mu, sd, X.min(axis=0), X.max(axis=0), tmu, tsd
+
+
+def product_index(X):
+    """One-hot product slot (0..3) of each row."""
+    return np.argmax(np.asarray(X)[:, F_PROD:F_PROD + 4], axis=1)
+
+
+def standardise_target(X, t, tmu, tsd):
+    j = product_index(X)
+    return f32((np.asarray(t, np.float64) - tmu[j]) / tsd[j])
 
 
 def standardise(X, mu, sd):
@@ -339,4 +354,5 @@ N_PARAMS = sum(int(np.prod(s)) if s else 1 for _, s in PARAM_SHAPES)
 def predict_reserves(p, X, amount, mu, sd, tmu, tsd):
     """Reserve predictions in FP64 from raw features X (bfloat16 mode)."""
     y, _ = forward(p, standardise(X, mu, sd), quant=True)
-    return amount * (np.asarray(y, np.float64) * tsd + tmu)
+    j = product_index(X)
+    return amount * (np.asarray(y, np.float64) * tsd[j] + tmu[j])

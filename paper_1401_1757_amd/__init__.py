@@ -84,7 +84,7 @@ class TrainReport(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int64), ("n_train", ctypes.c_int64),
                 ("n_holdout", ctypes.c_int64), ("steps", ctypes.c_int32),
                 ("first_loss", ctypes.c_float), ("final_loss", ctypes.c_float),
-                ("holdout_loss", ctypes.c_float), ("holdout_rmse", ctypes.c_double),
+                ("holdout_loss", ctypes.c_float), ("calibration", ctypes.c_float * 4),
                 ("data_ms", ctypes.c_double), ("train_ms", ctypes.c_double)]
 
 
@@ -98,7 +98,7 @@ _BLOB_HEADER = np.dtype([("magic", "S8"), ("version", "<i4"), ("n_feat", "<i4"),
                          ("n_factors", "<i4"), ("n_params", "<i4"), ("adam_step", "<i4"),
                          ("signature", "<i4", (4, 3)), ("reserved", "<i4", (2,))])
 _BLOB_F64 = [("mu", SG_FEATURES), ("sd", SG_FEATURES), ("lo", SG_FEATURES), ("hi", SG_FEATURES),
-             ("tmu", 1), ("tsd", 1), ("zbar", SG_TENORS), ("evec", SG_FACTORS * SG_TENORS)]
+             ("tmu", 4), ("tsd", 4), ("zbar", SG_TENORS), ("evec", SG_FACTORS * SG_TENORS)]
 
 
 def pack_surrogate_blob(params, mu, sd, lo, hi, tmu, tsd, zbar, evec, signature,
@@ -352,7 +352,9 @@ class Context:
         cfg = TrainCfg(run, epochs, batch, lr, lr_final, holdout, 1 if init else 0, seed)
         rep = TrainReport()
         self._check(self.lib.rr_surrogate_train(self.h, ctypes.byref(cfg), ctypes.byref(rep)))
-        return {k: getattr(rep, k) for k, _ in TrainReport._fields_}
+        out = {k: getattr(rep, k) for k, _ in TrainReport._fields_}
+        out["calibration"] = list(rep.calibration)
+        return out
 
     def surrogate_get_weights(self) -> bytes:
         need = ctypes.c_size_t()

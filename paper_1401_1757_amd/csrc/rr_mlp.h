@@ -102,6 +102,8 @@ struct Norm {
     const double *zbar;      // [N_TENORS]
     const double *evec;      // [N_FACTORS][N_TENORS]
     const int *signature;    // [4][3] table1, table2 (-1), timing (-1); table1 -1 = absent
+    const double *tmu;       // [4] target mean per one-hot product
+    const double *tsd;       // [4] target standard deviation per one-hot product
 };
 
 // Per (node, scenario): sums of log v over the 12 months of each tenor year,
@@ -127,10 +129,12 @@ struct Policies {
 };
 // Per (node, policy): raw features [node][n][9] (features 0-7 and 16),
 // standardised bfloat16 features 0-7 [node][n][8] and 16 [node][n],
-// state flag [node][n] (1 in the box, 0 outside, 2 expired).
+// state flag [node][n] (1 in the box, 0 outside, 2 expired) and the output
+// map r = y * scale + offset (amount x target sd / mean of the product).
 hipError_t launch_policy_features(const Policies &p, int node_begin, int node_count,
                                   int node_step, const Norm &nm, double *raw, bf16_t *feat,
-                                  bf16_t *feat2, int *flag, hipStream_t s);
+                                  bf16_t *feat2, int *flag, double *scale, double *offset,
+                                  hipStream_t s);
 
 // ---- fused inference -------------------------------------------------------
 struct Infer {
@@ -141,8 +145,8 @@ struct Infer {
     const int *pflag;        // [node][n]
     const bf16_t *sfeat;     // [node][scen][8]
     const int *sok;          // [node][scen]
-    const double *amount;    // [n]
-    double tmu, tsd;
+    const double *scale;     // [node][n] reserve = y * scale + offset
+    const double *offset;    // [node][n]
     double *r0;              // [node][n][scen] predictions written here, or null
     const double *exact;     // [node][n][scen] fallback values for rows outside the box
     double *partial;         // [node][n_chunks][scen]
@@ -160,14 +164,21 @@ hipError_t launch_samples(const double *praw, const double *sraw, const double *
                           const double *amount, const int2 *pairs, const long long *pair_off,
                           const long long *row_off, int node_count, int n, int scen_count,
                           long long n_rows, double *X, double *T, hipStream_t s);
-// Column mean, population sd, min and max of X[N][N_FEAT] and T (18 columns)
-// in a fixed order: out[18][4].
+// Column statistics in a fixed order, out[STAT_COLS][4] = mean, population
+// sd, min, max: columns 0-16 the features, 17 the target, 18-21 the target
+// over the rows of each one-hot product (count 0: mean 0, sd 0).
+constexpr int STAT_COLS = N_FEAT + 1 + 4;
+constexpr int STAT_BLOCKS = 256;
 hipError_t launch_colstats(const double *X, const double *T, long long n, double *work,
                            double *out, hipStream_t s);
-// Standardised bfloat16 rows at permuted positions and FP32 targets.
+// Standardised bfloat16 rows at permuted positions and FP32 targets
+// (standardised with the statistics of the row's product).
 hipError_t launch_build(const double *X, const double *T, long long n, const int *perm,
-                        const double *mu, const double *sd, double tmu, double tsd,
-                        bf16_t *xq, float *tq, hipStream_t s);
+                        const double *mu, const double *sd, const double *tmu, const double *tsd,
+                        bf16_t *xq, float *tq, unsigned char *prod, hipStream_t s);
+// Sums of t - y and row counts per one-hot product: out[0..3], out[4..7].
+hipError_t launch_residuals(const float *y, const float *t, const unsigned char *prod, int n,
+                            double *out, hipStream_t s);
 
 }  // namespace mlp
 }  // namespace rr

@@ -582,7 +582,8 @@ __constant__ int kSurrogateProducts[4] = {0, 1, 4, 5};
 
 __global__ void k_policy_features(Policies p, int node_begin, int node_count, int node_step, Norm nm,
                                   double *__restrict__ raw, bf16_t *__restrict__ feat,
-                                  bf16_t *__restrict__ feat2, int *__restrict__ flag)
+                                  bf16_t *__restrict__ feat2, int *__restrict__ flag,
+                                  double *__restrict__ oscale, double *__restrict__ ooffset)
 {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long long)node_count * p.n) return;
@@ -625,16 +626,20 @@ __global__ void k_policy_features(Policies p, int node_begin, int node_count, in
     *reinterpret_cast<u32x4 *>(feat + id * 8) = pk;
     feat2[id] = std_bf16(x[8], nm.mu[16], nm.sd[16]);
     flag[id] = expired ? 2 : (good ? 1 : 0);
+    const int j = slot >= 0 ? slot : 0;
+    oscale[id] = p.amount[i] * nm.tsd[j];
+    ooffset[id] = p.amount[i] * nm.tmu[j];
 }
 
 hipError_t launch_policy_features(const Policies &p, int node_begin, int node_count,
                                   int node_step, const Norm &nm, double *raw, bf16_t *feat,
-                                  bf16_t *feat2, int *flag, hipStream_t s)
+                                  bf16_t *feat2, int *flag, double *scale, double *offset,
+                                  hipStream_t s)
 {
     const long long n = (long long)node_count * p.n;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_policy_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p,
-                       node_begin, node_count, node_step, nm, raw, feat, feat2, flag);
+                       node_begin, node_count, node_step, nm, raw, feat, feat2, flag, scale, offset);
     return hipGetLastError();
 }
 
@@ -798,13 +803,13 @@ __global__ void __launch_bounds__(INFER_THREADS, 1) k_infer(Infer f, Weights w)
                 for (int g = 0; g < NG; ++g) yacc[g] = mfma(w3, pack8(gelu4(za[g]), gelu4(zb[g])), yacc[g]);
             }
             if (lane < 16) {
-                const double amt = f.amount[p];
+                const double sc = f.scale[pi], of = f.offset[pi];
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     const long long o = orow + 16 * g;
                     if (sok[g] == 2) {
                         const double y = (double)(yacc[g][0] + b3);
-                        const double r = amt * (y * f.tsd + f.tmu);
+                        const double r = y * sc + of;
                         if (f.r0) f.r0[o] = r;
                         tot[g] += r;
                     } else if (sok[g] == 1) {
@@ -904,73 +909,85 @@ hipError_t launch_samples(const double *praw, const double *sraw, const double *
     return hipGetLastError();
 }
 
-constexpr int N_COLS = N_FEAT + 1;
-constexpr int STAT_BLOCKS = 256;
-
-__device__ __forceinline__ double col_value(const double *X, const double *T, long long r, int c)
+// Value and weight of row r in statistics column c.
+__device__ __forceinline__ void col_value(const double *X, const double *T, long long r, int c,
+                                          double &x, double &w)
 {
-    return c < N_FEAT ? X[r * N_FEAT + c] : T[r];
+    if (c < N_FEAT) {
+        x = X[r * N_FEAT + c];
+        w = 1.0;
+    } else {
+        x = T[r];
+        w = c == N_FEAT ? 1.0 : X[r * N_FEAT + 2 + (c - N_FEAT - 1)];
+    }
 }
 
-// mode 0: per-block sum, min, max of each column; mode 1: per-block sum of
-// squared deviations from mean[c].  work[block][N_COLS][3].
+// mode 0: per block, weighted sum, weight, min and max of each column;
+// mode 1: weighted sum of squared deviations from the column mean.
+// work[block][STAT_COLS][4].
 __global__ void __launch_bounds__(256) k_colstats(const double *__restrict__ X,
                                                   const double *__restrict__ T, long long n,
-                                                  int mode, const double *__restrict__ mean,
+                                                  int mode, const double *__restrict__ stats,
                                                   double *__restrict__ work)
 {
     __shared__ double red[256];
-    for (int c = 0; c < N_COLS; ++c) {
-        double a = 0.0, lo = 1.0e300, hi = -1.0e300;
-        const double mu = mode ? mean[4 * c] : 0.0;
+    for (int c = 0; c < STAT_COLS; ++c) {
+        double a = 0.0, cnt = 0.0, lo = 1.0e300, hi = -1.0e300;
+        const double mu = mode ? stats[4 * c] : 0.0;
         for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < n; r += 256LL * STAT_BLOCKS) {
-            const double x = col_value(X, T, r, c);
+            double x, w;
+            col_value(X, T, r, c, x, w);
+            if (w == 0.0) continue;
             if (mode) {
                 a += (x - mu) * (x - mu);
             } else {
                 a += x;
+                cnt += 1.0;
                 lo = fmin(lo, x);
                 hi = fmax(hi, x);
             }
         }
-        for (int stat = 0; stat < (mode ? 1 : 3); ++stat) {
-            red[threadIdx.x] = stat == 0 ? a : (stat == 1 ? lo : hi);
+        for (int st = 0; st < (mode ? 1 : 4); ++st) {
+            red[threadIdx.x] = st == 0 ? a : (st == 1 ? cnt : (st == 2 ? lo : hi));
             __syncthreads();
             for (int w = 128; w > 0; w >>= 1) {
                 if ((int)threadIdx.x < w) {
                     const double o = red[threadIdx.x + w];
-                    red[threadIdx.x] = stat == 0 ? red[threadIdx.x] + o
-                                                 : (stat == 1 ? fmin(red[threadIdx.x], o) : fmax(red[threadIdx.x], o));
+                    const double m = red[threadIdx.x];
+                    red[threadIdx.x] = st < 2 ? m + o : (st == 2 ? fmin(m, o) : fmax(m, o));
                 }
                 __syncthreads();
             }
-            if (threadIdx.x == 0) work[((long long)blockIdx.x * N_COLS + c) * 3 + stat] = red[0];
+            if (threadIdx.x == 0) work[((long long)blockIdx.x * STAT_COLS + c) * 4 + st] = red[0];
             __syncthreads();
         }
     }
 }
 
-// out[c][0..3] = mean, population sd, min, max (mode 0 fills mean, min, max;
-// mode 1 the sd).
-__global__ void k_colstats_final(const double *__restrict__ work, long long n, int mode,
-                                 double *__restrict__ out)
+// out[c][0..3] = mean, population sd, min, max (mode 0: mean, min, max;
+// mode 1: sd).  Weight sums are kept in out[c][1] between the passes.
+__global__ void k_colstats_final(const double *__restrict__ work, int mode, double *__restrict__ out)
 {
     const int c = threadIdx.x;
-    if (c >= N_COLS) return;
+    if (c >= STAT_COLS) return;
     if (mode == 0) {
-        double a = 0.0, lo = 1.0e300, hi = -1.0e300;
+        double a = 0.0, cnt = 0.0, lo = 1.0e300, hi = -1.0e300;
         for (int b = 0; b < STAT_BLOCKS; ++b) {
-            a += work[((long long)b * N_COLS + c) * 3 + 0];
-            lo = fmin(lo, work[((long long)b * N_COLS + c) * 3 + 1]);
-            hi = fmax(hi, work[((long long)b * N_COLS + c) * 3 + 2]);
+            const double *w = work + ((long long)b * STAT_COLS + c) * 4;
+            a += w[0];
+            cnt += w[1];
+            lo = fmin(lo, w[2]);
+            hi = fmax(hi, w[3]);
         }
-        out[c * 4 + 0] = a / (double)n;
-        out[c * 4 + 2] = lo;
-        out[c * 4 + 3] = hi;
+        out[c * 4 + 0] = cnt > 0.0 ? a / cnt : 0.0;
+        out[c * 4 + 1] = cnt;
+        out[c * 4 + 2] = cnt > 0.0 ? lo : 0.0;
+        out[c * 4 + 3] = cnt > 0.0 ? hi : 0.0;
     } else {
         double a = 0.0;
-        for (int b = 0; b < STAT_BLOCKS; ++b) a += work[((long long)b * N_COLS + c) * 3 + 0];
-        out[c * 4 + 1] = sqrt(a / (double)n);
+        for (int b = 0; b < STAT_BLOCKS; ++b) a += work[((long long)b * STAT_COLS + c) * 4 + 0];
+        const double cnt = out[c * 4 + 1];
+        out[c * 4 + 1] = cnt > 0.0 ? sqrt(a / cnt) : 0.0;
     }
 }
 
@@ -980,16 +997,17 @@ hipError_t launch_colstats(const double *X, const double *T, long long n, double
     if (n <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_colstats, dim3(STAT_BLOCKS), dim3(256), 0, s, X, T, n, 0,
                        (const double *)nullptr, work);
-    hipLaunchKernelGGL(k_colstats_final, dim3(1), dim3(64), 0, s, work, n, 0, out);
+    hipLaunchKernelGGL(k_colstats_final, dim3(1), dim3(64), 0, s, work, 0, out);
     hipLaunchKernelGGL(k_colstats, dim3(STAT_BLOCKS), dim3(256), 0, s, X, T, n, 1, out, work);
-    hipLaunchKernelGGL(k_colstats_final, dim3(1), dim3(64), 0, s, work, n, 1, out);
+    hipLaunchKernelGGL(k_colstats_final, dim3(1), dim3(64), 0, s, work, 1, out);
     return hipGetLastError();
 }
 
 __global__ void k_build(const double *__restrict__ X, const double *__restrict__ T, long long n,
                         const int *__restrict__ perm, const double *__restrict__ mu,
-                        const double *__restrict__ sd, double tmu, double tsd,
-                        bf16_t *__restrict__ xq, float *__restrict__ tq)
+                        const double *__restrict__ sd, const double *__restrict__ tmu,
+                        const double *__restrict__ tsd, bf16_t *__restrict__ xq,
+                        float *__restrict__ tq, unsigned char *__restrict__ prod)
 {
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -1003,16 +1021,56 @@ __global__ void k_build(const double *__restrict__ X, const double *__restrict__
     }
     u32x4 *dst = reinterpret_cast<u32x4 *>(xq + d * K_IN);
     for (int j = 0; j < 4; ++j) dst[j] = u32x4{pk[4 * j], pk[4 * j + 1], pk[4 * j + 2], pk[4 * j + 3]};
-    tq[d] = (float)((T[r] - tmu) / tsd);
+    int j = 0;
+    for (int k = 1; k < 4; ++k)
+        if (X[r * N_FEAT + 2 + k] > X[r * N_FEAT + 2 + j]) j = k;
+    tq[d] = (float)((T[r] - tmu[j]) / tsd[j]);
+    prod[d] = (unsigned char)j;
 }
 
 hipError_t launch_build(const double *X, const double *T, long long n, const int *perm,
-                        const double *mu, const double *sd, double tmu, double tsd, bf16_t *xq,
-                        float *tq, hipStream_t s)
+                        const double *mu, const double *sd, const double *tmu, const double *tsd,
+                        bf16_t *xq, float *tq, unsigned char *prod, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_build, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, T, n, perm,
-                       mu, sd, tmu, tsd, xq, tq);
+                       mu, sd, tmu, tsd, xq, tq, prod);
+    return hipGetLastError();
+}
+
+// Residual t - y per one-hot product over n rows, fixed order:
+// out[0..3] sums, out[4..7] counts.
+__global__ void __launch_bounds__(256) k_residuals(const float *__restrict__ y,
+                                                   const float *__restrict__ t,
+                                                   const unsigned char *__restrict__ prod, int n,
+                                                   double *__restrict__ out)
+{
+    __shared__ double red[256];
+    for (int j = 0; j < 4; ++j) {
+        double a = 0.0, c = 0.0;
+        for (int i = threadIdx.x; i < n; i += 256) {
+            if (prod[i] == j) {
+                a += (double)t[i] - (double)y[i];
+                c += 1.0;
+            }
+        }
+        for (int st = 0; st < 2; ++st) {
+            red[threadIdx.x] = st ? c : a;
+            __syncthreads();
+            for (int w = 128; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) out[st * 4 + j] = red[0];
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_residuals(const float *y, const float *t, const unsigned char *prod, int n,
+                            double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residuals, dim3(1), dim3(256), 0, s, y, t, prod, n, out);
     return hipGetLastError();
 }
 

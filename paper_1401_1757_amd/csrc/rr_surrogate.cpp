@@ -33,7 +33,7 @@ struct BlobHeader {
     int32_t reserved[2];
 };
 static_assert(sizeof(BlobHeader) == 96, "blob header layout");
-constexpr size_t kBlobDoubles = 4 * M::N_FEAT + 2 + M::N_TENORS + M::N_FACTORS * M::N_TENORS;
+constexpr size_t kBlobDoubles = 4 * M::N_FEAT + 8 + M::N_TENORS + M::N_FACTORS * M::N_TENORS;
 constexpr size_t kBlobBytes = sizeof(BlobHeader) + kBlobDoubles * 8 + 3 * (size_t)M::N_PARAMS * 4;
 
 // splitmix64 (Steele, Lea and Flood, 2014).
@@ -112,7 +112,7 @@ struct rr::Surrogate {
     bool has_model = false;
     int version = 0;                      // bumps on every model change
     std::vector<double> mu, sd, lo, hi;   // [N_FEAT]
-    double tmu = 0.0, tsd = 1.0;
+    std::vector<double> tmu, tsd;         // [4] target statistics per one-hot product
     std::vector<double> zbar, evec;       // [N_TENORS], [N_FACTORS][N_TENORS]
     int32_t sig[12];
     int32_t adam_step = 0;
@@ -121,7 +121,7 @@ struct rr::Surrogate {
     DevBuf<float> master, adam_m, adam_v;
     DevBuf<uint16_t> w1t, w2t, w2n, w1_inf, w2_inf, w3_inf;
     DevBuf<float> w3e;
-    DevBuf<double> d_mu, d_sd, d_lo, d_hi, d_zbar, d_evec;
+    DevBuf<double> d_mu, d_sd, d_lo, d_hi, d_zbar, d_evec, d_tmu, d_tsd;
     DevBuf<int> d_sig;
 
     // portfolio copies in upload order
@@ -133,7 +133,7 @@ struct rr::Surrogate {
     DevBuf<double> seg, zcurves, sraw, praw;
     DevBuf<uint16_t> sfeat, pfeat, pfeat2;
     DevBuf<int> sok, pflag;
-    DevBuf<double> partial, exact, totals_tmp;
+    DevBuf<double> partial, exact, totals_tmp, oscale, ooffset;
 
     // fallback plan cache
     std::vector<uint64_t> plan_key;
@@ -151,7 +151,7 @@ struct rr::Surrogate {
     }
     M::Norm norm()
     {
-        return M::Norm{d_mu.p, d_sd.p, d_lo.p, d_hi.p, d_zbar.p, d_evec.p, d_sig.p};
+        return M::Norm{d_mu.p, d_sd.p, d_lo.p, d_hi.p, d_zbar.p, d_evec.p, d_sig.p, d_tmu.p, d_tsd.p};
     }
 };
 
@@ -191,6 +191,8 @@ int upload_norm(rr_ctx *c, Surrogate *S)
     if ((rc = upload_vec(c, S->d_hi, S->hi))) return rc;
     if ((rc = upload_vec(c, S->d_zbar, S->zbar))) return rc;
     if ((rc = upload_vec(c, S->d_evec, S->evec))) return rc;
+    if ((rc = upload_vec(c, S->d_tmu, S->tmu))) return rc;
+    if ((rc = upload_vec(c, S->d_tsd, S->tsd))) return rc;
     std::vector<int> sg(S->sig, S->sig + 12);
     if ((rc = upload_vec(c, S->d_sig, sg))) return rc;
     return RR_OK;
@@ -271,13 +273,16 @@ int compute_features(rr_ctx *c, Surrogate *S, const rr_run *run, bool with_model
     HIPCHK(c, S->pfeat.alloc((size_t)std::max(1LL, np * 8)));
     HIPCHK(c, S->pfeat2.alloc((size_t)std::max(1LL, np)));
     HIPCHK(c, S->pflag.alloc((size_t)std::max(1LL, np)));
+    HIPCHK(c, S->oscale.alloc((size_t)std::max(1LL, np)));
+    HIPCHK(c, S->ooffset.alloc((size_t)std::max(1LL, np)));
     HIPCHK(c, M::launch_scen_features(c->v.p, c->n_steps, c->scen_pad, c->shock.p, S->seg.p,
                                       run->node_begin, run->node_count, run->scen_begin,
                                       run->scen_count, nm, want_raw ? S->sraw.p : nullptr,
                                       S->sfeat.p, S->sok.p, st));
     HIPCHK(c, M::launch_policy_features(policies_of(S, c->n_user), run->node_begin, run->node_count,
                                         run->node_step_m, nm, want_raw ? S->praw.p : nullptr,
-                                        S->pfeat.p, S->pfeat2.p, S->pflag.p, st));
+                                        S->pfeat.p, S->pfeat2.p, S->pflag.p, S->oscale.p,
+                                        S->ooffset.p, st));
     return RR_OK;
 }
 
@@ -526,8 +531,8 @@ extern "C" int rr_surrogate_get_weights(rr_ctx *c, void *host, size_t bytes, siz
     for (int j = 0; j < M::N_FEAT; ++j) dd[k++] = S->sd[j];
     for (int j = 0; j < M::N_FEAT; ++j) dd[k++] = S->lo[j];
     for (int j = 0; j < M::N_FEAT; ++j) dd[k++] = S->hi[j];
-    dd[k++] = S->tmu;
-    dd[k++] = S->tsd;
+    for (int j = 0; j < 4; ++j) dd[k++] = S->tmu[j];
+    for (int j = 0; j < 4; ++j) dd[k++] = S->tsd[j];
     for (int j = 0; j < M::N_TENORS; ++j) dd[k++] = S->zbar[j];
     for (int j = 0; j < M::N_FACTORS * M::N_TENORS; ++j) dd[k++] = S->evec[j];
     float *ff = (float *)(dd + kBlobDoubles);
@@ -556,7 +561,9 @@ extern "C" int rr_surrogate_set_weights(rr_ctx *c, const void *host, size_t byte
         if (!(dd[M::N_FEAT + j] > 0.0)) return fail(c, RR_EINVAL, "feature %d: standard deviation must be > 0", j);
         if (dd[2 * M::N_FEAT + j] > dd[3 * M::N_FEAT + j]) return fail(c, RR_EINVAL, "feature %d: box lo > hi", j);
     }
-    if (!(dd[4 * M::N_FEAT + 1] > 0.0)) return fail(c, RR_EINVAL, "target standard deviation must be > 0");
+    for (int j = 0; j < 4; ++j)
+        if (!(dd[4 * M::N_FEAT + 4 + j] > 0.0))
+            return fail(c, RR_EINVAL, "target standard deviation %d must be > 0", j);
     const float *ff = (const float *)(dd + kBlobDoubles);
     for (size_t k = 0; k < 3 * (size_t)M::N_PARAMS; ++k)
         if (!std::isfinite(ff[k])) return fail(c, RR_EINVAL, "non-finite parameter at %zu", k);
@@ -572,8 +579,8 @@ extern "C" int rr_surrogate_set_weights(rr_ctx *c, const void *host, size_t byte
     S->sd.assign(dd + k, dd + k + M::N_FEAT); k += M::N_FEAT;
     S->lo.assign(dd + k, dd + k + M::N_FEAT); k += M::N_FEAT;
     S->hi.assign(dd + k, dd + k + M::N_FEAT); k += M::N_FEAT;
-    S->tmu = dd[k++];
-    S->tsd = dd[k++];
+    S->tmu.assign(dd + k, dd + k + 4); k += 4;
+    S->tsd.assign(dd + k, dd + k + 4); k += 4;
     S->zbar.assign(dd + k, dd + k + M::N_TENORS); k += M::N_TENORS;
     S->evec.assign(dd + k, dd + k + M::N_FACTORS * M::N_TENORS);
     memcpy(S->sig, h.signature, sizeof S->sig);
@@ -751,10 +758,10 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
     // Standardisation and box (new model).
     if (cfg->init) {
         DevBuf<double> work, stats;
-        HIPCHK(c, work.alloc((size_t)256 * (M::N_FEAT + 1) * 3));
-        HIPCHK(c, stats.alloc((size_t)(M::N_FEAT + 1) * 4));
+        HIPCHK(c, work.alloc((size_t)M::STAT_BLOCKS * M::STAT_COLS * 4));
+        HIPCHK(c, stats.alloc((size_t)M::STAT_COLS * 4));
         HIPCHK(c, M::launch_colstats(X.p, T.p, N, work.p, stats.p, st));
-        std::vector<double> hs((M::N_FEAT + 1) * 4);
+        std::vector<double> hs(M::STAT_COLS * 4);
         HIPCHK(c, hipMemcpyAsync(hs.data(), stats.p, hs.size() * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         S->mu.resize(M::N_FEAT);
@@ -767,8 +774,13 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
             S->lo[j] = hs[j * 4 + 2];
             S->hi[j] = hs[j * 4 + 3];
         }
-        S->tmu = hs[M::N_FEAT * 4 + 0];
-        S->tsd = hs[M::N_FEAT * 4 + 1] > 0.0 ? hs[M::N_FEAT * 4 + 1] : 1.0;
+        S->tmu.assign(4, 0.0);
+        S->tsd.assign(4, 1.0);
+        for (int j = 0; j < 4; ++j) {
+            const double *cs = &hs[(M::N_FEAT + 1 + j) * 4];
+            S->tmu[j] = cs[0];
+            S->tsd[j] = cs[1] > 0.0 ? cs[1] : 1.0;
+        }
         if ((rc = upload_norm(c, S))) return rc;
     }
 
@@ -782,12 +794,14 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
     const long long N_pad = pad64(N);
     DevBuf<uint16_t> xq;
     DevBuf<float> tq;
+    DevBuf<unsigned char> prod;
     HIPCHK(c, xq.alloc((size_t)N_pad * M::K_IN));
     HIPCHK(c, tq.alloc((size_t)N_pad));
+    HIPCHK(c, prod.alloc((size_t)N_pad));
     HIPCHK(c, hipMemsetAsync(xq.p, 0, (size_t)N_pad * M::K_IN * 2, st));
     HIPCHK(c, hipMemsetAsync(tq.p, 0, (size_t)N_pad * 4, st));
-    HIPCHK(c, M::launch_build(X.p, T.p, N, d_perm.p, S->d_mu.p, S->d_sd.p, S->tmu, S->tsd, xq.p,
-                              tq.p, st));
+    HIPCHK(c, M::launch_build(X.p, T.p, N, d_perm.p, S->d_mu.p, S->d_sd.p, S->d_tmu.p,
+                              S->d_tsd.p, xq.p, tq.p, prod.p, st));
     HIPCHK(c, hipStreamSynchronize(st));
     X.release();
     T.release();
@@ -837,6 +851,35 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
             return rc;
         HIPCHK(c, hipMemcpyAsync(&hold, S->scal.p, 4, hipMemcpyDeviceToHost, st));
     }
+    // Output calibration: per product, shift the target mean by the mean
+    // residual of the trained network over the training rows (the least-
+    // squares offset given the network).
+    double calib[4] = {0.0, 0.0, 0.0, 0.0};
+    {
+        DevBuf<double> part;
+        HIPCHK(c, part.alloc((size_t)n_batches * 8));
+        for (long long b = 0; b < n_batches; ++b) {
+            if ((rc = network_pass(c, S, xq.p + b * B * M::K_IN, B, B, nullptr, false, nullptr,
+                                   nullptr, S->y.p)))
+                return rc;
+            HIPCHK(c, M::launch_residuals(S->y.p, tq.p + b * B, prod.p + b * B, (int)B,
+                                          part.p + b * 8, st));
+        }
+        std::vector<double> hp((size_t)n_batches * 8);
+        HIPCHK(c, hipMemcpyAsync(hp.data(), part.p, hp.size() * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        for (int j = 0; j < 4; ++j) {
+            double a = 0.0, cnt = 0.0;
+            for (long long b = 0; b < n_batches; ++b) {
+                a += hp[(size_t)b * 8 + j];
+                cnt += hp[(size_t)b * 8 + 4 + j];
+            }
+            if (cnt > 0.0) calib[j] = a / cnt;
+            S->tmu[j] += S->tsd[j] * calib[j];
+        }
+        if ((rc = upload_norm(c, S))) return rc;
+        S->version += 1;
+    }
     HIPCHK(c, hipStreamSynchronize(st));
     const double t2 = now_ms();
     if (rep) {
@@ -853,7 +896,7 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
         rep->first_loss = (float)(f / (double)n_batches);
         rep->final_loss = (float)(l / (double)n_batches);
         rep->holdout_loss = hold;
-        rep->holdout_rmse = std::sqrt((double)hold) * S->tsd;
+        for (int j = 0; j < 4; ++j) rep->calibration[j] = (float)calib[j];
         rep->data_ms = t1 - t0;
         rep->train_ms = t2 - t1;
     }
@@ -959,13 +1002,27 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
     f.pflag = S->pflag.p;
     f.sfeat = S->sfeat.p;
     f.sok = S->sok.p;
-    f.amount = S->amount.p;
-    f.tmu = S->tmu;
-    f.tsd = S->tsd;
+    f.scale = S->oscale.p;
+    f.offset = S->ooffset.p;
     f.r0 = (mask & RR_OUT_R0) ? out->r0 : nullptr;
     f.exact = exact;
     f.partial = S->partial.p;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (c->opt_timing) {   // events around the fused kernel, read by rr_kernel_times
+        if (!c->ev_free.empty()) {
+            ev = c->ev_free.back();
+            c->ev_free.pop_back();
+        } else {
+            HIPCHK(c, hipEventCreate(&ev.first));
+            HIPCHK(c, hipEventCreate(&ev.second));
+        }
+        HIPCHK(c, hipEventRecord(ev.first, st));
+    }
     HIPCHK(c, M::launch_infer(f, S->weights(), st));
+    if (c->opt_timing) {
+        HIPCHK(c, hipEventRecord(ev.second, st));
+        c->ev_pending.push_back(ev);
+    }
     if (totals) {
         HIPCHK(c, M::launch_chunk_totals(S->partial.p, run->node_count, n_chunks, run->scen_count,
                                          totals, st));

@@ -61,7 +61,7 @@ def neutral_model(rng, params):
     import paper_1401_1757_amd as rr
     E, _ = np.linalg.qr(rng.normal(size=(mlp.N_TENORS, 3)))
     return rr.pack_surrogate_blob(mlp.flatten(params), np.zeros(17), np.ones(17),
-                                  np.full(17, -1e9), np.full(17, 1e9), 0.0, 1.0,
+                                  np.full(17, -1e9), np.full(17, 1e9), np.zeros(4), np.ones(4),
                                   np.zeros(mlp.N_TENORS), E.T, np.full((4, 3), -1))
 
 
@@ -122,7 +122,7 @@ def test_adam_step_matches_oracle(ctx, rr):
     for d in (m, v):
         d["W1"][mlp.N_FEAT:] = 0
     blob = rr.pack_surrogate_blob(mlp.flatten(p), np.zeros(17), np.ones(17), np.full(17, -1.0),
-                                  np.ones(17), 0.0, 1.0, np.zeros(50), np.eye(3, 50),
+                                  np.ones(17), np.zeros(4), np.ones(4), np.zeros(50), np.eye(3, 50),
                                   np.full((4, 3), -1), adam_m=mlp.flatten(m), adam_v=mlp.flatten(v),
                                   adam_step=4)
     ctx.surrogate_set_weights(blob)
@@ -262,7 +262,8 @@ def test_infer_matches_oracle_with_fallback(ctx, rr, omodel):
             X = np.array([mlp.assemble(praw[k, i], sraw[k, s], 0) for s in range(b.n_scen)])
             pred[k, i] = mlp.predict_reserves(p, X, pf.amount[i], omodel["mu"], omodel["sd"],
                                               omodel["tmu"], omodel["tsd"])
-    ys = (pf.amount[None, :, None] * omodel["tsd"]) * np.ones_like(exact)
+    slot = np.select([pf.product == c for c in mlp.SURROGATE_PRODUCTS], [0, 1, 2, 3], 0)
+    ys = (pf.amount * omodel["tsd"][slot])[None, :, None] * np.ones_like(exact)
     assert_flip_tolerant(got[net] / ys[net], pred[net] / ys[net], 1.0, "inference rows")
     # totals: the sum of the rows, with or without r0 written
     tot = to_np(out["totals"])
@@ -292,8 +293,13 @@ def test_training_fits_and_matches_oracle_statistics(ctx, rr, omodel):
     assert rep["final_loss"] < 0.05 * rep["first_loss"]
     assert rep["holdout_loss"] < 0.05
     got = rr.unpack_surrogate_blob(ctx.surrogate_get_weights())
-    for k in ("mu", "sd", "tmu", "tsd"):
+    for k in ("mu", "sd", "tsd"):
         np.testing.assert_allclose(got[k], omodel[k], rtol=1e-9, atol=1e-12)
+    # target means carry the output calibration reported by training
+    cal = np.asarray(rep["calibration"], np.float64)
+    assert np.all(np.abs(cal) < 0.05)
+    np.testing.assert_allclose(got["tmu"] - got["tsd"] * cal, omodel["tmu"], rtol=0,
+                               atol=1e-6 * float(np.max(omodel["tsd"])))
     np.testing.assert_allclose(got["lo"], omodel["lo"], rtol=1e-13, atol=1e-14)
     np.testing.assert_allclose(got["hi"], omodel["hi"], rtol=1e-13, atol=1e-14)
     np.testing.assert_allclose(got["zbar"], omodel["zbar"], rtol=1e-12, atol=1e-15)

@@ -205,5 +205,10 @@ def test_samples_come_from_exact_reserves():
     live = X.std(axis=0) > 0
     assert np.allclose(zs[:, :mlp.N_FEAT][:, live].std(axis=0), 1, atol=1e-6)
     assert np.all(zs[:, mlp.N_FEAT:] == 0)
+    ts = mlp.standardise_target(X, T, tmu, tsd)
+    for j in range(4):
+        sel = X[:, mlp.F_PROD + j] == 1
+        if sel.sum() > 1 and np.std(T[sel]) > 0:
+            assert abs(ts[sel].mean()) < 1e-6 and abs(ts[sel].std() - 1) < 1e-6
     assert mlp.in_range(X, lo, hi).all()
     assert not mlp.in_range(X[:1] + (hi - lo + 1), lo, hi).any()
