@@ -122,14 +122,18 @@ SURROGATE_FIT = dict(epochs=24, batch=8192, lr=2e-3, lr_final=1e-5, holdout=0.01
 MLP_FLOPS_PER_ROW = 2 * (17 * 256 + 256 * 256 + 256)   # algorithmic: 17 inputs, two 256-wide layers, head
 
 
-def surrogate_leg(rr, synth, ctx, w, exact_totals, n_val, exact_ms, steps, sync, profile_only=False):
+def surrogate_leg(rr, synth, ctx, w, exact_totals, n_val, exact_ms, steps, sync, profile_only=False,
+                  epochs=0):
     """Train the MLP surrogate on GPU-generated exact samples, then time its
     inference over the same workload (same outputs as the exact step)."""
     tw = synth.surrogate_training_workload(**SURROGATE_TRAIN)
     ctx.basis_upload(tw.basis.q, tw.basis.v, tw.basis.shock)
     ctx.portfolio_upload(tw.portfolio)
     t0 = time.perf_counter()
-    rep = ctx.surrogate_train(node_step=0, **SURROGATE_FIT)
+    fit = dict(SURROGATE_FIT)
+    if epochs:
+        fit["epochs"] = epochs
+    rep = ctx.surrogate_train(node_step=0, **fit)
     train_s = time.perf_counter() - t0
     b, pf = w.basis, w.portfolio
     ctx.basis_upload(b.q, b.v, b.shock)
@@ -194,6 +198,8 @@ def main():
     ap.add_argument("--wg", type=int, default=0, help="pin workgroups per CU (0 = autotune)")
     ap.add_argument("--block-j", type=int, default=0, help="pin policies per lane (0 = autotune)")
     ap.add_argument("--term-bucket", type=int, default=0, help="months per term bucket (0 = default)")
+    ap.add_argument("--surrogate-epochs", type=int, default=0,
+                    help="epochs of the surrogate training (0 = the default fit)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -251,7 +257,7 @@ def main():
         ctx.close()
         ctx = rr.Context(0)
         r = surrogate_leg(rr, synth, ctx, w, None, n_val, ms_per_step, args.steps, sync,
-                          profile_only=True)
+                          profile_only=True, epochs=args.surrogate_epochs)
         print(json.dumps(r))
         ctx.close()
         return

@@ -147,8 +147,8 @@ struct rr_ctx {
     // graphs
     std::vector<GraphEntry> graphs;
 
-    // work list of the surrogate's exact fallback
-    Plan item_plan;
+    // work lists of the surrogate's exact fallback
+    Plan item_plan[2];
 
     // surrogate
     rr::Surrogate *sur = nullptr;
@@ -175,10 +175,14 @@ int upload_vec(rr_ctx *c, DevBuf<T> &d, const std::vector<T> &h)
     return RR_OK;
 }
 
-// Run the recurrence kernel (one scenario and one tile per lane group) on a
+// Run the recurrence kernel (K scenarios per lane, one tile per item) on a
 // given list of work items of run `run`, writing state-0 reserves r_0
-// [node][policy][scen] only; asynchronous on the context's stream.
-int run_items(rr_ctx *c, const rr_run *run, const std::vector<Item> &items, double *r0);
+// [node][policy][scen] only; asynchronous on the context's stream.  slot
+// (0 or 1) selects the device copy of the list, so two lists can be in
+// flight; fresh = false reuses the copy uploaded by the previous call on
+// that slot (the caller guarantees the same list).
+int run_items(rr_ctx *c, const rr_run *run, const std::vector<Item> &items, int K, double *r0,
+              int slot, bool fresh);
 
 }  // namespace host
 }  // namespace rr

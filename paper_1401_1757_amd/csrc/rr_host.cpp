@@ -752,17 +752,21 @@ static int enqueue_run(rr_ctx *c, const rr_run *run, const rr_outputs *out, Plan
     return RR_OK;
 }
 
-int rr::host::run_items(rr_ctx *c, const rr_run *run, const std::vector<Item> &items, double *r0)
+int rr::host::run_items(rr_ctx *c, const rr_run *run, const std::vector<Item> &items, int K,
+                        double *r0, int slot, bool fresh)
 {
     if (items.empty()) return RR_OK;
+    if (!supported_kj(K, 1) || slot < 0 || slot > 1) return fail(c, RR_EINVAL, "bad item launch");
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, hipStreamSynchronize(c->stream));   // the item buffers may be in use
-    Plan &pl = c->item_plan;
-    std::vector<int> qbeg = {0, (int)items.size()};
+    Plan &pl = c->item_plan[slot];
     int rc;
-    if ((rc = upload_vec(c, pl.items, items))) return rc;
-    if ((rc = upload_vec(c, pl.qbeg, qbeg))) return rc;
-    pl.K = 1;
+    if (fresh || pl.n_items != (int)items.size()) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));   // the item buffers may be in use
+        std::vector<int> qbeg = {0, (int)items.size()};
+        if ((rc = upload_vec(c, pl.items, items))) return rc;
+        if ((rc = upload_vec(c, pl.qbeg, qbeg))) return rc;
+    }
+    pl.K = K;
     pl.J = 1;
     pl.n_items = (int)items.size();
     pl.n_queues = 1;
@@ -775,7 +779,7 @@ int rr::host::run_items(rr_ctx *c, const rr_run *run, const std::vector<Item> &i
     o.r0 = r0;
     RecParams P = make_params(c, &r, &o, &pl, nullptr);
     const size_t lds = P.q_in_lds ? (size_t)P.n_q * sizeof(double) : 0;
-    HIPCHK(c, launch_recurrence(1, 1, P, pl.grid, lds, c->stream));
+    HIPCHK(c, launch_recurrence(K, 1, P, pl.grid, lds, c->stream));
     return RR_OK;
 }
 

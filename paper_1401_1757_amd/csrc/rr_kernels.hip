@@ -55,59 +55,14 @@ __device__ __forceinline__ double qload(const double *__restrict__ lds, const do
     else return glob[idx];
 }
 
-// State-0 reserves of a tile through the wavefront's LDS rows: each lane
-// holds K consecutive scenarios of its own policy (one output row each), so
-// a direct store would touch 64 rows per instruction.  After the transpose a
-// store instruction writes whole K-scenario segments of 128 / K policies'
-// rows (K = 16: eight 128-byte segments).  Row stride K + 2 doubles keeps the
-// LDS writes free of bank conflicts.
-template <int K>
-__device__ __forceinline__ void store_r0_rows(const RecParams &P, double *sout, int node_rel, int sb,
-                                              int lane, int uid, bool live, const double (&r0)[K])
-{
-    constexpr int W = K + 2;
-    double *row = sout + lane * W;
-#pragma unroll
-    for (int k = 0; k < K; k += 2) {
-        double2 x;
-        x.x = live ? r0[k] : 0.0;
-        x.y = live ? r0[k + 1] : 0.0;
-        *reinterpret_cast<double2 *>(row + k) = x;
-    }
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    constexpr int G = K / 2;        // lanes per policy, two scenarios each
-    constexpr int PPI = 64 / G;     // policies per store instruction
-    const int sub = lane % G, pl = lane / G;
-    double *base = P.r0 + (size_t)node_rel * P.n_user * P.scen_count + sb + 2 * sub;
-#pragma unroll
-    for (int i = 0; i < 64 / PPI; ++i) {
-        const int p = i * PPI + pl;
-        const int u = __shfl(uid, p);
-        const double2 x = *reinterpret_cast<const double2 *>(sout + p * W + 2 * sub);
-        if (u >= 0) *reinterpret_cast<double2 *>(base + (size_t)u * P.scen_count) = x;
-    }
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // reads done before the rows are reused
-}
-
-template <int K>
-constexpr bool kTransposeStores = K >= 2 && K <= 16;
-
 // Store the item's results: per-lane r0 slots and per-scenario wave totals.
 template <int K>
-__device__ __forceinline__ void store_results(const RecParams &P, double *sout, int node_rel,
-                                              int tile, int sb, int lane, int uid, bool live,
-                                              const double (&r0)[K], const double (&r1)[K],
-                                              const double (&r2)[K], bool has1, bool has2)
+__device__ __forceinline__ void store_results(const RecParams &P, int node_rel, int tile, int sb,
+                                              int lane, int uid, bool live, const double (&r0)[K],
+                                              const double (&r1)[K], const double (&r2)[K],
+                                              bool has1, bool has2)
 {
-    bool rows_done = false;
-    if constexpr (kTransposeStores<K>) {
-        // whole K-blocks of an even scenario count: 16-byte aligned segments
-        if (P.r0 != nullptr && P.r0_states == 1 && sb + K <= P.scen_count && (P.scen_count & 1) == 0) {
-            store_r0_rows<K>(P, sout, node_rel, sb, lane, uid, live, r0);
-            rows_done = true;
-        }
-    }
-    if (!rows_done && P.r0 != nullptr && uid >= 0) {
+    if (P.r0 != nullptr && uid >= 0) {
         double *o = P.r0 + (((size_t)node_rel * P.n_user + uid) * P.scen_count + sb) * P.r0_states;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -318,7 +273,7 @@ template <int K, int J, bool LDSQ, bool TWO>
 __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__restrict__ lq,
                                            const double *__restrict__ vcurves, int node_rel,
                                            int tile, int count, const Tile &T0, int item_smax,
-                                           int item_smin, int sb, int lane, double *sout)
+                                           int item_smin, int sb, int lane)
 {
     const int node = P.node_begin + node_rel;
     const int shift = node * P.node_step;
@@ -369,8 +324,8 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
     for (int j = 0; j < J; ++j) {
         if (j < count) {
             const bool live = uid[j] >= 0 && L[j].S > 0;
-            store_results<K>(P, sout, node_rel, tile + j, sb, lane, uid[j], live, r[j], r[j], r[j],
-                             false, false);
+            store_results<K>(P, node_rel, tile + j, sb, lane, uid[j], live, r[j], r[j], r[j], false,
+                             false);
         }
     }
 }
@@ -493,8 +448,7 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
 template <int K, bool LDSQ, bool LAST>
 __device__ __forceinline__ void run_vector(const RecParams &P, const double *__restrict__ lq,
                                            const double *__restrict__ vcurves, int node_rel,
-                                           int tile, const Tile &T, int sb, int lane,
-                                           double *sout)
+                                           int tile, const Tile &T, int sb, int lane)
 {
     const int node = P.node_begin + node_rel;
     const int shift = node * P.node_step;
@@ -529,7 +483,7 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
     else
         vector_steps<K, LDSQ, LAST, true>(lq, P.q, vb, P.scen_pad, qa, qb, m, cf, S, smax, smin,
                                           r0, r1, r2, path);
-    store_results<K>(P, sout, node_rel, tile, sb, lane, uid, live, r0, r1, r2, LAST, true);
+    store_results<K>(P, node_rel, tile, sb, lane, uid, live, r0, r1, r2, LAST, true);
 }
 
 // Persistent grid: each wavefront takes items from its XCD's queue (the
@@ -542,9 +496,6 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
              const Tile *__restrict__ tiles, const int *__restrict__ qbeg)
 {
     extern __shared__ double s_q[];
-    // per-wavefront rows for the transposed r0 stores
-    __shared__ __attribute__((aligned(16))) double s_out[kTransposeStores<K> ? (WG_THREADS / 64) * 64 * (K + 2) : 2];
-    double *sout = s_out + (kTransposeStores<K> ? (threadIdx.x >> 6) * 64 * (K + 2) : 0);
     if constexpr (LDSQ) {
         for (int i = threadIdx.x; i < P.n_q; i += blockDim.x) s_q[i] = P.q[i];
         __syncthreads();
@@ -582,15 +533,15 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
         }
         if (T.kind == KIND_SINGLE) {
             run_scalar<K, J, LDSQ, false>(P, s_q, vcurves, node_rel, tile, count, T, smax, smin, sb,
-                                          lane, sout);
+                                          lane);
         } else if (T.kind == KIND_JOINT) {
             run_scalar<K, J, LDSQ, true>(P, s_q, vcurves, node_rel, tile, count, T, smax, smin, sb,
-                                         lane, sout);
+                                         lane);
         } else if constexpr (VEC) {
             if (T.kind == KIND_REV)
-                run_vector<K, LDSQ, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane, sout);
+                run_vector<K, LDSQ, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
             else
-                run_vector<K, LDSQ, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane, sout);
+                run_vector<K, LDSQ, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
         }
     }
     // The last wavefront to finish re-arms the queues for the next launch.

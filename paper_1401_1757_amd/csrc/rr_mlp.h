@@ -153,8 +153,11 @@ struct Infer {
 };
 hipError_t launch_infer(const Infer &f, const Weights &w, hipStream_t s);
 int infer_rows_per_unit();   // scenarios per work unit of the fused kernel
+// totals[node][scen] = sum over chunks of partial[node][chunk][scen], fixed
+// order; work holds chunk_totals_work(node_count, scen_count) doubles.
+long long chunk_totals_work(int node_count, int scen_count);
 hipError_t launch_chunk_totals(const double *partial, int node_count, int n_chunks,
-                               int scen_count, double *totals, hipStream_t s);
+                               int scen_count, double *work, double *totals, hipStream_t s);
 
 // ---- training data --------------------------------------------------------
 // Raw sample rows X[N][N_FEAT] and targets from exact reserves
@@ -176,7 +179,9 @@ hipError_t launch_colstats(const double *X, const double *T, long long n, double
 hipError_t launch_build(const double *X, const double *T, long long n, const int *perm,
                         const double *mu, const double *sd, const double *tmu, const double *tsd,
                         bf16_t *xq, float *tq, unsigned char *prod, hipStream_t s);
-// Sums of t - y and row counts per one-hot product: out[0..3], out[4..7].
+// Sums of t - y and row counts per one-hot product for each block of 1024
+// rows: out[block][0..3], out[block][4..7], residual_blocks(n) blocks.
+int residual_blocks(int n);
 hipError_t launch_residuals(const float *y, const float *t, const unsigned char *prod, int n,
                             double *out, hipStream_t s);
 

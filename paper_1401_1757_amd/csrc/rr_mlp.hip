@@ -847,24 +847,55 @@ hipError_t launch_infer(const Infer &f, const Weights &w, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_chunk_totals(const double *__restrict__ partial, int node_count, int n_chunks,
-                               int scen_count, double *__restrict__ totals)
+// Totals over the policy chunks of the fused kernel, in a fixed order: the
+// chunks are split into CT_GROUPS contiguous groups (one workgroup column
+// each, four interleaved lanes per scenario), then the groups are summed.
+constexpr int CT_GROUPS = 16;
+
+__global__ void __launch_bounds__(256) k_chunk_partial(const double *__restrict__ partial,
+                                                       int n_chunks, int scen_count,
+                                                       double *__restrict__ work)
+{
+    __shared__ double red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int s = blockIdx.x * 64 + tx, g = blockIdx.y, k = blockIdx.z;
+    const int per = (n_chunks + CT_GROUPS - 1) / CT_GROUPS;
+    const int c0 = g * per, c1 = min(n_chunks, c0 + per);
+    double a = 0.0;
+    if (s < scen_count) {
+        for (int c = c0 + ty; c < c1; c += 4) a += partial[((long long)k * n_chunks + c) * scen_count + s];
+    }
+    red[ty][tx] = a;
+    __syncthreads();
+    if (ty == 0 && s < scen_count)
+        work[((long long)k * CT_GROUPS + g) * scen_count + s] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+}
+
+__global__ void k_chunk_final(const double *__restrict__ work, int node_count, int scen_count,
+                              double *__restrict__ totals)
 {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long long)node_count * scen_count) return;
     const int k = (int)(id / scen_count), s = (int)(id % scen_count);
     double a = 0.0;
-    for (int c = 0; c < n_chunks; ++c) a += partial[((long long)k * n_chunks + c) * scen_count + s];
+    for (int g = 0; g < CT_GROUPS; ++g) a += work[((long long)k * CT_GROUPS + g) * scen_count + s];
     totals[id] = a;
 }
 
+long long chunk_totals_work(int node_count, int scen_count)
+{
+    return (long long)node_count * CT_GROUPS * scen_count;
+}
+
 hipError_t launch_chunk_totals(const double *partial, int node_count, int n_chunks, int scen_count,
-                               double *totals, hipStream_t s)
+                               double *work, double *totals, hipStream_t s)
 {
     const long long n = (long long)node_count * scen_count;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chunk_totals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial,
-                       node_count, n_chunks, scen_count, totals);
+    hipLaunchKernelGGL(k_chunk_partial, dim3((scen_count + 63) / 64, CT_GROUPS, node_count), dim3(256),
+                       0, s, partial, n_chunks, scen_count, work);
+    hipLaunchKernelGGL(k_chunk_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, work,
+                       node_count, scen_count, totals);
     return hipGetLastError();
 }
 
@@ -1038,17 +1069,19 @@ hipError_t launch_build(const double *X, const double *T, long long n, const int
     return hipGetLastError();
 }
 
-// Residual t - y per one-hot product over n rows, fixed order:
-// out[0..3] sums, out[4..7] counts.
+// Residual t - y per one-hot product, per block of 1024 rows in a fixed
+// order: out[block][0..3] sums, out[block][4..7] counts.
 __global__ void __launch_bounds__(256) k_residuals(const float *__restrict__ y,
                                                    const float *__restrict__ t,
                                                    const unsigned char *__restrict__ prod, int n,
                                                    double *__restrict__ out)
 {
     __shared__ double red[256];
+    const int r0 = blockIdx.x * 1024;
+    const int r1 = min(n, r0 + 1024);
     for (int j = 0; j < 4; ++j) {
         double a = 0.0, c = 0.0;
-        for (int i = threadIdx.x; i < n; i += 256) {
+        for (int i = r0 + threadIdx.x; i < r1; i += 256) {
             if (prod[i] == j) {
                 a += (double)t[i] - (double)y[i];
                 c += 1.0;
@@ -1061,16 +1094,19 @@ __global__ void __launch_bounds__(256) k_residuals(const float *__restrict__ y,
                 if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
                 __syncthreads();
             }
-            if (threadIdx.x == 0) out[st * 4 + j] = red[0];
+            if (threadIdx.x == 0) out[(long long)blockIdx.x * 8 + st * 4 + j] = red[0];
             __syncthreads();
         }
     }
 }
 
+int residual_blocks(int n) { return (n + 1023) / 1024; }
+
 hipError_t launch_residuals(const float *y, const float *t, const unsigned char *prod, int n,
                             double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_residuals, dim3(1), dim3(256), 0, s, y, t, prod, n, out);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_residuals, dim3(residual_blocks(n)), dim3(256), 0, s, y, t, prod, n, out);
     return hipGetLastError();
 }
 

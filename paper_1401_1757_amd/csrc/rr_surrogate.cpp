@@ -25,6 +25,7 @@ constexpr char kMagic[8] = {'R', 'R', 'S', 'U', 'R', 'R', '0', '1'};
 constexpr int kVersion = 1;
 constexpr int kProducts[4] = {RR_SL_ANN, RR_JL_ANN, RR_TERM, RR_ENDOW};
 constexpr int kChunk = 16;   // policies per work unit of the fused inference kernel
+constexpr int kFbK = 4;      // scenarios per lane for fallback tiles (short items, wide launch)
 
 struct BlobHeader {
     char magic[8];
@@ -133,11 +134,12 @@ struct rr::Surrogate {
     DevBuf<double> seg, zcurves, sraw, praw;
     DevBuf<uint16_t> sfeat, pfeat, pfeat2;
     DevBuf<int> sok, pflag;
-    DevBuf<double> partial, exact, totals_tmp, oscale, ooffset;
+    DevBuf<double> partial, exact, totals_tmp, oscale, ooffset, ct_work;
 
     // fallback plan cache
     std::vector<uint64_t> plan_key;
-    std::vector<Item> fb_items;
+    std::vector<Item> fb_tiles;     // tiles with a policy outside the box x blocks of kFbK scenarios
+    std::vector<Item> fb_scens;     // the other tiles x scenarios outside the box
     int64_t fb_rows = 0, in_rows = 0;
 
     // network workspaces (rows padded to 64)
@@ -856,21 +858,22 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
     // squares offset given the network).
     double calib[4] = {0.0, 0.0, 0.0, 0.0};
     {
+        const long long rb = M::residual_blocks((int)B);
         DevBuf<double> part;
-        HIPCHK(c, part.alloc((size_t)n_batches * 8));
+        HIPCHK(c, part.alloc((size_t)(n_batches * rb * 8)));
         for (long long b = 0; b < n_batches; ++b) {
             if ((rc = network_pass(c, S, xq.p + b * B * M::K_IN, B, B, nullptr, false, nullptr,
                                    nullptr, S->y.p)))
                 return rc;
             HIPCHK(c, M::launch_residuals(S->y.p, tq.p + b * B, prod.p + b * B, (int)B,
-                                          part.p + b * 8, st));
+                                          part.p + b * rb * 8, st));
         }
-        std::vector<double> hp((size_t)n_batches * 8);
+        std::vector<double> hp((size_t)(n_batches * rb * 8));
         HIPCHK(c, hipMemcpyAsync(hp.data(), part.p, hp.size() * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         for (int j = 0; j < 4; ++j) {
             double a = 0.0, cnt = 0.0;
-            for (long long b = 0; b < n_batches; ++b) {
+            for (long long b = 0; b < n_batches * rb; ++b) {
                 a += hp[(size_t)b * 8 + j];
                 cnt += hp[(size_t)b * 8 + 4 + j];
             }
@@ -950,12 +953,13 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
                                        (uint64_t)run->node_begin, (uint64_t)run->node_count,
                                        (uint64_t)run->scen_begin, (uint64_t)run->scen_count,
                                        (uint64_t)run->node_step_m};
-    if (key != S->plan_key) {
+    const bool fresh = key != S->plan_key;
+    if (fresh) {
         std::vector<int> pf((size_t)run->node_count * n), so((size_t)ns);
         HIPCHK(c, hipMemcpyAsync(pf.data(), S->pflag.p, pf.size() * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipMemcpyAsync(so.data(), S->sok.p, so.size() * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        std::vector<Item> items;
+        std::vector<Item> tiles_items, scen_items;
         int64_t fb = 0, in = 0;
         for (int k = 0; k < run->node_count; ++k) {
             std::vector<char> bad_tile(c->n_tiles, 0), bad_scen(run->scen_count, 0);
@@ -972,23 +976,29 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
             in += live_ok * (run->scen_count - nbad_scen);
             fb += live * run->scen_count - live_ok * (run->scen_count - nbad_scen);
             for (int tl = 0; tl < c->n_tiles; ++tl) {
-                for (int s = 0; s < run->scen_count; ++s)
-                    if (bad_tile[tl] || bad_scen[s]) items.push_back(Item{k, tl, s, 1});
+                if (bad_tile[tl]) {
+                    for (int s = 0; s < run->scen_count; s += kFbK) tiles_items.push_back(Item{k, tl, s, 1});
+                } else {
+                    for (int s = 0; s < run->scen_count; ++s)
+                        if (bad_scen[s]) scen_items.push_back(Item{k, tl, s, 1});
+                }
             }
         }
-        S->fb_items.swap(items);
+        S->fb_tiles.swap(tiles_items);
+        S->fb_scens.swap(scen_items);
         S->fb_rows = fb;
         S->in_rows = in;
         S->plan_key = key;
     }
     double *exact = nullptr;
-    if (!S->fb_items.empty()) {
+    if (!S->fb_tiles.empty() || !S->fb_scens.empty()) {
         if (mask & RR_OUT_R0) exact = out->r0;
         else {
             HIPCHK(c, S->exact.alloc((size_t)ns * n));
             exact = S->exact.p;
         }
-        if ((rc = run_items(c, run, S->fb_items, exact))) return rc;
+        if ((rc = run_items(c, run, S->fb_tiles, kFbK, exact, 0, fresh))) return rc;
+        if ((rc = run_items(c, run, S->fb_scens, 1, exact, 1, fresh))) return rc;
     }
     const int n_chunks = (n + kChunk - 1) / kChunk;
     HIPCHK(c, S->partial.alloc((size_t)run->node_count * n_chunks * run->scen_count));
@@ -1024,8 +1034,9 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
         c->ev_pending.push_back(ev);
     }
     if (totals) {
+        HIPCHK(c, S->ct_work.alloc((size_t)M::chunk_totals_work(run->node_count, run->scen_count)));
         HIPCHK(c, M::launch_chunk_totals(S->partial.p, run->node_count, n_chunks, run->scen_count,
-                                         totals, st));
+                                         S->ct_work.p, totals, st));
     }
     if (mask & RR_OUT_STATS) {
         const double tail = run->tail > 0.0 ? run->tail : 0.005;

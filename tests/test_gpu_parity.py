@@ -79,8 +79,7 @@ def test_all_products_random_small(ctx, K, J):
 @pytest.mark.parametrize("K,J", [(2, 1), (4, 1), (8, 1), (16, 1), (4, 2), (8, 2), (16, 2), (2, 4),
                                  (4, 4), (8, 4), (16, 4)])
 def test_even_scenario_count_state0_rows(ctx, K, J):
-    """State-0 outputs only, an even scenario count with a ragged last block:
-    whole blocks take the transposed row stores, the last one the direct path."""
+    """State-0 outputs only, an even scenario count with a ragged last block."""
     rng = np.random.default_rng(300 + K + 7 * J)
     w = synth.random_small(rng, n=333, n_steps=80, n_scen=2 * K + 6 if K > 2 else 10, n_nodes=2,
                            shock=True)
