@@ -20,7 +20,10 @@ enum Kind : int {
 constexpr int TILE = 64;          // policies per tile = lanes per wavefront
 constexpr int N_COEF = 6;         // per-policy cash-flow coefficients
 constexpr int MAX_QUEUES = 8;     // one work queue per XCD
-constexpr int WG_THREADS = 256;   // 4 wavefronts per workgroup
+#ifndef RR_WG_THREADS
+#define RR_WG_THREADS 256
+#endif
+constexpr int WG_THREADS = RR_WG_THREADS;   // wavefronts per workgroup x 64
 
 // Per-policy coefficients (rows of coef[N_COEF][n_pad]):
 //  KIND_SINGLE / KIND_JOINT:  0: a0 advance amount in state 0 (annuity due - premium)

@@ -318,6 +318,31 @@ def test_training_fits_and_matches_oracle_statistics(ctx, rr, omodel):
     assert np.array_equal(y1, y2)
 
 
+def test_training_and_inference_are_deterministic(rr, omodel):
+    """Every reduction runs in a fixed order: the same seed gives the same
+    model bit for bit, and inference repeats bit for bit."""
+    tw = omodel["workload"]
+    b, pf = tw.basis, tw.portfolio
+    blobs, outs = [], []
+    for _ in range(2):
+        c = rr.Context(0)
+        try:
+            c.basis_upload(b.q, b.v, b.shock)
+            c.portfolio_upload(pf)
+            c.surrogate_train(0, b.n_nodes, 0, b.n_scen, 0, epochs=3, batch=512, lr=2e-3,
+                              lr_final=1e-4, holdout=0.05, seed=9)
+            blobs.append(c.surrogate_get_weights())
+            o = c.alloc_outputs(b.n_nodes, b.n_scen, stats=True)
+            c.surrogate_infer(0, b.n_nodes, 0, b.n_scen, 0, o)
+            torch.cuda.synchronize()
+            outs.append({k: to_np(v) for k, v in o.items() if k != "report"})
+        finally:
+            c.close()
+    assert blobs[0] == blobs[1]
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
 def test_invalid_surrogate_calls(ctx, rr):
     w = parity_workload(n=64, n_nodes=1, n_scen=4)
     ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
