@@ -765,13 +765,97 @@ __global__ void __launch_bounds__(256) k_stats_select(const double *__restrict__
     if (tid == 0) stats[2 * node + 1] = key_value(sel_prefix);
 }
 
+// Small ranks (the 1-in-200 statistic): the rank largest totals are taken
+// one per round, the largest remaining one each time (ties: the lowest
+// scenario index), so the last one taken is the rank-th largest.  Each
+// thread keeps its TOP_PER_THREAD totals in registers; a round is a local
+// maximum, a wavefront arg-max by XOR butterfly and a pick among the four
+// wavefronts.
+constexpr int TOP_MAX_RANK = 32;
+constexpr int TOP_PER_THREAD = 16;
+
+__device__ __forceinline__ bool top_better(double a, int ia, double b, int ib)
+{
+    return a > b || (a == b && ia < ib);
+}
+
+__global__ void __launch_bounds__(256) k_stats_top(const double *__restrict__ totals,
+                                                   int scen_count, int rank,
+                                                   double *__restrict__ stats)
+{
+    __shared__ double red[256];
+    __shared__ double wv[4];
+    __shared__ int wi[4];
+    const int node = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double *x = totals + (size_t)node * scen_count;
+    double v[TOP_PER_THREAD];
+    unsigned int live = 0u;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < TOP_PER_THREAD; ++j) {
+        const int i = tid + 256 * j;
+        v[j] = i < scen_count ? x[i] : 0.0;
+        if (i < scen_count) {
+            acc += v[j];
+            live |= 1u << j;
+        }
+    }
+    const double total = block_sum_fixed(acc, red);
+    if (tid == 0) stats[2 * node] = total / (double)scen_count;
+    double g = 0.0;
+    for (int round = 0; round < rank; ++round) {
+        double bv = -__builtin_huge_val();
+        int bi = 0x7fffffff;
+#pragma unroll
+        for (int j = 0; j < TOP_PER_THREAD; ++j) {
+            const int i = tid + 256 * j;
+            if (((live >> j) & 1u) && top_better(v[j], i, bv, bi)) {
+                bv = v[j];
+                bi = i;
+            }
+        }
+        // a thread with no live entry holds (-inf, INT_MAX), which every live
+        // (finite) total beats
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off);
+            const int oi = __shfl_xor(bi, off);
+            if (top_better(ov, oi, bv, bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            wv[wave] = bv;
+            wi[wave] = bi;
+        }
+        __syncthreads();
+        double gv = wv[0];
+        int gi = wi[0];
+        for (int w = 1; w < 4; ++w)
+            if (top_better(wv[w], wi[w], gv, gi)) {
+                gv = wv[w];
+                gi = wi[w];
+            }
+        __syncthreads();
+        if ((gi & 255) == tid) live &= ~(1u << (gi >> 8));
+        g = gv;
+    }
+    if (tid == 0) stats[2 * node + 1] = g;
+}
+
 hipError_t launch_stats(const double *totals, int node_count, int scen_count, int rank,
                         double *stats, hipStream_t stream)
 {
     if (node_count <= 0 || scen_count <= 0) return hipSuccess;
     if (rank < 1 || rank > scen_count) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_stats_select, dim3(node_count), dim3(256), 0, stream, totals,
-                       scen_count, rank, stats);
+    if (rank <= TOP_MAX_RANK && scen_count <= 256 * TOP_PER_THREAD)
+        hipLaunchKernelGGL(k_stats_top, dim3(node_count), dim3(256), 0, stream, totals, scen_count,
+                           rank, stats);
+    else
+        hipLaunchKernelGGL(k_stats_select, dim3(node_count), dim3(256), 0, stream, totals,
+                           scen_count, rank, stats);
     return hipGetLastError();
 }
 
