@@ -44,7 +44,9 @@ class _Portfolio(ctypes.Structure):
                 ("age1", ctypes.c_void_p), ("age2", ctypes.c_void_p),
                 ("term", ctypes.c_void_p), ("table1", ctypes.c_void_p),
                 ("table2", ctypes.c_void_p), ("timing", ctypes.c_void_p),
-                ("amount", ctypes.c_void_p), ("premium", ctypes.c_void_p)]
+                ("amount", ctypes.c_void_p), ("premium", ctypes.c_void_p),
+                ("escalation", ctypes.c_void_p), ("anniv", ctypes.c_void_p),
+                ("annual", ctypes.c_void_p)]
 
 
 def _load():
@@ -82,9 +84,11 @@ class _Args:
                         self.v.shape[1], self.v.shape[2], _ptr(self.v), _ptr(self.shock))
         i32 = lambda x: np.ascontiguousarray(x, np.int32)
         f64 = lambda x: np.ascontiguousarray(x, np.float64)
+        opt = lambda x, f: None if x is None else f(x)
         self.arrs = [i32(pf.product), i32(pf.age1_m), i32(pf.age2_m), i32(pf.term_m),
                      i32(pf.table1), i32(pf.table2), i32(pf.timing), f64(pf.amount),
-                     f64(pf.premium)]
+                     f64(pf.premium), opt(getattr(pf, "escalation", None), f64),
+                     opt(getattr(pf, "anniv_m", None), i32), opt(getattr(pf, "annual", None), i32)]
         self.p = _Portfolio(int(pf.product.shape[0]), *[_ptr(a) for a in self.arrs])
         self.n = int(pf.product.shape[0])
 

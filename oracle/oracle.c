@@ -31,6 +31,14 @@
  *     age_l + node*node_step + t (equivalent to the paper's age-shift form by
  *     the cash-flow shift identity, Eq. (3.2)).
  *   - Node shock m multiplies every monthly q, capped at 1.
+ *   - Annuity payment patterns (the representative portfolio of Sec. 5.3):
+ *     a policy anniversary falls a months after node 0 (1 <= a <= 12) and
+ *     every 12 months after; with escalation rate e every payment at a time
+ *     T (months after node 0) carries the factor (1+e)^n(T), n(T) the number
+ *     of anniversaries in (0, T]; monthly policies pay amount/12 each month,
+ *     annual ones pay amount at each anniversary only.  The time-varying
+ *     annuity stream c_t of Eq. (3.1) is the level stream times this factor
+ *     at the payment time (t for f = 0, t + 1 for f = 1).
  *   - A policy whose remaining term at the node is <= 0 has expired: all its
  *     outputs are 0 and it is left out of totals.
  */
@@ -70,6 +78,9 @@ typedef struct {
     const int32_t *timing;   /* 0: annuity at f = 0, 1: at f = 1 */
     const double *amount;    /* annual annuity amount, or sum assured */
     const double *premium;   /* level monthly premium, paid in advance */
+    const double *escalation;/* annuity escalation rate per anniversary, or NULL */
+    const int32_t *anniv;    /* months from node 0 to the first anniversary, or NULL */
+    const int32_t *annual;   /* 1: one payment a year, at anniversaries; or NULL */
 } orc_portfolio;
 
 /* A contract in the paper's state-space form (Sec. 3.1, Sec. 4). */
@@ -242,6 +253,21 @@ static void add_stream(const orc_contract *k, const double *q, double v, double 
     for (int j = 0; j < n; ++j) acc[j] += vg * y[j];
 }
 
+/* Factor of the level annuity stream for a payment at time T (months after
+ * node 0): (1+e)^n(T) with n(T) the anniversaries in (0, T], times 12 at an
+ * anniversary and 0 elsewhere for annual payment. */
+static double payment_factor(const orc_portfolio *p, int i, int T)
+{
+    double e = p->escalation ? p->escalation[i] : 0.0;
+    int a = p->anniv ? p->anniv[i] : 12;
+    int annual = p->annual ? p->annual[i] : 0;
+    int n = T < a ? 0 : 1 + (T - a) / 12;
+    int at_anniv = T >= a && (T - a) % 12 == 0;
+    double lev = pow(1.0 + e, (double)n);
+    if (annual) return at_anniv ? 12.0 * lev : 0.0;
+    return lev;
+}
+
 /* Backward recurrence, Eq. (3.1), for one policy / node / scenario.  Writes
  * the reserve vector at t = 0 into r0 (n_states entries) and, if path is not
  * NULL, the state-0 reserve at t = 0..S into path[0..S]. */
@@ -260,7 +286,10 @@ static void recurrence_one(const orc_basis *b, const orc_portfolio *p, int i,
         step_q(b, p, i, age_shift, m, t, q);
         for (int j = 0; j < n; ++j) rn[j] = 0.0;
         add_stream(k, q, v, 0.0, k->c_prem, rn);
-        add_stream(k, q, v, k->f_ann, k->c_ann, rn);
+        double c_pay[ORC_MAX_STATES];
+        double fac = payment_factor(p, i, age_shift + t + (k->f_ann == 1.0 ? 1 : 0));
+        for (int j = 0; j < n; ++j) c_pay[j] = fac * k->c_ann[j];
+        add_stream(k, q, v, k->f_ann, c_pay, rn);
         add_stream(k, q, v, 1.0, k->c_ben, rn);
         orc_build_w(k->n_lives, k->life_model, q, 1.0, W1);
         matvec(W1, r, n, y);
@@ -288,6 +317,8 @@ static int validate(const orc_basis *b, const orc_portfolio *p)
         if (p->term[i] < 1 || p->term[i] > b->n_steps) return -1;
         if (p->age1[i] < 0 || p->age1[i] + p->term[i] > b->n_ages - 1) return -1;
         if (p->table1[i] < 0 || p->table1[i] >= b->n_tables) return -1;
+        if (p->anniv && (p->anniv[i] < 1 || p->anniv[i] > 12)) return -1;
+        if (p->escalation && !(p->escalation[i] >= 0.0)) return -1;
         int two = p->product[i] == O_JL_ANN || p->product[i] == O_REV_ANN ||
                   p->product[i] == O_LS_ANN;
         if (two) {
@@ -437,6 +468,7 @@ int orc_reserve_path_summation(const orc_basis *b, const orc_portfolio *p, int i
                 matmul(P, Wg, n, PW);
                 matvec(PW, streams[st], n, y);
                 double d = D * pow(v, gs[st]);
+                if (st == 1) d *= payment_factor(p, i, shift + u + (k.f_ann == 1.0 ? 1 : 0));
                 for (int j = 0; j < n; ++j) r[j] += d * y[j];
             }
             orc_build_w(k.n_lives, k.life_model, q, 1.0, Wg);

@@ -141,17 +141,23 @@ class Portfolio:
     timing: np.ndarray    # int32 [n] annuity timing (ADVANCE / ARREARS)
     amount: np.ndarray    # float64 [n] annual annuity amount or sum assured
     premium: np.ndarray   # float64 [n] level monthly premium, paid in advance
+    # Annuity payment pattern (None: monthly, level):
+    escalation: np.ndarray | None = None   # float64 [n] rate e, payments x (1+e) at each anniversary
+    anniv_m: np.ndarray | None = None      # int32 [n] months from node 0 to the first anniversary, 1..12
+    annual: np.ndarray | None = None       # int32 [n] 1: one payment of `amount` per anniversary
 
     @property
     def n(self) -> int:
         return int(self.product.shape[0])
 
     def subset(self, idx) -> "Portfolio":
-        return Portfolio(**{f.name: np.ascontiguousarray(getattr(self, f.name)[idx])
+        return Portfolio(**{f.name: (None if getattr(self, f.name) is None
+                                     else np.ascontiguousarray(getattr(self, f.name)[idx]))
                             for f in dataclasses.fields(self)})
 
     def scaled(self, factor: float) -> "Portfolio":
-        d = {f.name: getattr(self, f.name).copy() for f in dataclasses.fields(self)}
+        d = {f.name: (None if getattr(self, f.name) is None else getattr(self, f.name).copy())
+             for f in dataclasses.fields(self)}
         d["amount"] = d["amount"] * factor
         d["premium"] = d["premium"] * factor
         return Portfolio(**d)
@@ -413,3 +419,23 @@ def random_mlp_params(rng, n_feat: int = 17, k_in: int = 32, hidden: int = 256,
             "b2": rng.normal(0.0, bias_sd, hidden).astype(np.float32),
             "W3": rng.normal(0.0, 1.0 / np.sqrt(hidden), hidden).astype(np.float32),
             "b3": np.float32(rng.normal(0.0, bias_sd))}
+
+
+def with_payment_patterns(rng, pf: Portfolio, frac_escalating: float = 0.5,
+                          frac_annual: float = 0.5,
+                          rates=(0.03, 0.0425, 0.05)) -> Portfolio:
+    """Copy of pf whose annuities get random payment patterns: an anniversary
+    month U{1..12}, escalation at one of `rates` for frac_escalating of them
+    and annual payment for frac_annual; escalating or annual annuities carry
+    no premium (single-premium annuities)."""
+    n = pf.n
+    out = pf.subset(np.arange(n))
+    is_ann = np.isin(pf.product, (SL_ANN, JL_ANN, REV_ANN, LS_ANN))
+    esc = np.where(is_ann & (rng.uniform(size=n) < frac_escalating),
+                   np.asarray(rates)[rng.integers(0, len(rates), n)], 0.0)
+    annual = (is_ann & (rng.uniform(size=n) < frac_annual)).astype(np.int32)
+    out.escalation = esc.astype(np.float64)
+    out.anniv_m = rng.integers(1, 13, n).astype(np.int32)
+    out.annual = annual
+    out.premium = np.where((esc > 0) | (annual == 1), 0.0, pf.premium)
+    return out

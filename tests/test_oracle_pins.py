@@ -403,3 +403,95 @@ def test_scenario_window_matches_single_scenario_basis():
         b1 = Basis(q=w.basis.q, v=w.basis.v[:, s:s + 1, :])
         one = oracle.reserves(b1, w.portfolio)["r_all"]
         np.testing.assert_array_equal(part[:, :, s - 2, :], one[:, :, 0, :])
+
+
+# --------------------------------------------------------------------------
+# Annuity payment patterns (escalation on anniversaries, annual payment)
+# --------------------------------------------------------------------------
+def _pattern_pf(product, age1, term, amount, timing, esc, anniv, annual, age2=0):
+    pf = make_pf(product, age1, term, amount=amount, timing=timing, age2=age2)
+    n = pf.n
+    pf.escalation = np.asarray(np.broadcast_to(esc, (n,)), np.float64).copy()
+    pf.anniv_m = np.asarray(np.broadcast_to(anniv, (n,)), np.int32).copy()
+    pf.annual = np.asarray(np.broadcast_to(annual, (n,)), np.int32).copy()
+    return pf
+
+
+@pytest.mark.parametrize("a", [1, 5, 12])
+@pytest.mark.parametrize("S", [1, 11, 12, 13, 300, 599])
+def test_escalating_annuities_certain_closed_forms(a, S):
+    """Zero mortality: geometric sums over the anniversary years."""
+    v, e, theta = V_FLAT, 0.05, 1200.0
+    b = basis(np.zeros(N_AGES), np.full(600, v))
+    pf = _pattern_pf([SL_ANN] * 4, 700, S, theta, [ARREARS, ADVANCE, ARREARS, ADVANCE],
+                     e, a, [0, 0, 1, 1])
+    r = r0(b, pf)[:, 0]
+    g = 1.0 + e
+
+    def blocks(first, last):
+        # sum over months tau in [first, last] of g^(years passed) v^tau, by blocks
+        tot = 0.0
+        lo = first
+        while lo <= last:
+            k = 0 if lo < a else 1 + (lo - a) // 12           # anniversaries in (0, lo]
+            hi = min(last, a - 1 if lo < a else a + 12 * k - 1)
+            m = hi - lo + 1                                    # months at level g^k
+            tot += g ** k * v ** lo * (1 - v ** m) / (1 - v)
+            lo = hi + 1
+        return tot
+
+    monthly_arr = theta / 12 * blocks(1, S)
+    monthly_adv = theta / 12 * blocks(0, S - 1)
+    x = g * v ** 12
+    m_arr = 0 if S < a else (S - a) // 12 + 1                 # anniversaries in [1, S]
+    m_adv = 0 if S - 1 < a else (S - 1 - a) // 12 + 1         # anniversaries in [1, S-1]
+    annual_arr = theta * g * v ** a * (1 - x ** m_arr) / (1 - x)
+    annual_adv = theta * g * v ** a * (1 - x ** m_adv) / (1 - x)
+    np.testing.assert_allclose(r, [monthly_arr, monthly_adv, annual_arr, annual_adv],
+                               rtol=1e-13, atol=1e-12)
+
+
+def test_level_patterns_equal_the_plain_annuity_bitwise():
+    rng = np.random.default_rng(31)
+    w = synth.random_small(rng, n=60, n_steps=90, n_scen=2, n_nodes=2, shock=True)
+    pf = w.portfolio
+    lv = pf.subset(np.arange(pf.n))
+    lv.escalation = np.zeros(pf.n)
+    lv.anniv_m = rng.integers(1, 13, pf.n).astype(np.int32)
+    lv.annual = np.zeros(pf.n, np.int32)
+    a = oracle.reserves(w.basis, pf)["r_all"]
+    b = oracle.reserves(w.basis, lv)["r_all"]
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_payment_patterns_recurrence_equals_summation(seed):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=20, n_steps=60, n_scen=2, n_nodes=3, shock=True,
+                           products=(SL_ANN, JL_ANN, REV_ANN, LS_ANN))
+    b = w.basis
+    pf = synth.with_payment_patterns(rng, w.portfolio, 0.6, 0.5)
+    for node in range(3):
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=1, node_step=7)
+        for i in range(pf.n):
+            if int(pf.term_m[i]) - 7 * node <= 0:
+                continue
+            summ = oracle.reserve_path_summation(b, pf, i, node=node, scen=1, node_step=7)
+            scale = np.abs(summ).max() + 1e-300
+            np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=0,
+                                       atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("step", [12, 7])
+def test_payment_patterns_node_shift_equals_path(step):
+    """The payment factor depends on the time since node 0 only."""
+    q = gm(1.0)
+    b = Basis(q=np.atleast_2d(q), v=np.full((4, 1, 600), V_FLAT))
+    pf = _pattern_pf([SL_ANN, SL_ANN, JL_ANN, SL_ANN], [700, 650, 600, 720], [600, 500, 550, 400],
+                     [1200.0, 900.0, 600.0, 300.0], [ARREARS, ADVANCE, ARREARS, ARREARS],
+                     [0.05, 0.03, 0.0425, 0.0], [3, 12, 7, 1], [0, 1, 0, 1], age2=[0, 0, 700, 0])
+    path, off = oracle.reserve_paths(b, pf, node=0)
+    full = oracle.reserves(b, pf, node_step=step)
+    for k in range(4):
+        for i in range(pf.n):
+            assert full["r_all"][k, i, 0, 0] == path[off[i] + step * k]
