@@ -112,6 +112,23 @@ typedef struct {
  * may be NULL (all 0).  Requirements: 1 <= term_m <= n_steps of the basis,
  * age + term_m <= n_ages - 1 for every life used, valid table indices, finite
  * amount and premium >= 0.
+ *
+ * Annuity payment patterns (the representative annuity portfolio, Sec. 5.3),
+ * three optional arrays, each NULL for "none":
+ *   escalation[i]  yearly escalation rate e >= 0 (finite, at most 1);
+ *   anniv_m[i]     months from node 0 to the next policy anniversary, 1..12
+ *                  (NULL: 12); further anniversaries follow every 12 months;
+ *   annual[i]      1 = the amount is paid once a year, at each anniversary;
+ *                  0 = amount / 12 every month.
+ * A payment at time T (months after node 0; T = t for RR_ADVANCE and t + 1 for
+ * RR_ARREARS in step t) is the level payment times (1+e)^n(T), n(T) the number
+ * of anniversaries in (0, T]; an annual payer pays 12 level monthly payments
+ * times that factor at an anniversary and nothing in other months.  A policy
+ * with e > 0 or annual = 1 is "patterned": it must be an annuity (RR_SL_ANN,
+ * RR_JL_ANN, RR_REV_ANN, RR_LS_ANN) in payment, i.e. with premium 0; anything
+ * else is RR_EINVAL.  Level policies ignore anniv_m (values must still be in
+ * range).  Patterned policies are outside the surrogate's domain and take its
+ * exact fallback.
  */
 typedef struct {
     int32_t n;
@@ -125,6 +142,9 @@ typedef struct {
     const double *amount;
     const double *premium;   /* level monthly premium, paid in advance */
     int32_t mem_kind;        /* RR_HOST or RR_DEVICE, for all arrays */
+    const double *escalation;   /* or NULL: payment patterns, see above */
+    const int32_t *anniv_m;     /* or NULL */
+    const int32_t *annual;      /* or NULL */
 } rr_portfolio;
 
 /* One valuation run over nodes [node_begin, node_begin + node_count) and
@@ -148,8 +168,9 @@ typedef struct {
  *   path[sum_i (max(S_i,0) + 1)]      RR_OUT_PATH (node_count = scen_count = 1):
  *                                     policy i, step t at offset
  *                                     off_i + t, off_i = sum_{j<i}(max(S_j,0)+1),
- *                                     S_i = term_i - node*node_step_m; path_cap
- *                                     is its length in doubles.
+ *                                     S_i = term_i - node*node_step_m (a policy
+ *                                     expired at the node has one entry, 0);
+ *                                     path_cap is its length in doubles.
  *   stats[node_count][2]              RR_OUT_STATS: mean over scenarios and the
  *                                     ceil(tail*scen_count)-th largest total.
  */
@@ -182,9 +203,9 @@ int rr_check_portfolio(const rr_portfolio *p, int32_t n_steps, int32_t n_ages,
  * returns RR_ESTATE until a portfolio is uploaded again. */
 int rr_basis_upload(rr_ctx *ctx, const rr_basis *b);
 
-/* Copy, check, sort (by state model, remaining term descending, age) and tile
- * the portfolio (Sec. 3.8.2's per-policy inputs; the paper balances uneven
- * terms with a dynamic schedule, Sec. 5.1.1). */
+/* Copy, check, sort (by state model, payment pattern, remaining term
+ * descending, age) and tile the portfolio (Sec. 3.8.2's per-policy inputs; the
+ * paper balances uneven terms with a dynamic schedule, Sec. 5.1.1). */
 int rr_portfolio_upload(rr_ctx *ctx, const rr_portfolio *p);
 
 /* Length in doubles of the RR_OUT_PATH buffer for a node. */

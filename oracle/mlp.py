@@ -136,14 +136,28 @@ def scenario_features(v_node_scen, shock, zbar, E):
     return out
 
 
+def patterned(pf):
+    """Annuities with a payment pattern (escalation or annual payment): outside
+    the surrogate's domain, whose features describe level payments only."""
+    esc = getattr(pf, "escalation", None)
+    ann = getattr(pf, "annual", None)
+    out = np.zeros(pf.n, bool)
+    if esc is not None:
+        out |= np.asarray(esc) > 0.0
+    if ann is not None:
+        out |= np.asarray(ann) == 1
+    return out
+
+
 def product_signature(pf):
     """Per one-hot product: (table of life 1, table of life 2 or -1, annuity
     timing or -1) of the training policies, which must be unique; None for a
     product absent from training.  Features carry neither tables nor timing,
     so other combinations are outside the model's domain."""
     sig = []
+    level = ~patterned(pf)
     for code in SURROGATE_PRODUCTS:
-        sel = pf.product == code
+        sel = (pf.product == code) & level
         if not sel.any():
             sig.append(None)
             continue
@@ -160,7 +174,7 @@ def policy_features(pf, node, node_step, signature=None):
     """Raw policy features [n][9]: columns 0-7 and 16 of the feature vector
     (age, term, one-hot x4, log amount, premium rate, age2), and whether the
     policy's product (and, given a signature, its tables and timing) is in
-    the model's domain."""
+    the model's domain (level payments only)."""
     n = pf.n
     out = np.zeros((n, 9))
     shift = node * node_step
@@ -171,7 +185,7 @@ def policy_features(pf, node, node_step, signature=None):
     out[:, 6] = np.log(pf.amount)
     out[:, 7] = 12.0 * pf.premium / pf.amount
     out[:, 8] = np.where(pf.product == JL_ANN, (pf.age2_m + shift) / 12.0, 0.0)
-    supported = np.isin(pf.product, SURROGATE_PRODUCTS)
+    supported = np.isin(pf.product, SURROGATE_PRODUCTS) & ~patterned(pf)
     if signature is not None:
         for j, code in enumerate(SURROGATE_PRODUCTS):
             sel = pf.product == code

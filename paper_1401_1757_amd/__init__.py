@@ -57,7 +57,8 @@ class Portfolio(ctypes.Structure):
                 ("term_m", ctypes.c_void_p), ("table1", ctypes.c_void_p),
                 ("table2", ctypes.c_void_p), ("timing", ctypes.c_void_p),
                 ("amount", ctypes.c_void_p), ("premium", ctypes.c_void_p),
-                ("mem_kind", ctypes.c_int32)]
+                ("mem_kind", ctypes.c_int32), ("escalation", ctypes.c_void_p),
+                ("anniv_m", ctypes.c_void_p), ("annual", ctypes.c_void_p)]
 
 
 class Run(ctypes.Structure):
@@ -201,9 +202,14 @@ def portfolio_struct(pf, keep=None):
     arrs = [_np(pf.product, np.int32), _np(pf.age1_m, np.int32), _np(pf.age2_m, np.int32),
             _np(pf.term_m, np.int32), _np(pf.table1, np.int32), _np(pf.table2, np.int32),
             _np(pf.timing, np.int32), _np(pf.amount, np.float64), _np(pf.premium, np.float64)]
+    # Optional annuity payment patterns (None: level payments).
+    opt = [None if getattr(pf, name, None) is None else _np(getattr(pf, name), dt)
+           for name, dt in (("escalation", np.float64), ("anniv_m", np.int32), ("annual", np.int32))]
     if keep is not None:
         keep.extend(arrs)
-    return Portfolio(arrs[0].shape[0], *[a.ctypes.data for a in arrs], HOST)
+        keep.extend(opt)
+    return Portfolio(arrs[0].shape[0], *[a.ctypes.data for a in arrs], HOST,
+                     *[None if a is None else a.ctypes.data for a in opt])
 
 
 def check_portfolio(pf, n_steps, n_ages, n_tables):

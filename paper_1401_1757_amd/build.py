@@ -23,7 +23,7 @@ DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++
                 "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
 HOST_FLAGS = ["-x", "c++", "-O2", "-fPIC", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-Wall"]
 
-DEVICE_SOURCES = ["rr_kernels.hip", "rr_mlp.hip"]
+DEVICE_SOURCES = ["rr_kernels.hip", "rr_kernels_pat.hip", "rr_mlp.hip"]
 HOST_SOURCES = ["rr_host.cpp", "rr_surrogate.cpp"]
 
 

@@ -119,10 +119,14 @@ struct rr_ctx {
     int head_pad = 0;                     // largest ragged head of an item (steps)
     std::vector<int32_t> h_product, h_age1, h_age2, h_term, h_table1, h_table2, h_timing;
     std::vector<double> h_amount, h_premium;
+    std::vector<int32_t> h_patterned;     // 1: escalating or annual annuity
     std::vector<Tile> tiles_host;
     std::vector<int> slot_of_user;       // user index -> sorted slot
     DevBuf<int> age1, age2, term, qoff1, qoff2, uidx;
     DevBuf<double> coef;
+    DevBuf<double> pat_g;                 // [n_pad] (pattern tiles only)
+    DevBuf<int> pat_code;
+    bool has_pattern = false;
     DevBuf<Tile> tiles;
     int gen = 0;                          // bumps on every upload
 

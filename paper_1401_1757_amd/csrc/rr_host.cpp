@@ -125,8 +125,9 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
                                           const int32_t *age2, const int32_t *term,
                                           const int32_t *table1, const int32_t *table2,
                                           const int32_t *timing, const double *amount,
-                                          const double *premium, int n_steps, int n_ages,
-                                          int n_tables)
+                                          const double *premium, const double *escalation,
+                                          const int32_t *anniv, const int32_t *annual,
+                                          int n_steps, int n_ages, int n_tables)
 {
     char b[256];
     if (n < 0) return "portfolio: n must be >= 0";
@@ -176,6 +177,31 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
             snprintf(b, sizeof b, "portfolio: policy %d premium %g must be finite and >= 0", i, premium[i]);
             return b;
         }
+        const double e = escalation ? escalation[i] : 0.0;
+        if (!(e >= 0.0 && e <= 1.0)) {
+            snprintf(b, sizeof b, "portfolio: policy %d escalation %g outside [0, 1]", i, e);
+            return b;
+        }
+        if (anniv && (anniv[i] < 1 || anniv[i] > 12)) {
+            snprintf(b, sizeof b, "portfolio: policy %d anniv_m %d outside [1, 12]", i, anniv[i]);
+            return b;
+        }
+        if (annual && annual[i] != 0 && annual[i] != 1) {
+            snprintf(b, sizeof b, "portfolio: policy %d annual %d is not 0 or 1", i, annual[i]);
+            return b;
+        }
+        if (e > 0.0 || (annual && annual[i] == 1)) {
+            if (pr != RR_SL_ANN && pr != RR_JL_ANN && pr != RR_REV_ANN && pr != RR_LS_ANN) {
+                snprintf(b, sizeof b, "portfolio: policy %d has a payment pattern but product %d is not an annuity",
+                         i, pr);
+                return b;
+            }
+            if (premium && premium[i] != 0.0) {
+                snprintf(b, sizeof b, "portfolio: policy %d has a payment pattern and premium %g (must be 0)",
+                         i, premium[i]);
+                return b;
+            }
+        }
     }
     return "";
 }
@@ -197,7 +223,8 @@ extern "C" int rr_check_portfolio(const rr_portfolio *p, int32_t n_steps, int32_
     if (p->mem_kind != RR_HOST) { set_msg(msg, msg_len, "rr_check_portfolio needs host arrays"); return RR_EINVAL; }
     std::string s = check_portfolio_arrays(p->n, p->product, p->age1_m, p->age2_m, p->term_m,
                                            p->table1, p->table2, p->timing, p->amount,
-                                           p->premium, n_steps, n_ages, n_tables);
+                                           p->premium, p->escalation, p->anniv_m, p->annual,
+                                           n_steps, n_ages, n_tables);
     set_msg(msg, msg_len, s);
     return s.empty() ? RR_OK : RR_EINVAL;
 }
@@ -412,7 +439,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     HIPCHK(c, hipSetDevice(c->device));
     const size_t n = (size_t)p->n;
     std::vector<int32_t> product, age1, age2, term, table1, table2, timing;
-    std::vector<double> amount, premium;
+    std::vector<double> amount, premium, escalation;
+    std::vector<int32_t> anniv, annual;
     int rc;
     if (n > 0 && (!p->product || !p->age1_m || !p->term_m || !p->table1 || !p->amount))
         return fail(c, RR_EINVAL, "portfolio: product, age1_m, term_m, table1 and amount must not be NULL");
@@ -429,6 +457,12 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     else timing.assign(n, RR_ARREARS);
     if (p->premium) { if ((rc = fetch(c, p->premium, n, p->mem_kind, premium))) return rc; }
     else premium.assign(n, 0.0);
+    if (p->escalation) { if ((rc = fetch(c, p->escalation, n, p->mem_kind, escalation))) return rc; }
+    else escalation.assign(n, 0.0);
+    if (p->anniv_m) { if ((rc = fetch(c, p->anniv_m, n, p->mem_kind, anniv))) return rc; }
+    else anniv.assign(n, 12);
+    if (p->annual) { if ((rc = fetch(c, p->annual, n, p->mem_kind, annual))) return rc; }
+    else annual.assign(n, 0);
     bool any_two = false;
     for (size_t i = 0; i < n; ++i) any_two |= is_two_life(product[i]);
     std::string s = check_portfolio_arrays(p->n, product.data(), age1.data(),
@@ -436,6 +470,7 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                                            term.data(), table1.data(),
                                            (p->table2 || !any_two) ? table2.data() : nullptr,
                                            timing.data(), amount.data(), premium.data(),
+                                           escalation.data(), anniv.data(), annual.data(),
                                            c->n_steps, c->n_ages, c->n_tables);
     if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
 
@@ -444,7 +479,11 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     c->tuned.clear();
     c->has_pf = false;
 
-    // Sort: state model, remaining term descending, age (stable on index).
+    // Sort: state model, payment pattern, remaining term descending, age
+    // (stable on index).
+    std::vector<int32_t> patterned(n, 0);
+    for (size_t i = 0; i < n; ++i) patterned[i] = (escalation[i] > 0.0 || annual[i] == 1) ? 1 : 0;
+    auto group_of = [&](int u) { return 2 * kind_of(product[u]) + patterned[u]; };
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     // Within a model, remaining terms are bucketed (width term_bucket months,
@@ -453,7 +492,7 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     // LDS bank conflicts) at the price of at most term_bucket ragged steps.
     const int tb = std::max(1, c->opt_term_bucket);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        int ka = kind_of(product[a]), kb = kind_of(product[b]);
+        int ka = group_of(a), kb = group_of(b);
         if (ka != kb) return ka < kb;
         const int ba = (term[a] - 1) / tb, bb = (term[b] - 1) / tb;
         if (ba != bb) return ba > bb;
@@ -468,12 +507,13 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     size_t i0 = 0;
     int max_age = 1;
     while (i0 < n) {
-        int kind = kind_of(product[order[i0]]);
+        const int group = group_of(order[i0]);
         size_t i1 = i0;
-        while (i1 < n && kind_of(product[order[i1]]) == kind) ++i1;
+        while (i1 < n && group_of(order[i1]) == group) ++i1;
         for (size_t a = i0; a < i1; a += TILE) {
             Tile T;
-            T.kind = kind;
+            T.kind = group / 2;
+            T.pat = group % 2;
             T.first = (int)s_uidx.size();
             T.smax = 0;
             T.smin = 1 << 30;
@@ -511,7 +551,10 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     int head_pad = 0;
     for (size_t t0 = 0; t0 < tiles.size(); ++t0) {
         int smax = 0, smin = 1 << 30;
-        for (size_t t1 = t0; t1 < tiles.size() && t1 < t0 + 4 && tiles[t1].kind == tiles[t0].kind; ++t1) {
+        const size_t span = tiles[t0].pat ? 1 : 4;
+        for (size_t t1 = t0; t1 < tiles.size() && t1 < t0 + span && tiles[t1].kind == tiles[t0].kind &&
+                             tiles[t1].pat == tiles[t0].pat;
+             ++t1) {
             smax = std::max(smax, tiles[t1].smax);
             smin = std::min(smin, tiles[t1].smin);
             head_pad = std::max(head_pad, smax - smin);
@@ -576,6 +619,21 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     if ((rc = upload_vec(c, c->uidx, s_uidx))) return rc;
     if ((rc = upload_vec(c, c->coef, coef))) return rc;
     if ((rc = upload_vec(c, c->tiles, tiles))) return rc;
+    // Payment patterns of the slots (level slots: g = 1, anniversary 12).
+    c->has_pattern = false;
+    for (const Tile &T : tiles) c->has_pattern |= T.pat != 0;
+    if (c->has_pattern) {
+        std::vector<double> pg(n_pad, 1.0);
+        std::vector<int> pc(n_pad, 12);
+        for (int j = 0; j < n_pad; ++j) {
+            const int u = s_uidx[j];
+            if (u < 0) continue;
+            pg[j] = 1.0 + escalation[u];
+            pc[j] = anniv[u] | (annual[u] ? PAT_ANNUAL : 0) | (timing[u] == RR_ARREARS ? PAT_ARREARS : 0);
+        }
+        if ((rc = upload_vec(c, c->pat_g, pg))) return rc;
+        if ((rc = upload_vec(c, c->pat_code, pc))) return rc;
+    }
     c->n_user = (int)n;
     c->n_pad = n_pad;
     c->n_tiles = (int)tiles.size();
@@ -589,6 +647,7 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     c->h_timing.swap(timing);
     c->h_amount.swap(amount);
     c->h_premium.swap(premium);
+    c->h_patterned.swap(patterned);
     c->slot_of_user.assign(n, -1);
     for (int j = 0; j < n_pad; ++j)
         if (s_uidx[j] >= 0) c->slot_of_user[s_uidx[j]] = j;
@@ -627,9 +686,12 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
         std::vector<std::pair<int, int>> groups;   // (first tile, count)
         for (int t = 0; t < c->n_tiles;) {
             const int kind = c->tiles_host[t].kind;
-            const int jmax = (kind == KIND_SINGLE || kind == KIND_JOINT) ? J : 1;
+            const int pat = c->tiles_host[t].pat;
+            const int jmax = ((kind == KIND_SINGLE || kind == KIND_JOINT) && !pat) ? J : 1;
             int count = 1;
-            while (count < jmax && t + count < c->n_tiles && c->tiles_host[t + count].kind == kind) ++count;
+            while (count < jmax && t + count < c->n_tiles && c->tiles_host[t + count].kind == kind &&
+                   c->tiles_host[t + count].pat == pat)
+                ++count;
             groups.push_back({t, count});
             t += count;
         }
@@ -641,7 +703,8 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
                 for (int j = 1; j < g.second; ++j) smax = std::max(smax, c->tiles_host[g.first + j].smax);
                 const long long steps = std::max(smax - shift, 0);
                 const long long cost =
-                    steps * g.second * (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind)) + 64;
+                    steps * g.second *
+                        (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind) + (T.pat ? 16 : 0)) + 64;
                 for (int b = 0; b < nsb; ++b) {
                     const int qid = queues > 1 ? (int)(((long long)nr * nsb + b) % queues) : 0;
                     qs[qid].push_back({cost, Item{nr, g.first, b * K, g.second}});
@@ -696,6 +759,8 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.qoff2 = c->qoff2.p;
     P.uidx = c->uidx.p;
     P.coef = c->coef.p;
+    P.pat_g = c->has_pattern ? c->pat_g.p : nullptr;
+    P.pat_code = c->has_pattern ? c->pat_code.p : nullptr;
     P.n_pad = c->n_pad;
     P.n_user = c->n_user;
     P.tiles = c->tiles.p;

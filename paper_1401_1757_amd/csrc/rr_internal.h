@@ -39,7 +39,15 @@ struct Tile {
     int first;    // first sorted slot (multiple of TILE)
     int smax;     // largest remaining term at node 0 among valid lanes
     int smin;     // smallest remaining term at node 0 among valid lanes
+    int pat;      // 1: annuities with a payment pattern (escalation or annual
+                  // payment; premium 0), run one tile per item
 };
+
+// Payment pattern of a slot in a pattern tile: the code packs the months to
+// the first anniversary after node 0 (bits 0-7, 1..12), annual payment (bit 8)
+// and the payment offset f (bit 9: 1 for arrears, payment at t + 1).
+constexpr int PAT_ANNUAL = 1 << 8;
+constexpr int PAT_ARREARS = 1 << 9;
 
 struct Item {
     int node_rel;  // node - node_begin
@@ -67,6 +75,8 @@ struct RecParams {
     const int *qoff2;
     const int *uidx;          // upload index, -1 for padding
     const double *coef;       // [N_COEF][n_pad]
+    const double *pat_g;      // [n_pad] 1 + escalation rate (pattern tiles), or null
+    const int *pat_code;      // [n_pad] anniversary / annual / timing code, or null
     int n_pad;
     int n_user;
     const Tile *tiles;

@@ -126,6 +126,7 @@ struct Policies {
     int n;
     const int *product, *age1, *age2, *term, *table1, *table2, *timing;
     const double *amount, *premium;
+    const int *patterned;   // 1: annuity with a payment pattern (outside the domain), or null
 };
 // Per (node, policy): raw features [node][n][9] (features 0-7 and 16),
 // standardised bfloat16 features 0-7 [node][n][8] and 16 [node][n],

@@ -603,7 +603,7 @@ __global__ void k_policy_features(Policies p, int node_begin, int node_count, in
     if (raw) {
         for (int j = 0; j < 9; ++j) raw[id * 9 + j] = x[j];
     }
-    bool supported = slot >= 0;
+    bool supported = slot >= 0 && !(p.patterned && p.patterned[i]);
     if (supported && nm.signature) {
         const int *sg = nm.signature + 3 * slot;
         supported = sg[0] >= 0 && p.table1[i] == sg[0] && (sg[1] < 0 || p.table2[i] == sg[1]) &&

@@ -1,0 +1,704 @@
+// Device templates of the reserve recurrence kernel, instantiated by
+// rr_kernels.hip (level portfolios) and rr_kernels_pat.hip (portfolios
+// with annuity payment patterns).
+//
+// Device kernels of the reserve recurrence (gfx950, FP64 vector ALU).
+//
+// One lane per policy, K scenarios per lane: lane i of a wavefront walks its
+// policy's steps backward (Sec. 3.8.2) carrying K reserve chains in
+// registers.  The per-policy work of a step (gather of the monthly q from the
+// LDS copy of the mortality table, W entries, W c) is shared by the K
+// chains; the scenario's one-step discount factor v_t is wavefront-uniform
+// and read with scalar loads from the month-major curve array.  Work items
+// (node, tile of 64 policies, block of K scenarios) are taken from per-XCD
+// queues, longest first, by a persistent grid.
+#pragma once
+
+#include "rr_internal.h"
+
+namespace rr {
+
+
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// DPP lane permutation of a double (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes with a fixed association, as VALU work only: within
+// each row of 16 lanes, pairs, quads, half-rows and rows are added through
+// DPP permutations (every lane of a row ends with the same row sum, bit for
+// bit, since each addition sees the same two operands); the four row sums are
+// then added in lane order.  The result is wavefront-uniform and identical on
+// every call with the same inputs.
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x += dpp_f64<0xb1>(x);    // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4e>(x);    // quad_perm [2,3,0,1]
+    x += dpp_f64<0x141>(x);   // row_half_mirror
+    x += dpp_f64<0x140>(x);   // row_mirror
+    const int lo0 = __builtin_amdgcn_readlane(__double2loint(x), 0);
+    const int hi0 = __builtin_amdgcn_readlane(__double2hiint(x), 0);
+    const int lo1 = __builtin_amdgcn_readlane(__double2loint(x), 16);
+    const int hi1 = __builtin_amdgcn_readlane(__double2hiint(x), 16);
+    const int lo2 = __builtin_amdgcn_readlane(__double2loint(x), 32);
+    const int hi2 = __builtin_amdgcn_readlane(__double2hiint(x), 32);
+    const int lo3 = __builtin_amdgcn_readlane(__double2loint(x), 48);
+    const int hi3 = __builtin_amdgcn_readlane(__double2hiint(x), 48);
+    return (__hiloint2double(hi0, lo0) + __hiloint2double(hi1, lo1)) +
+           (__hiloint2double(hi2, lo2) + __hiloint2double(hi3, lo3));
+}
+
+template <bool LDSQ>
+__device__ __forceinline__ double qload(const double *__restrict__ lds, const double *__restrict__ glob,
+                                        int idx)
+{
+    if constexpr (LDSQ) return lds[idx];
+    else return glob[idx];
+}
+
+// Store the item's results: per-lane r0 slots and per-scenario wave totals.
+template <int K>
+__device__ __forceinline__ void store_results(const RecParams &P, int node_rel, int tile, int sb,
+                                              int lane, int uid, bool live, const double (&r0)[K],
+                                              const double (&r1)[K], const double (&r2)[K],
+                                              bool has1, bool has2)
+{
+    if (P.r0 != nullptr && uid >= 0) {
+        double *o = P.r0 + (((size_t)node_rel * P.n_user + uid) * P.scen_count + sb) * P.r0_states;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (sb + k < P.scen_count) {
+                if (P.r0_states == 1) {
+                    o[k] = live ? r0[k] : 0.0;
+                } else {
+                    o[4 * k + 0] = live ? r0[k] : 0.0;
+                    o[4 * k + 1] = (live && has1) ? r1[k] : 0.0;
+                    o[4 * k + 2] = (live && has2) ? r2[k] : 0.0;
+                    o[4 * k + 3] = 0.0;
+                }
+            }
+        }
+    }
+    if (P.partial != nullptr) {
+        double *pt = P.partial + ((size_t)node_rel * P.n_tiles + tile) * P.scen_count + sb;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double s = wave_sum(live ? r0[k] : 0.0);
+            if (lane == 0 && sb + k < P.scen_count) pt[k] = s;
+        }
+    }
+}
+
+// The all-lanes-active phase runs in blocks of U steps.  Every load of a block
+// (q from LDS, v with scalar loads) is issued one block ahead, right after the
+// wait for the current block, so its latency overlaps the current block's
+// arithmetic: scalar loads complete out of order, so each wait is a wait for
+// all of them, and the issue point has to come after that wait.  U*K <= 16
+// curve values per block (double-buffered: 64 scalar registers); K = 32 uses
+// single blocks of one step.  With J policies per lane a block carries
+// U*K*J*2 <= 128 FMAs, so one scalar load feeds J times more arithmetic and a
+// block outlasts a scalar-cache miss.
+template <int K, int J = 1>
+struct StepBlock {
+    static constexpr int U0 = K >= 16 ? 1 : (16 / K > 8 ? 8 : 16 / K);
+    static constexpr int U1 = (64 / (K * J)) < 1 ? 1 : 64 / (K * J);
+    static constexpr int U2 = (8 / J) < 1 ? 1 : 8 / J;   // <= 8 policy-steps of table values per block
+    static constexpr int U01 = U0 < U1 ? U0 : U1;
+    static constexpr int U = U01 < U2 ? U01 : U2;
+    static constexpr bool PIPE = K <= 16;
+};
+
+// Make the arithmetic that follows wait here for the loads of the block in
+// flight (the wait is inserted before this point because it reads them).
+__device__ __forceinline__ void wait_for(double q, double v)
+{
+    asm volatile("" ::"v"(q), "s"(v));
+}
+
+// Survival probability over one step with the node's mortality shock m
+// applied to the death probability (capped at 1).
+template <bool LDSQ, bool SHOCK>
+__device__ __forceinline__ double p_eff(const double *__restrict__ lq, const double *__restrict__ gq,
+                                        int idx, double m)
+{
+    double p = qload<LDSQ>(lq, gq, idx);
+    if constexpr (SHOCK) p = 1.0 - fmin(1.0, m * (1.0 - p));
+    return p;
+}
+
+// Per-lane state of one policy in a scalar-reserve item.
+struct ScalarLane {
+    int S;        // remaining term at the node (<= 0: expired or padding)
+    int qa, qb;   // LDS indices of the q of life 1 / life 2 at t = 0
+    double a0, a1mb1, b1, a1;
+    double rS;    // boundary reserve (state 0)
+};
+
+// Payment pattern of one lane (escalating or annually paid annuity in
+// payment, Sec. 5.3): every cash flow of such a policy is its level value
+// times F(T), T = base + t the payment time in months after node 0, with
+// F(T) = (1+e)^n(T), n(T) = number of anniversaries in (0, T] (anniversaries
+// at a, a + 12, ...), and for annual payment 12 F(T) at an anniversary and 0
+// elsewhere.  Steps are taken in decreasing t, one at a time, so n falls by
+// at most one per step and the level follows by one multiplication by
+// 1/(1+e) at each anniversary crossed.
+struct PatLane {
+    int base;      // node shift + payment offset (1 for arrears)
+    int a;         // months from node 0 to the first anniversary, 1..12
+    int annual;
+    double ginv;   // 1 / (1 + e)
+    double lev;    // (1 + e)^n at the last step taken
+    int n;         // n(T) at the last step taken
+};
+
+// n(T) for T >= 0: floor((T + 12 - a) / 12).
+__device__ __forceinline__ unsigned pat_count(int T, int a) { return (unsigned)(T + 12 - a) / 12u; }
+
+// Lane state for a walk that starts at step t0 (its first call is for t0).
+__device__ __forceinline__ PatLane pat_init(const RecParams &P, int slot, int shift, int t0)
+{
+    PatLane pl;
+    const int code = P.pat_code[slot];
+    const double g = P.pat_g[slot];
+    pl.a = code & 255;
+    pl.annual = code & PAT_ANNUAL;
+    pl.base = shift + ((code & PAT_ARREARS) ? 1 : 0);
+    pl.ginv = 1.0 / g;
+    const int n0 = (int)pat_count(max(pl.base + t0, 0), pl.a);
+    double lev = 1.0, x = g;   // g^n0 by repeated squaring
+    for (int k = n0; k > 0; k >>= 1) {
+        if (k & 1) lev *= x;
+        x *= x;
+    }
+    pl.lev = lev;
+    pl.n = n0;
+    return pl;
+}
+
+// F(base + t), advancing the lane's state to step t.
+__device__ __forceinline__ double pat_factor(PatLane &pl, int t)
+{
+    const int T = pl.base + t;
+    const unsigned w = (unsigned)(T + 12 - pl.a);
+    const int n = (int)(w / 12u);
+    pl.lev = n < pl.n ? pl.lev * pl.ginv : pl.lev;
+    pl.n = n;
+    const bool at = n > 0 && w == 12u * (unsigned)n;
+    return pl.annual ? (at ? 12.0 * pl.lev : 0.0) : pl.lev;
+}
+
+// Scalar-reserve models: one life (annuity, term assurance, endowment,
+// endowment assurance; Sec. 4.1 with the zero-reserve states removed) and the
+// joint-life annuity (Sec. 4.2.1 b: only state 00 carries a reserve, and its
+// one-step survival probability is px * py).  Per step and scenario:
+//   r <- a0 + v * (p * r + c),  c = p * a1 + q * b1 = b1 + p * (a1 - b1).
+// Each lane carries J policies (one per tile of the item) x K scenarios.
+// ESC: annuities with a payment pattern (J = 1; no death benefit), whose a0
+// and a1 at step t are the level amounts times F of the payment time.
+template <int K, int J, bool LDSQ, bool TWO, bool SHOCK, bool ESC>
+__device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
+                                             const double *__restrict__ gq,
+                                             const double *__restrict__ vb, int stride,
+                                             const ScalarLane (&L)[J], PatLane (&PL)[J], double m,
+                                             int smax, int smin, double (&r)[J][K], double *path)
+{
+    // x1, x2: one-step survival probabilities from the staged table.
+    auto coeffs = [&](int j, int t, double x1, double x2, double &p, double &c, double &a0) {
+        const ScalarLane &l = L[j];
+        if constexpr (SHOCK) {
+            x1 = 1.0 - fmin(1.0, m * (1.0 - x1));
+            if constexpr (TWO) x2 = 1.0 - fmin(1.0, m * (1.0 - x2));
+        }
+        p = TWO ? x1 * x2 : x1;
+        if constexpr (ESC) {
+            const double f = pat_factor(PL[j], t);
+            c = p * (f * l.a1);
+            a0 = f * l.a0;
+        } else {
+            c = TWO ? p * l.a1 : fma(p, l.a1mb1, l.b1);
+            a0 = l.a0;
+        }
+    };
+    auto apply = [&](double (&rj)[K], const double (&vk)[K], double p, double c, double a0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) rj[k] = fma(vk[k], fma(p, rj[k], c), a0);
+    };
+    constexpr int U = StepBlock<K, J>::U;
+    auto load_block = [&](int tb, const double *vtb, double (&vk)[U][K], double (&q1)[U][J],
+                          double (&q2)[U][J]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) vk[u][k] = vtb[k - u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                q1[u][j] = qload<LDSQ>(lq, gq, L[j].qa + tb - u);
+                q2[u][j] = TWO ? qload<LDSQ>(lq, gq, L[j].qb + tb - u) : 0.0;
+            }
+    };
+    // One block of U steps, every policy of the block active (t < smin).
+    auto run_block = [&](int tb, const double (&vk)[U][K], const double (&q1)[U][J],
+                         const double (&q2)[U][J]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                double p, c, a0;
+                coeffs(j, tb - u, q1[u][j], q2[u][j], p, c, a0);
+                apply(r[j], vk[u], p, c, a0);
+            }
+            if constexpr (K == 1 && J == 1) {
+                if (path != nullptr) path[tb - u] = r[0][0];
+            }
+        }
+    };
+    // Ragged head of the item (t >= smin): a policy that has not started
+    // (t >= S) takes the step with p = 0, c = 0, a0 = r_S, which leaves its
+    // reserve at the boundary value exactly (v * 0 + r_S = r_S), so the loop
+    // needs no branches.  Its table reads land in the staged table's padding.
+    int t = smax - 1;
+    for (; t >= smin; --t) {
+        const double *vt = vb + (ptrdiff_t)t * stride;
+        double vk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) vk[k] = vt[k];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            double p, c, a0;
+            coeffs(j, t, qload<LDSQ>(lq, gq, L[j].qa + t),
+                   TWO ? qload<LDSQ>(lq, gq, L[j].qb + t) : 0.0, p, c, a0);
+            const bool on = t < L[j].S;
+            p = on ? p : 0.0;
+            c = on ? c : 0.0;
+            apply(r[j], vk, p, c, on ? a0 : L[j].rS);
+        }
+        if constexpr (K == 1 && J == 1) {
+            if (path != nullptr && t < L[0].S) path[t] = r[0][0];
+        }
+    }
+    if constexpr (StepBlock<K, J>::PIPE) {
+        // Pairs of blocks through two named buffers (ping-pong): no register
+        // copy of a block in flight and no branch between a prefetch and its
+        // use, so the compiler keeps every load at its issue point.  The
+        // prefetch after the last pair is clamped in bounds and unused.
+        const int npair = ((t + 1) / U) / 2;
+        if (npair > 0) {
+            double av[U][K], aq1[U][J], aq2[U][J], bv[U][K], bq1[U][J], bq2[U][J];
+            load_block(t, vb + (ptrdiff_t)t * stride, av, aq1, aq2);
+            for (int i = 0; i < npair; ++i) {
+                wait_for(aq1[0][0], av[0][0]);
+                __builtin_amdgcn_sched_barrier(0);
+                load_block(t - U, vb + (ptrdiff_t)(t - U) * stride, bv, bq1, bq2);
+                __builtin_amdgcn_sched_barrier(0);
+                run_block(t, av, aq1, aq2);
+                wait_for(bq1[0][0], bv[0][0]);
+                const int tl = max(t - 2 * U, U - 1);
+                __builtin_amdgcn_sched_barrier(0);
+                load_block(tl, vb + (ptrdiff_t)tl * stride, av, aq1, aq2);
+                __builtin_amdgcn_sched_barrier(0);
+                run_block(t - U, bv, bq1, bq2);
+                t -= 2 * U;
+            }
+        }
+    }
+    for (; t >= U - 1; t -= U) {
+        double vk[U][K], q1[U][J], q2[U][J];
+        load_block(t, vb + (ptrdiff_t)t * stride, vk, q1, q2);
+        run_block(t, vk, q1, q2);
+    }
+    for (; t >= 0; --t) {   // fewer than U steps left
+        const double *vt = vb + (ptrdiff_t)t * stride;
+        double vk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) vk[k] = vt[k];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            double p, c, a0;
+            coeffs(j, t, qload<LDSQ>(lq, gq, L[j].qa + t),
+                   TWO ? qload<LDSQ>(lq, gq, L[j].qb + t) : 0.0, p, c, a0);
+            apply(r[j], vk, p, c, a0);
+        }
+        if constexpr (K == 1 && J == 1) {
+            if (path != nullptr) path[t] = r[0][0];
+        }
+    }
+}
+
+// An item of `count` (<= J) consecutive tiles of one scalar model and a block
+// of K scenarios: lane l carries slot first + 64 j + l of every tile j.
+template <int K, int J, bool LDSQ, bool TWO, bool ESC>
+__device__ __forceinline__ void run_scalar(const RecParams &P, const double *__restrict__ lq,
+                                           const double *__restrict__ vcurves, int node_rel,
+                                           int tile, int count, const Tile &T0, int item_smax,
+                                           int item_smin, int sb, int lane)
+{
+    const int node = P.node_begin + node_rel;
+    const int shift = node * P.node_step;
+    const int smax = item_smax - shift;
+    const int smin = max(item_smin - shift, 0);
+    const double m = P.shock[node];
+    ScalarLane L[J];
+    PatLane PL[J];
+    int uid[J];
+    double r[J][K];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int slot = T0.first + j * TILE + lane;   // tiles of an item are consecutive
+        if (j < count) {
+            L[j].S = P.term[slot] - shift;
+            uid[j] = P.uidx[slot];
+            L[j].a0 = P.coef[0 * P.n_pad + slot];
+            L[j].a1 = P.coef[1 * P.n_pad + slot];
+            L[j].b1 = P.coef[2 * P.n_pad + slot];
+            L[j].a1mb1 = L[j].a1 - L[j].b1;
+            L[j].qa = P.qoff1[slot] + P.age1[slot] + shift;
+            L[j].qb = TWO ? P.qoff2[slot] + P.age2[slot] + shift : 0;
+            L[j].rS = P.coef[3 * P.n_pad + slot];
+            if constexpr (ESC) PL[j] = pat_init(P, slot, shift, smax - 1);
+#pragma unroll
+            for (int k = 0; k < K; ++k) r[j][k] = L[j].rS;
+        } else {   // missing tile of a short item: an always-inactive lane
+            L[j].S = -1;
+            uid[j] = -1;
+            L[j].a0 = L[j].a1 = L[j].b1 = L[j].a1mb1 = L[j].rS = 0.0;
+            L[j].qa = shift;
+            L[j].qb = shift;
+            if constexpr (ESC) PL[j] = PatLane{0, 12, 0, 1.0, 1.0, 0};
+#pragma unroll
+            for (int k = 0; k < K; ++k) r[j][k] = 0.0;
+        }
+    }
+    const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
+    double *path = nullptr;
+    if constexpr (K == 1 && J == 1) {
+        if (P.path != nullptr && uid[0] >= 0) {
+            if (L[0].S > 0) {
+                path = P.path + P.path_off[uid[0]];
+                path[L[0].S] = r[0][0];
+            } else {
+                P.path[P.path_off[uid[0]]] = 0.0;   // expired: its one entry is 0
+            }
+        }
+    }
+    if (m == 1.0)
+        scalar_steps<K, J, LDSQ, TWO, false, ESC>(lq, P.q, vb, P.scen_pad, L, PL, m, smax, smin, r,
+                                                  path);
+    else
+        scalar_steps<K, J, LDSQ, TWO, true, ESC>(lq, P.q, vb, P.scen_pad, L, PL, m, smax, smin, r,
+                                                 path);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (j < count) {
+            const bool live = uid[j] >= 0 && L[j].S > 0;
+            store_results<K>(P, node_rel, tile + j, sb, lane, uid[j], live, r[j], r[j], r[j], false,
+                             false);
+        }
+    }
+}
+
+// Two-life annuities with a vector reserve (Sec. 4.2.1 a, c).  States 00, 01,
+// 10 of the 4-state model (state 11 is a zero-reserve state); REV keeps 00
+// and 10 only (01 is a zero-reserve state for a reversion to life 2).  With
+// y = c_arrears + r' (per state) and W row 00 = (px py, px qy, qx py, .),
+// row 01 = (., px, ., qx), row 10 = (., ., py, qy):
+//   r00 <- c00_adv + v (px py y00 + px qy y01 + qx py y10)
+//   r01 <- c01_adv + v px y01
+//   r10 <- c10_adv + v py y10
+//
+// ESC: an annuity with a payment pattern (premium 0): every coefficient at
+// step t is its level value times F of the payment time.
+template <int K, bool LDSQ, bool LAST, bool SHOCK, bool ESC>
+__device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
+                                             const double *__restrict__ gq,
+                                             const double *__restrict__ vb, int stride, int qa,
+                                             int qb, double m, const double (&cf)[6], PatLane &pl,
+                                             int S, int smax, int smin, double (&r0)[K],
+                                             double (&r1)[K], double (&r2)[K], double *path)
+{
+    auto apply = [&](const double (&vk)[K], double px, double py, int t) {
+        double f = 1.0;
+        if constexpr (ESC) f = pat_factor(pl, t);
+        const double c00a = ESC ? f * cf[0] : cf[0], c00r = ESC ? f * cf[1] : cf[1];
+        const double c01a = ESC ? f * cf[2] : cf[2], c01r = ESC ? f * cf[3] : cf[3];
+        const double c10a = ESC ? f * cf[4] : cf[4], c10r = ESC ? f * cf[5] : cf[5];
+        const double qx = 1.0 - px, qy = 1.0 - py;
+        const double w00 = px * py, w10 = qx * py;
+        const double w01 = px * qy;
+        double cw0 = fma(w10, c10r, w00 * c00r);
+        if constexpr (LAST) cw0 = fma(w01, c01r, cw0);
+        const double cw1 = px * c01r;
+        const double cw2 = py * c10r;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double a = fma(w00, r0[k], cw0);
+            a = fma(w10, r2[k], a);
+            if constexpr (LAST) a = fma(w01, r1[k], a);
+            const double c = fma(py, r2[k], cw2);
+            if constexpr (LAST) {
+                const double b = fma(px, r1[k], cw1);
+                r1[k] = fma(vk[k], b, c01a);
+            }
+            r0[k] = fma(vk[k], a, c00a);
+            r2[k] = fma(vk[k], c, c10a);
+        }
+        if constexpr (K == 1) {
+            if (path != nullptr) path[t] = r0[0];
+        }
+    };
+    int t = smax - 1;
+    const double *vt = vb + (ptrdiff_t)t * stride;
+    for (; t >= smin; --t, vt -= stride) {
+        double vk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) vk[k] = vt[k];
+        if (t < S)
+            apply(vk, p_eff<LDSQ, SHOCK>(lq, gq, qa + t, m), p_eff<LDSQ, SHOCK>(lq, gq, qb + t, m), t);
+    }
+    constexpr int U = StepBlock<K>::U;
+    auto load_block = [&](int tb, const double *vtb, double (&vk)[U][K], double (&qx)[U],
+                          double (&qy)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) vk[u][k] = vtb[k - u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            qx[u] = qload<LDSQ>(lq, gq, qa + tb - u);
+            qy[u] = qload<LDSQ>(lq, gq, qb + tb - u);
+        }
+    };
+    auto run_block = [&](int tb, const double (&vk)[U][K], const double (&qx)[U],
+                         const double (&qy)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double x = qx[u], y = qy[u];
+            if constexpr (SHOCK) {
+                x = 1.0 - fmin(1.0, m * (1.0 - x));
+                y = 1.0 - fmin(1.0, m * (1.0 - y));
+            }
+            apply(vk[u], x, y, tb - u);
+        }
+    };
+    if constexpr (StepBlock<K>::PIPE) {
+        {
+            const int npair = ((t + 1) / U) / 2;
+            if (npair > 0) {
+                double av[U][K], aqx[U], aqy[U], bv[U][K], bqx[U], bqy[U];
+                load_block(t, vt, av, aqx, aqy);
+                for (int i = 0; i < npair; ++i) {
+                    wait_for(aqx[0], av[0][0]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_block(t - U, vb + (ptrdiff_t)(t - U) * stride, bv, bqx, bqy);
+                    __builtin_amdgcn_sched_barrier(0);
+                    run_block(t, av, aqx, aqy);
+                    wait_for(bqx[0], bv[0][0]);
+                    const int tl = max(t - 2 * U, U - 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_block(tl, vb + (ptrdiff_t)tl * stride, av, aqx, aqy);
+                    __builtin_amdgcn_sched_barrier(0);
+                    run_block(t - U, bv, bqx, bqy);
+                    t -= 2 * U;
+                }
+            }
+            vt = vb + (ptrdiff_t)t * stride;
+        }
+    }
+    {
+        for (; t >= U - 1; t -= U, vt -= U * stride) {
+            double vk[U][K], qx[U], qy[U];
+            load_block(t, vt, vk, qx, qy);
+            run_block(t, vk, qx, qy);
+        }
+    }
+    for (; t >= 0; --t, vt -= stride) {
+        double vk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) vk[k] = vt[k];
+        apply(vk, p_eff<LDSQ, SHOCK>(lq, gq, qa + t, m), p_eff<LDSQ, SHOCK>(lq, gq, qb + t, m), t);
+    }
+}
+
+template <int K, bool LDSQ, bool LAST, bool ESC>
+__device__ __forceinline__ void run_vector(const RecParams &P, const double *__restrict__ lq,
+                                           const double *__restrict__ vcurves, int node_rel,
+                                           int tile, const Tile &T, int sb, int lane)
+{
+    const int node = P.node_begin + node_rel;
+    const int shift = node * P.node_step;
+    const int slot = T.first + lane;
+    const int S = P.term[slot] - shift;
+    const int uid = P.uidx[slot];
+    const bool live = (uid >= 0) && (S > 0);
+    const int smax = T.smax - shift;
+    const int smin = max(T.smin - shift, 0);
+    const double m = P.shock[node];
+    double cf[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) cf[j] = P.coef[j * P.n_pad + slot];
+    const int qa = P.qoff1[slot] + P.age1[slot] + shift;
+    const int qb = P.qoff2[slot] + P.age2[slot] + shift;
+    const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
+
+    double r0[K], r1[K], r2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { r0[k] = 0.0; r1[k] = 0.0; r2[k] = 0.0; }
+
+    double *path = nullptr;
+    if constexpr (K == 1) {
+        if (P.path != nullptr && live) {
+            path = P.path + P.path_off[uid];
+            path[S] = 0.0;
+        } else if (P.path != nullptr && uid >= 0) {
+            P.path[P.path_off[uid]] = 0.0;         // expired: its one entry is 0
+        }
+    }
+    // A lane takes its first step at t = S - 1 (the head skips t >= S).
+    PatLane pl{0, 12, 0, 1.0, 1.0, 0};
+    if constexpr (ESC) pl = pat_init(P, slot, shift, S - 1);
+    if (m == 1.0)
+        vector_steps<K, LDSQ, LAST, false, ESC>(lq, P.q, vb, P.scen_pad, qa, qb, m, cf, pl, S, smax,
+                                                smin, r0, r1, r2, path);
+    else
+        vector_steps<K, LDSQ, LAST, true, ESC>(lq, P.q, vb, P.scen_pad, qa, qb, m, cf, pl, S, smax,
+                                               smin, r0, r1, r2, path);
+    store_results<K>(P, node_rel, tile, sb, lane, uid, live, r0, r1, r2, LAST, true);
+}
+
+// Persistent grid: each wavefront takes items from its XCD's queue (the
+// hardware places workgroup b on XCD b mod 8), then steals from the others.
+// The read-only inputs are separate __restrict__ arguments so that the
+// compiler may read the wavefront-uniform curve values with scalar loads.
+// PAT: the portfolio has tiles of annuities with payment patterns (run with
+// one policy per lane, whatever J).
+template <int K, int J, bool LDSQ, bool VEC, bool PAT>
+__global__ void __launch_bounds__(WG_THREADS)
+k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__restrict__ items,
+             const Tile *__restrict__ tiles, const int *__restrict__ qbeg)
+{
+    extern __shared__ double s_q[];
+    if constexpr (LDSQ) {
+        for (int i = threadIdx.x; i < P.n_q; i += blockDim.x) s_q[i] = P.q[i];
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    int qcur = blockIdx.x % P.n_queues;
+    int tried = 0;
+    while (tried < P.n_queues) {
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(&P.counters[qcur], 1);
+        idx = wave_uniform(idx);   // every lane is active here: lane 0's value
+        const int beg = wave_uniform(qbeg[qcur]);
+        const int end = wave_uniform(qbeg[qcur + 1]);
+        if (beg + idx >= end) {
+            qcur = (qcur + 1 == P.n_queues) ? 0 : qcur + 1;
+            ++tried;
+            continue;
+        }
+        const Item it = items[beg + idx];
+        const int node_rel = wave_uniform(it.node_rel);
+        const int tile = wave_uniform(it.tile);
+        const int sb = wave_uniform(it.sblock);
+        const int count = wave_uniform(it.count);
+        Tile T = tiles[tile];
+        T.kind = wave_uniform(T.kind);
+        T.first = wave_uniform(T.first);
+        T.smax = wave_uniform(T.smax);
+        T.smin = wave_uniform(T.smin);
+        T.pat = wave_uniform(T.pat);
+        // Terms are bucketed, not strictly sorted: take the extremes over the
+        // item's tiles.
+        int smax = T.smax, smin = T.smin;
+        for (int j = 1; j < count; ++j) {
+            smax = max(smax, wave_uniform(tiles[tile + j].smax));
+            smin = min(smin, wave_uniform(tiles[tile + j].smin));
+        }
+        if (PAT && T.pat) {
+            if constexpr (PAT) {
+                if (T.kind == KIND_SINGLE)
+                    run_scalar<K, 1, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, 1, T, T.smax,
+                                                        T.smin, sb, lane);
+                else if (T.kind == KIND_JOINT)
+                    run_scalar<K, 1, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, 1, T, T.smax,
+                                                       T.smin, sb, lane);
+                else if (T.kind == KIND_REV)
+                    run_vector<K, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                else
+                    run_vector<K, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+            }
+        } else if (T.kind == KIND_SINGLE) {
+            run_scalar<K, J, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, count, T, smax,
+                                                 smin, sb, lane);
+        } else if (T.kind == KIND_JOINT) {
+            run_scalar<K, J, LDSQ, true, false>(P, s_q, vcurves, node_rel, tile, count, T, smax,
+                                                smin, sb, lane);
+        } else if constexpr (VEC) {
+            if (T.kind == KIND_REV)
+                run_vector<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+            else
+                run_vector<K, LDSQ, true, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+        }
+    }
+    // The last wavefront to finish re-arms the queues for the next launch.
+    if (lane == 0) {
+        const int total = (int)(gridDim.x * (blockDim.x / 64));
+        if (atomicAdd(&P.counters[MAX_QUEUES], 1) == total - 1) {
+            for (int i = 0; i <= MAX_QUEUES; ++i) atomicExch(&P.counters[i], 0);
+        }
+    }
+}
+
+template <int K, int J, bool PAT>
+static void launch_kjp(const RecParams &p, int grid, size_t lds, hipStream_t s)
+{
+    const dim3 g(grid), b(WG_THREADS);
+    if (p.q_in_lds) {
+        if (p.has_vector)
+            hipLaunchKernelGGL((k_recurrence<K, J, true, true, PAT>), g, b, lds, s, p, p.v, p.items, p.tiles, p.qbeg);
+        else
+            hipLaunchKernelGGL((k_recurrence<K, J, true, false, PAT>), g, b, lds, s, p, p.v, p.items, p.tiles, p.qbeg);
+    } else {
+        if (p.has_vector)
+            hipLaunchKernelGGL((k_recurrence<K, J, false, true, PAT>), g, b, 0, s, p, p.v, p.items, p.tiles, p.qbeg);
+        else
+            hipLaunchKernelGGL((k_recurrence<K, J, false, false, PAT>), g, b, 0, s, p, p.v, p.items, p.tiles, p.qbeg);
+    }
+}
+
+
+// Launch of the (K, J) instance for the supported pairs (supported_kj).
+template <bool PAT>
+static hipError_t launch_switch(int K, int J, const RecParams &p, int grid, size_t lds,
+                                hipStream_t s)
+{
+    switch (J * 64 + K) {
+    case 64 + 1: launch_kjp<1, 1, PAT>(p, grid, lds, s); break;
+    case 64 + 2: launch_kjp<2, 1, PAT>(p, grid, lds, s); break;
+    case 64 + 4: launch_kjp<4, 1, PAT>(p, grid, lds, s); break;
+    case 64 + 8: launch_kjp<8, 1, PAT>(p, grid, lds, s); break;
+    case 64 + 16: launch_kjp<16, 1, PAT>(p, grid, lds, s); break;
+    case 64 + 32: launch_kjp<32, 1, PAT>(p, grid, lds, s); break;
+    case 128 + 4: launch_kjp<4, 2, PAT>(p, grid, lds, s); break;
+    case 128 + 8: launch_kjp<8, 2, PAT>(p, grid, lds, s); break;
+    case 128 + 16: launch_kjp<16, 2, PAT>(p, grid, lds, s); break;
+    case 256 + 2: launch_kjp<2, 4, PAT>(p, grid, lds, s); break;
+    case 256 + 4: launch_kjp<4, 4, PAT>(p, grid, lds, s); break;
+    case 256 + 8: launch_kjp<8, 4, PAT>(p, grid, lds, s); break;
+    case 256 + 16: launch_kjp<16, 4, PAT>(p, grid, lds, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Launch of the kernels with the payment-pattern paths (rr_kernels_pat.hip).
+hipError_t launch_recurrence_pat(int K, int J, const RecParams &p, int grid, size_t lds_bytes,
+                                 hipStream_t stream);
+
+}  // namespace rr

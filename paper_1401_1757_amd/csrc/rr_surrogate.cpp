@@ -127,7 +127,7 @@ struct rr::Surrogate {
 
     // portfolio copies in upload order
     int pol_gen = -1;
-    DevBuf<int> product, age1, age2, term, table1, table2, timing;
+    DevBuf<int> product, age1, age2, term, table1, table2, timing, patterned;
     DevBuf<double> amount, premium;
 
     // feature and inference workspaces
@@ -213,6 +213,7 @@ int sync_policies(rr_ctx *c, Surrogate *S)
     if ((rc = upload_vec(c, S->timing, c->h_timing))) return rc;
     if ((rc = upload_vec(c, S->amount, c->h_amount))) return rc;
     if ((rc = upload_vec(c, S->premium, c->h_premium))) return rc;
+    if ((rc = upload_vec(c, S->patterned, c->h_patterned))) return rc;
     S->pol_gen = c->gen;
     return RR_OK;
 }
@@ -220,7 +221,7 @@ int sync_policies(rr_ctx *c, Surrogate *S)
 M::Policies policies_of(Surrogate *S, int n)
 {
     return M::Policies{n, S->product.p, S->age1.p, S->age2.p, S->term.p, S->table1.p,
-                       S->table2.p, S->timing.p, S->amount.p, S->premium.p};
+                       S->table2.p, S->timing.p, S->amount.p, S->premium.p, S->patterned.p};
 }
 
 int check_run(rr_ctx *c, const rr_run *run)
@@ -429,7 +430,8 @@ std::vector<float> init_params(uint64_t seed)
     return p;
 }
 
-// Per one-hot product, the (table1, table2, timing) of the training policies.
+// Per one-hot product, the (table1, table2, timing) of the training policies
+// (level payments only: patterned annuities are outside the domain).
 int product_signature(rr_ctx *c, int32_t sig[12])
 {
     for (int j = 0; j < 4; ++j) {
@@ -438,7 +440,7 @@ int product_signature(rr_ctx *c, int32_t sig[12])
         sig[3 * j + 2] = -1;
         bool seen = false;
         for (int i = 0; i < c->n_user; ++i) {
-            if (c->h_product[i] != kProducts[j]) continue;
+            if (c->h_product[i] != kProducts[j] || c->h_patterned[i]) continue;
             const int t1 = c->h_table1[i];
             const int t2 = kProducts[j] == RR_JL_ANN ? c->h_table2[i] : -1;
             const int tm = (kProducts[j] == RR_SL_ANN || kProducts[j] == RR_JL_ANN) ? c->h_timing[i] : -1;

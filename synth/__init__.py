@@ -326,6 +326,66 @@ def config_c3a(seed: int = 1013, n: int = 10_000, n_scen: int = 1000,
                     Basis(q=q, v=v[None]), pf)
 
 
+# Representative annuity portfolio (Sec. 5.3, Table 2): tables by sex.
+TABLE_MALE, TABLE_FEMALE = 0, 1
+REP_LOADINGS = (1.0, 0.6)          # female q = 0.6 x male q (a reading: the paper gives no table)
+REP_COMPOSITION = ((SL_ANN, 300_000), (JL_ANN, 50_000), (REV_ANN, 100_000), (LS_ANN, 50_000))
+REP_AGE_LO_Y, REP_AGE_HI_Y = 57, 67
+REP_N_STEPS = LIMIT_AGE_M - REP_AGE_LO_Y * 12     # 756: to age 120 from the youngest age
+
+
+def portfolio_representative(rng, n: int = 500_000) -> Portfolio:
+    """Annuities of a recently retired cohort (Sec. 5.3): products in the
+    proportions of Table 2 (exact counts for n = 500,000); attained ages
+    uniform over [57, 67] years in whole months, both lives of two-life
+    policies from the same law; life 1 male with probability 0.75, life 2 of
+    the other sex; inception uniform over the year before the valuation date,
+    so the next anniversary is U{1..12} months away; 80 % pay monthly, 20 %
+    once a year on the anniversary; the amount of each payment is lognormal
+    with mean 5.0 and sd 1.5; 95 % level, the rest escalating at 3, 4.25 or
+    5 % on each anniversary.  Payments fall at month ends (arrears), no
+    premiums remain, and every policy runs to the limiting age of 120 of its
+    younger life (q = 1 from there)."""
+    total = sum(c for _, c in REP_COMPOSITION)
+    counts = np.array([c * n // total for _, c in REP_COMPOSITION])
+    counts[0] += n - counts.sum()
+    product = np.concatenate([np.full(c, p, np.int32) for (p, _), c in zip(REP_COMPOSITION, counts)])
+    rng.shuffle(product)
+    two = np.isin(product, TWO_LIFE)
+    age1 = rng.integers(REP_AGE_LO_Y * 12, REP_AGE_HI_Y * 12, n, endpoint=True).astype(np.int32)
+    age2 = rng.integers(REP_AGE_LO_Y * 12, REP_AGE_HI_Y * 12, n, endpoint=True).astype(np.int32)
+    age2 = np.where(two, age2, 0).astype(np.int32)
+    male = rng.uniform(size=n) < 0.75
+    table1 = np.where(male, TABLE_MALE, TABLE_FEMALE).astype(np.int32)
+    table2 = np.where(two, np.where(male, TABLE_FEMALE, TABLE_MALE), table1).astype(np.int32)
+    youngest = np.where(two, np.minimum(age1, age2), age1)
+    term = (LIMIT_AGE_M - youngest).astype(np.int32)
+    annual = (rng.uniform(size=n) < 0.20).astype(np.int32)
+    sd_log = math.sqrt(math.log1p((1.5 / 5.0) ** 2))
+    per_payment = _lognormal(rng, 5.0, sd_log, n)
+    amount = np.where(annual == 1, per_payment, 12.0 * per_payment)
+    rates = np.array([0.03, 0.0425, 0.05])
+    esc = np.where(rng.uniform(size=n) < 0.05, rates[rng.integers(0, 3, n)], 0.0)
+    anniv = rng.integers(1, 13, n).astype(np.int32)
+    return Portfolio(product=product, age1_m=age1, age2_m=age2, term_m=term, table1=table1,
+                     table2=table2, timing=np.full(n, ARREARS, np.int32), amount=amount,
+                     premium=np.zeros(n), escalation=esc, anniv_m=anniv, annual=annual)
+
+
+def config_rep(seed: int = 1006, n: int = 500_000, n_scen: int = 1000,
+               scen_seed: int = 2006) -> Workload:
+    """The representative 500,000-annuity portfolio x Vasicek inner scenarios
+    over the 756 monthly steps to the limiting age."""
+    rng = np.random.default_rng(seed)
+    pf = portfolio_representative(rng, n)
+    q = mortality_tables(max_attained_age(pf) + 1, REP_LOADINGS)
+    srng = np.random.default_rng(scen_seed)
+    v, _ = vasicek_paths(srng, n_scen, REP_N_STEPS, VAS_R0)
+    return Workload(f"representative portfolio: {n:,} annuities (Table 2 mix, 5 % escalating, "
+                    f"20 % annual) x {n_scen:,} Vasicek scenarios, 756 monthly steps",
+                    Basis(q=q, v=v[None]), pf)
+
+
 def outer_path(rng, n_nodes: int, node_step_m: int = 12):
     """One outer Vasicek path observed every node_step_m months: r at nodes."""
     _, r = vasicek_paths(rng, 1, n_nodes * node_step_m, VAS_R0)

@@ -85,3 +85,75 @@ def test_basis_checks(rr):
     v3 = v.copy(); v3[0, 0, 0] = np.inf
     assert "v[0]" in rr.check_basis(q, v3)
     assert "shock[0]" in rr.check_basis(q, v, shock=np.array([-1.0]))
+
+
+def test_payment_pattern_checks(rr):
+    """Patterns only on annuities in payment; rates, anniversaries and the
+    annual flag in range."""
+    w = synth.config_c2(n=2000)
+    n_ages = w.basis.q.shape[1]
+    base = w.portfolio.subset(np.arange(40))
+    ann = np.flatnonzero(np.isin(base.product, (synth.SL_ANN, synth.JL_ANN)))
+    ins = np.flatnonzero(np.isin(base.product, (synth.TERM, synth.ENDOW)))
+    assert ann.size and ins.size
+
+    def patterned(esc=0.0, anniv=3, annual=0):
+        pf = base.subset(np.arange(base.n))
+        pf.escalation = np.zeros(pf.n)
+        pf.anniv_m = np.full(pf.n, 12, np.int32)
+        pf.annual = np.zeros(pf.n, np.int32)
+        return pf
+
+    ok = patterned()
+    ok.escalation[ann] = 0.05
+    ok.annual[ann[::2]] = 1
+    ok.anniv_m[:] = np.arange(ok.n) % 12 + 1
+    assert rr.check_portfolio(ok, 600, n_ages, 3) == ""
+    i, k = int(ann[0]), int(ins[0])
+    cases = [
+        ("escalation", i, -0.01, f"policy {i} escalation"),
+        ("escalation", i, float("nan"), f"policy {i} escalation"),
+        ("escalation", i, 1.5, f"policy {i} escalation"),
+        ("anniv_m", i, 0, f"policy {i} anniv_m 0"),
+        ("anniv_m", k, 13, f"policy {k} anniv_m 13"),
+        ("annual", i, 2, f"policy {i} annual 2"),
+        ("escalation", k, 0.03, f"policy {k} has a payment pattern but product"),
+        ("annual", k, 1, f"policy {k} has a payment pattern but product"),
+    ]
+    for field, j, val, msg in cases:
+        pf = patterned()
+        getattr(pf, field)[j] = val
+        got = rr.check_portfolio(pf, 600, n_ages, 3)
+        assert msg in got, (field, j, val, got)
+    pf = patterned()
+    pf.escalation[i] = 0.03
+    pf.premium[i] = 1.0
+    assert f"policy {i} has a payment pattern and premium" in rr.check_portfolio(pf, 600, n_ages, 3)
+    # a level annuity may keep a premium whatever its anniversary
+    pf = patterned()
+    pf.premium[i] = 1.0
+    pf.anniv_m[i] = 1
+    assert rr.check_portfolio(pf, 600, n_ages, 3) == ""
+
+
+def test_representative_portfolio_law():
+    """The Sec. 5.3 recipe: composition, ages, sexes, frequencies, amounts,
+    escalation, anniversaries and terms to the limiting age."""
+    rng = np.random.default_rng(7)
+    pf = synth.portfolio_representative(rng, 500_000)
+    assert np.bincount(pf.product, minlength=4).tolist() == [300_000, 50_000, 100_000, 50_000]
+    assert pf.age1_m.min() >= 57 * 12 and pf.age1_m.max() <= 67 * 12
+    two = np.isin(pf.product, synth.TWO_LIFE)
+    assert pf.age2_m[two].min() >= 57 * 12 and pf.age2_m[two].max() <= 67 * 12
+    assert abs((pf.table1 == synth.TABLE_MALE).mean() - 0.75) < 0.005
+    assert np.all(pf.table2[two] != pf.table1[two])
+    assert abs(pf.annual.mean() - 0.20) < 0.005
+    pay = np.where(pf.annual == 1, pf.amount, pf.amount / 12.0)
+    assert abs(pay.mean() - 5.0) < 0.02 and abs(pay.std() - 1.5) < 0.02
+    assert abs((pf.escalation > 0).mean() - 0.05) < 0.002
+    assert set(np.unique(pf.escalation)) == {0.0, 0.03, 0.0425, 0.05}
+    assert set(np.unique(pf.anniv_m)) == set(range(1, 13))
+    youngest = np.where(two, np.minimum(pf.age1_m, pf.age2_m), pf.age1_m)
+    assert np.all(pf.term_m == synth.LIMIT_AGE_M - youngest)
+    assert abs(pf.term_m.mean() / 12 - 58) < 1.5     # the paper's average outstanding term
+    assert np.all(pf.premium == 0) and np.all(pf.timing == synth.ARREARS)

@@ -117,6 +117,28 @@ def test_c1_full_with_path(ctx, rr):
     assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
 
 
+def test_path_at_a_later_node_with_expired_policies(ctx):
+    """Path mode at node 2 (24 months on): expired policies own one entry,
+    which must be written as 0; the buffer starts as NaN."""
+    rng = np.random.default_rng(77)
+    w = synth.random_small(rng, n=200, n_steps=60, n_scen=2, n_nodes=3, shock=True)
+    b, pf = w.basis, w.portfolio
+    assert (pf.term_m <= 24).sum() > 20
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("path at node 2")
+    po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=2, node_step=12)
+    po["path"].fill_(float("nan"))
+    ctx.reserve_recurrence(2, 1, 1, 1, 12, po)
+    torch.cuda.synchronize()
+    path, off = oracle.reserve_paths(b, pf, node=2, scen=1, node_step=12)
+    ref = oracle.reserves(b, pf, 2, 1, 1, 1, 12)
+    gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+    got = to_np(po["path"])
+    assert not np.isnan(got).any()
+    assert_reserves_close(got, path, np.maximum(gross, 0), what="path")
+
+
 def test_c2_full_r0_totals_and_path(ctx):
     w = synth.config_c2()
     _say("C2 full")

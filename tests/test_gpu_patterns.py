@@ -1,0 +1,175 @@
+"""GPU parity for annuity payment patterns (escalation on policy
+anniversaries, annual payment) and the representative annuity portfolio
+(Sec. 5.3, Table 2), through the C ABI against the CPU oracle.
+
+Same bar as the level products: FP64 reserves within 1e-10 of max(|r|,
+gross PV) per valuation and totals within 1e-10 of the summed gross PV.
+The representative portfolio at its full size (500,000 annuities x 1,000
+Vasicek scenarios x 756 steps) is checked on sampled outputs in the launch
+configuration the benchmark times."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._helpers import RTOL, assert_reserves_close, assert_states_close, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ANNUITIES = (synth.SL_ANN, synth.JL_ANN, synth.REV_ANN, synth.LS_ANN)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1401_1757_amd as rr
+    return rr
+
+
+@pytest.fixture()
+def ctx(rr):
+    c = rr.Context(0)
+    yield c
+    c.close()
+
+
+def patterned_workload(seed, n, n_steps, n_scen, n_nodes, products=tuple(range(7)), node_step=7):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=n, n_steps=n_steps, n_scen=n_scen, n_nodes=n_nodes, shock=True,
+                           products=products)
+    pf = synth.with_payment_patterns(rng, w.portfolio, 0.5, 0.4)
+    return synth.Workload("patterned", w.basis, pf, node_step_m=node_step)
+
+
+def compare(ctx, w, all_states=True, node0=0, nnode=None, scen0=0, nscen=None):
+    b, pf = w.basis, w.portfolio
+    nnode = b.n_nodes - node0 if nnode is None else nnode
+    nscen = b.n_scen - scen0 if nscen is None else nscen
+    out = ctx.alloc_outputs(nnode, nscen, all_states=all_states)
+    ctx.reserve_recurrence(node0, nnode, scen0, nscen, w.node_step_m, out)
+    torch.cuda.synchronize()
+    ref = oracle.reserves(b, pf, node0, nnode, scen0, nscen, w.node_step_m)
+    if all_states:
+        assert_states_close(to_np(out["r0"]), ref["r_all"], ref["gross"])
+    else:
+        assert_reserves_close(to_np(out["r0"]), ref["r_all"][..., 0], ref["gross"])
+    err = np.abs(to_np(out["totals"]) - ref["totals"])
+    assert np.all(err <= RTOL * np.maximum(ref["gross_totals"], 1e-300)), err.max()
+    return out, ref
+
+
+@pytest.mark.parametrize("K,J", [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (32, 1), (4, 2),
+                                 (8, 2), (16, 2), (2, 4), (4, 4), (8, 4), (16, 4)])
+def test_patterns_mixed_with_level_policies(ctx, K, J):
+    """Every product; half the annuities escalate, 40 % pay annually; three
+    nodes 7 months apart with shocks; ragged tiles and scenario blocks."""
+    w = patterned_workload(500 + K + 7 * J, n=400, n_steps=100, n_scen=2 * K + 3, n_nodes=3)
+    assert (w.portfolio.escalation > 0).sum() > 20 and w.portfolio.annual.sum() > 20
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(w.portfolio)
+    ctx.set_option(1, K)
+    ctx.set_option(8, J)
+    _say(f"patterns K={K} J={J}")
+    compare(ctx, w)
+
+
+@pytest.mark.parametrize("product", ANNUITIES)
+def test_patterns_each_annuity_all_states(ctx, product):
+    w = patterned_workload(600 + product, n=150, n_steps=200, n_scen=9, n_nodes=2,
+                           products=(product,), node_step=12)
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(w.portfolio)
+    _say(f"patterns product {product}")
+    compare(ctx, w)
+
+
+def test_pattern_paths(ctx):
+    """Reserve at every step for one node and scenario (K = 1 path mode)."""
+    w = patterned_workload(700, n=120, n_steps=150, n_scen=3, n_nodes=2, products=ANNUITIES,
+                           node_step=12)
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("pattern paths")
+    for node, scen in ((0, 0), (1, 2)):
+        po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=node, node_step=12)
+        po["path"].fill_(float("nan"))        # every entry must be written
+        ctx.reserve_recurrence(node, 1, scen, 1, 12, po)
+        torch.cuda.synchronize()
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=scen, node_step=12)
+        ref = oracle.reserves(b, pf, node, 1, scen, 1, 12)
+        gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+        assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
+
+
+def test_level_patterns_bitwise_equal_plain(ctx):
+    """Anniversaries on level policies change nothing: same tiles, same bits."""
+    rng = np.random.default_rng(710)
+    w = synth.random_small(rng, n=300, n_steps=90, n_scen=17, n_nodes=2, shock=True)
+    b, pf = w.basis, w.portfolio
+    lv = pf.subset(np.arange(pf.n))
+    lv.escalation = np.zeros(pf.n)
+    lv.anniv_m = rng.integers(1, 13, pf.n).astype(np.int32)
+    lv.annual = np.zeros(pf.n, np.int32)
+    ctx.basis_upload(b.q, b.v, b.shock)
+    res = []
+    for p in (pf, lv):
+        ctx.portfolio_upload(p)
+        out = ctx.alloc_outputs(2, b.n_scen, all_states=True)
+        ctx.reserve_recurrence(0, 2, 0, b.n_scen, 12, out)
+        torch.cuda.synchronize()
+        res.append((to_np(out["r0"]), to_np(out["totals"])))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_representative_portfolio_small_all_steps(ctx):
+    """3,000 policies of the Sec. 5.3 law, 24 Vasicek scenarios, every
+    output checked (756 monthly steps to the limiting age)."""
+    w = synth.config_rep(n=3000, n_scen=24)
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(w.portfolio)
+    _say("representative 3,000 x 24")
+    compare(ctx, w)
+
+
+def test_representative_portfolio_full_size_sampled(ctx):
+    """500,000 annuities x 1,000 scenarios in the benchmark's launch
+    configuration (autotuned, totals and the tail statistic): two scenario
+    totals over the whole portfolio and sampled reserves against the oracle."""
+    import os
+    threads = int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
+    w = synth.config_rep()
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("representative 500,000 x 1,000")
+    out = ctx.alloc_outputs(1, b.n_scen, r0=False, stats=True)
+    ctx.reserve_recurrence(0, 1, 0, b.n_scen, 12, out)
+    torch.cuda.synchronize()
+    tot = to_np(out["totals"])[0]
+    st = to_np(out["stats"])[0]
+    k = int(np.ceil(0.005 * b.n_scen))
+    assert st[1] == np.sort(tot)[::-1][k - 1]
+    for s in (0, 777):
+        _say(f"  oracle total of scenario {s}")
+        ref = oracle.reserves(b, pf, 0, 1, s, 1, 12, n_threads=threads)
+        assert abs(tot[s] - ref["totals"][0, 0]) <= RTOL * ref["gross_totals"][0, 0]
+    # sampled reserves in a window of scenarios (r0 written)
+    rng = np.random.default_rng(9)
+    idx = np.sort(rng.choice(pf.n, 400, replace=False))
+    win = ctx.alloc_outputs(1, 8, all_states=True)
+    ctx.reserve_recurrence(0, 1, 500, 8, 12, win)
+    torch.cuda.synchronize()
+    got = to_np(win["r0"])[:, idx]
+    ref = oracle.reserves(b, pf.subset(idx), 0, 1, 500, 8, 12, n_threads=threads)
+    assert_states_close(got, ref["r_all"], ref["gross"])

@@ -174,6 +174,13 @@ def parity_workload(seed=41, n=300, n_nodes=2, n_scen=40):
     pf.age2_m[np.flatnonzero(pf.product == synth.REV_ANN)] = 700
     pf.amount[np.flatnonzero(pf.product == synth.TERM)[0]] *= 1e4   # far outside the box
     pf.term_m[np.flatnonzero(pf.product == synth.ENDOW)[:2]] = 12    # expired at node 1
+    # escalating and annual annuities: outside the domain (exact fallback)
+    sl = np.flatnonzero(pf.product == synth.SL_ANN)
+    pf.escalation = np.zeros(n)
+    pf.annual = np.zeros(n, np.int32)
+    pf.anniv_m = (np.arange(n) % 12 + 1).astype(np.int32)
+    pf.escalation[sl[2]] = 0.05
+    pf.annual[sl[3]] = 1
     q = synth.mortality_tables(synth.max_attained_age(pf) + 1, synth.C2_LOADINGS)
     v = np.empty((n_nodes, n_scen, 600))
     for k in range(n_nodes):
@@ -223,7 +230,9 @@ def test_features_and_flags_match_oracle(ctx, rr, omodel):
     np.testing.assert_allclose(to_np(f["scen"]), sraw, rtol=1e-12, atol=1e-13)
     assert np.array_equal(to_np(f["pflag"]), pflag)
     assert np.array_equal(to_np(f["sflag"]), sflag)
-    assert (pflag == 0).sum() >= 3 and (pflag == 2).sum() >= 1 and (sflag == 0).sum() >= 1
+    assert (pflag == 0).sum() >= 5 and (pflag == 2).sum() >= 1 and (sflag == 0).sum() >= 1
+    sl = np.flatnonzero(pf.product == synth.SL_ANN)
+    assert np.all(pflag[:, sl[2:4]] == 0)     # patterned annuities
 
 
 def test_infer_matches_oracle_with_fallback(ctx, rr, omodel):
