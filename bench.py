@@ -207,10 +207,13 @@ def representative_leg(rr, synth, sync, steps=5):
         timed_steps(f, steps, sync)
         kms = float(np.mean(ctx.kernel_times()))
         ctx.set_option(rr.OPT_KERNEL_TIMING, 0)
-        _, _, live, vsteps = scenario_step_work(pf)
+        flops, ops, live, vsteps = scenario_step_work(pf)
         ms = 1e3 * e / steps
+        achieved = flops * b.n_scen / (kms * 1e-3) / 1e12
         return {"workload": w.name, "policies": pf.n, "scenarios": b.n_scen,
                 "ms_per_step": ms, "kernel_ms": kms,
+                "kernel_tflops": achieved, "kernel_frac_fp64_peak": achieved / FP64_PEAK_TFLOPS,
+                "kernel_issue_frac": ops * b.n_scen / (kms * 1e-3) / FP64_ISSUE_PEAK,
                 "valuations_per_s": live * b.n_scen / (e / steps),
                 "valuation_steps_per_s": vsteps * b.n_scen / (e / steps),
                 "escalating": int((pf.escalation > 0).sum()), "annual": int(pf.annual.sum()),
@@ -239,6 +242,8 @@ def main():
                     help="only run a plain 1 GiB device copy (traffic counter calibration)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the timed region of the headline workload (for profiling)")
+    ap.add_argument("--representative-only", action="store_true",
+                    help="only the representative 500,000-annuity portfolio leg (for profiling)")
     ap.add_argument("--block-k", type=int, default=0, help="pin scenarios per lane (0 = autotune)")
     ap.add_argument("--wg", type=int, default=0, help="pin workgroups per CU (0 = autotune)")
     ap.add_argument("--block-j", type=int, default=0, help="pin policies per lane (0 = autotune)")
@@ -268,6 +273,9 @@ def main():
     import synth
 
     sync = torch.cuda.synchronize
+    if args.representative_only:
+        print(json.dumps(representative_leg(rr, synth, sync, steps=args.steps)))
+        return
     w = synth.config_c3()
     b, pf = w.basis, w.portfolio
     ctx = rr.Context(0)

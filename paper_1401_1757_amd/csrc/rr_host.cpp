@@ -806,7 +806,8 @@ static int enqueue_run(rr_ctx *c, const rr_run *run, const rr_outputs *out, Plan
         c->ev_pending.push_back(ev);
     }
     if (totals) {
-        HIPCHK(c, launch_totals(partial, run->node_count, c->n_tiles, run->scen_count, totals, s));
+        HIPCHK(c, launch_totals(partial, run->node_count, c->n_tiles, run->scen_count, totals,
+                                partial + (size_t)run->node_count * c->n_tiles * run->scen_count, s));
     }
     if ((run->out_mask & RR_OUT_STATS) && out->stats) {
         double tail = run->tail > 0.0 ? run->tail : 0.005;
@@ -991,7 +992,9 @@ extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outp
     }
     double *partial = nullptr;
     if (need_tot) {
-        size_t np = (size_t)run->node_count * c->n_tiles * run->scen_count;
+        // per-tile partials, then the scratch of the chunked totals pass
+        size_t np = (size_t)run->node_count * c->n_tiles * run->scen_count +
+                    (size_t)totals_scratch_doubles(run->node_count, c->n_tiles, run->scen_count);
         if (np > c->partial.n) drop_graphs(c);
         HIPCHK(c, c->partial.alloc(np));
         partial = c->partial.p;

@@ -102,8 +102,11 @@ struct RecParams {
 // Launchers (rr_kernels.hip).  All are asynchronous on `stream`.
 hipError_t launch_recurrence(int K, int J, const RecParams &p, int grid, size_t lds_bytes,
                              hipStream_t stream);
+// scratch: totals_scratch_doubles(node_count, n_tiles, scen_count) doubles
+// (may be null when that is 0).
 hipError_t launch_totals(const double *partial, int node_count, int n_tiles, int scen_count,
-                         double *totals, hipStream_t stream);
+                         double *totals, double *scratch, hipStream_t stream);
+long long totals_scratch_doubles(int node_count, int n_tiles, int scen_count);
 hipError_t launch_stats(const double *totals, int node_count, int scen_count, int rank,
                         double *stats, hipStream_t stream);
 hipError_t launch_fill(double *dst, long long n, double value, hipStream_t stream);

@@ -33,19 +33,42 @@ hipError_t launch_recurrence(int K, int J, const RecParams &p, int grid, size_t 
 // ---------------------------------------------------------------------------
 constexpr int TOT_SCEN = 64;     // scenarios per workgroup (one wavefront wide)
 constexpr int TOT_GROUPS = 16;   // tile groups summed in parallel, then in order
+constexpr int TOT_CHUNK = 256;   // tiles per workgroup when the tiles are split
 
+// Number of tile chunks the wide pass splits a node's tiles into (1: one
+// pass straight into the totals).  Many tiles and few scenario blocks would
+// otherwise leave the chip idle (e.g. 7,813 tiles x 1,000 scenarios: 16
+// workgroups).
+static int totals_chunks(int n_tiles, int scen_count)
+{
+    if (scen_count < 32 || n_tiles <= 2 * TOT_CHUNK) return 1;
+    return (n_tiles + TOT_CHUNK - 1) / TOT_CHUNK;
+}
+
+long long totals_scratch_doubles(int node_count, int n_tiles, int scen_count)
+{
+    const int nc = totals_chunks(n_tiles, scen_count);
+    return nc > 1 ? (long long)node_count * nc * scen_count : 0;
+}
+
+// Workgroup (scenario block, node, chunk): the sum over the chunk's tiles,
+// TOT_GROUPS strided partial sums then those in order.  Output
+// out[node][chunk][scen] (n_chunks = 1: the totals).
 __global__ void __launch_bounds__(TOT_SCEN * TOT_GROUPS)
-k_totals_wide(const double *__restrict__ partial, int n_tiles, int scen_count,
-              double *__restrict__ totals)
+k_totals_wide(const double *__restrict__ partial, int n_tiles, int scen_count, int chunk_tiles,
+              int n_chunks, double *__restrict__ out)
 {
     __shared__ double sh[TOT_GROUPS][TOT_SCEN];
     const int sx = threadIdx.x, g = threadIdx.y;
     const int s = blockIdx.x * TOT_SCEN + sx;
     const int node = blockIdx.y;
+    const int chunk = blockIdx.z;
+    const int t0 = chunk * chunk_tiles;
+    const int t1 = min(t0 + chunk_tiles, n_tiles);
     double acc = 0.0;
     if (s < scen_count) {
         const double *p = partial + (size_t)node * n_tiles * scen_count + s;
-        for (int t = g; t < n_tiles; t += TOT_GROUPS) acc += p[(size_t)t * scen_count];
+        for (int t = t0 + g; t < t1; t += TOT_GROUPS) acc += p[(size_t)t * scen_count];
     }
     sh[g][sx] = acc;
     __syncthreads();
@@ -53,8 +76,21 @@ k_totals_wide(const double *__restrict__ partial, int n_tiles, int scen_count,
         double tot = 0.0;
 #pragma unroll
         for (int j = 0; j < TOT_GROUPS; ++j) tot += sh[j][sx];
-        totals[(size_t)node * scen_count + s] = tot;
+        out[((size_t)node * n_chunks + chunk) * scen_count + s] = tot;
     }
+}
+
+// Chunk sums of each (node, scenario) added in chunk order.
+__global__ void __launch_bounds__(256) k_totals_merge(const double *__restrict__ chunks, int n_chunks,
+                                                      int scen_count, double *__restrict__ totals)
+{
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int node = blockIdx.y;
+    if (s >= scen_count) return;
+    const double *p = chunks + (size_t)node * n_chunks * scen_count + s;
+    double tot = 0.0;
+    for (int c = 0; c < n_chunks; ++c) tot += p[(size_t)c * scen_count];
+    totals[(size_t)node * scen_count + s] = tot;
 }
 
 // Few scenarios, many tiles: one workgroup per (node, scenario); strided
@@ -79,13 +115,21 @@ __global__ void __launch_bounds__(256) k_totals_narrow(const double *__restrict_
 }
 
 hipError_t launch_totals(const double *partial, int node_count, int n_tiles, int scen_count,
-                         double *totals, hipStream_t stream)
+                         double *totals, double *scratch, hipStream_t stream)
 {
     if (node_count <= 0 || scen_count <= 0) return hipSuccess;
     if (scen_count >= 32) {
-        dim3 grid((scen_count + TOT_SCEN - 1) / TOT_SCEN, node_count);
+        const int nc = totals_chunks(n_tiles, scen_count);
+        if (nc > 1 && scratch == nullptr) return hipErrorInvalidValue;
+        dim3 grid((scen_count + TOT_SCEN - 1) / TOT_SCEN, node_count, nc);
         hipLaunchKernelGGL(k_totals_wide, grid, dim3(TOT_SCEN, TOT_GROUPS), 0, stream, partial,
-                           n_tiles, scen_count, totals);
+                           n_tiles, scen_count, nc > 1 ? TOT_CHUNK : n_tiles, nc,
+                           nc > 1 ? scratch : totals);
+        if (nc > 1) {
+            dim3 mgrid((scen_count + 255) / 256, node_count);
+            hipLaunchKernelGGL(k_totals_merge, mgrid, dim3(256), 0, stream, scratch, nc, scen_count,
+                               totals);
+        }
     } else {
         dim3 grid(scen_count, node_count);
         hipLaunchKernelGGL(k_totals_narrow, grid, dim3(256), 0, stream, partial, n_tiles,

@@ -139,6 +139,22 @@ def test_path_at_a_later_node_with_expired_policies(ctx):
     assert_reserves_close(got, path, np.maximum(gross, 0), what="path")
 
 
+def test_many_tiles_chunked_totals(ctx):
+    """Over 512 tiles with a wide scenario range: the totals are summed in
+    tile chunks, then the chunks in order; every total against the oracle."""
+    rng = np.random.default_rng(78)
+    w = synth.random_small(rng, n=40_000, n_steps=24, n_scen=70, n_nodes=2, shock=True)
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(w.portfolio)
+    _say("chunked totals, 40,000 policies")
+    out = ctx.alloc_outputs(2, 70, r0=False, stats=True)
+    ctx.reserve_recurrence(0, 2, 0, 70, 12, out)
+    torch.cuda.synchronize()
+    ref = oracle.reserves(w.basis, w.portfolio, 0, 2, 0, 70, 12)
+    err = np.abs(to_np(out["totals"]) - ref["totals"])
+    assert np.all(err <= RTOL * np.maximum(ref["gross_totals"], 1e-300)), err.max()
+
+
 def test_c2_full_r0_totals_and_path(ctx):
     w = synth.config_c2()
     _say("C2 full")
