@@ -46,7 +46,8 @@ class _Portfolio(ctypes.Structure):
                 ("table2", ctypes.c_void_p), ("timing", ctypes.c_void_p),
                 ("amount", ctypes.c_void_p), ("premium", ctypes.c_void_p),
                 ("escalation", ctypes.c_void_p), ("anniv", ctypes.c_void_p),
-                ("annual", ctypes.c_void_p)]
+                ("annual", ctypes.c_void_p), ("cf_row", ctypes.c_void_p),
+                ("cf", ctypes.c_void_p), ("n_cf_rows", ctypes.c_int), ("cf_len", ctypes.c_int)]
 
 
 def _load():
@@ -88,8 +89,13 @@ class _Args:
         self.arrs = [i32(pf.product), i32(pf.age1_m), i32(pf.age2_m), i32(pf.term_m),
                      i32(pf.table1), i32(pf.table2), i32(pf.timing), f64(pf.amount),
                      f64(pf.premium), opt(getattr(pf, "escalation", None), f64),
-                     opt(getattr(pf, "anniv_m", None), i32), opt(getattr(pf, "annual", None), i32)]
-        self.p = _Portfolio(int(pf.product.shape[0]), *[_ptr(a) for a in self.arrs])
+                     opt(getattr(pf, "anniv_m", None), i32), opt(getattr(pf, "annual", None), i32),
+                     opt(getattr(pf, "cf_row", None), i32)]
+        cf = getattr(pf, "cf", None)
+        self.cf = None if cf is None else np.ascontiguousarray(np.atleast_2d(cf), np.float64)
+        n_rows, cf_len = (0, 0) if self.cf is None else self.cf.shape
+        self.p = _Portfolio(int(pf.product.shape[0]), *[_ptr(a) for a in self.arrs], _ptr(self.cf),
+                            n_rows, cf_len)
         self.n = int(pf.product.shape[0])
 
 

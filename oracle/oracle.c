@@ -39,6 +39,9 @@
  *     annual ones pay amount at each anniversary only.  The time-varying
  *     annuity stream c_t of Eq. (3.1) is the level stream times this factor
  *     at the payment time (t for f = 0, t + 1 for f = 1).
+ *   - A cash-flow-table policy (one life) pays amount x cf[row][T] at the
+ *     end of step T (months since node 0) if alive then, plus the level
+ *     premium in advance; its boundary reserve is 0.
  *   - A policy whose remaining term at the node is <= 0 has expired: all its
  *     outputs are 0 and it is left out of totals.
  */
@@ -50,7 +53,7 @@
 /* Product codes (input format). */
 enum {
     O_SL_ANN = 0, O_JL_ANN = 1, O_REV_ANN = 2, O_LS_ANN = 3,
-    O_TERM = 4, O_ENDOW = 5, O_ENDOW_ASSUR = 6, O_N_PRODUCTS = 7
+    O_TERM = 4, O_ENDOW = 5, O_ENDOW_ASSUR = 6, O_CF_TABLE = 7, O_N_PRODUCTS = 8
 };
 
 #define ORC_MAX_STATES 9
@@ -81,6 +84,10 @@ typedef struct {
     const double *escalation;/* annuity escalation rate per anniversary, or NULL */
     const int32_t *anniv;    /* months from node 0 to the first anniversary, or NULL */
     const int32_t *annual;   /* 1: one payment a year, at anniversaries; or NULL */
+    const int32_t *cf_row;   /* O_CF_TABLE: row of the cash-flow table, or NULL */
+    const double *cf;        /* [n_cf_rows][cf_len] cash flow per unit amount, or NULL */
+    int n_cf_rows;
+    int cf_len;
 } orc_portfolio;
 
 /* A contract in the paper's state-space form (Sec. 3.1, Sec. 4). */
@@ -93,6 +100,7 @@ typedef struct {
     double c_ben[ORC_MAX_STATES];       /* death benefit stream, at f = 1 */
     double c_prem[ORC_MAX_STATES];      /* premium stream, at f = 0 */
     double boundary[ORC_MAX_STATES];    /* reserve vector at the end of the term */
+    int gross;                          /* absolute values of every cash flow */
 } orc_contract;
 
 /* ------------------------------------------------------------------------ */
@@ -217,10 +225,17 @@ int orc_contract_of(int product, int timing, double amount, double premium,
         k->n_lives = 2; k->life_model = 2; k->n_states = 4;
         k->c_ann[0] = pay; k->c_ann[1] = pay; k->c_ann[2] = pay;
         break;
+    case O_CF_TABLE:     /* single life, c_t = amount x table value, at f = 1
+                            (Sec. 4.4: c_t holds the nominal amounts) */
+        k->n_lives = 1; k->life_model = 2; k->n_states = 2;
+        k->f_ann = 1.0;
+        k->c_ann[0] = gross ? fabs(amount) : amount;
+        break;
     default:
         return -1;
     }
     k->c_prem[0] = prem;   /* premiums while every life is alive */
+    k->gross = gross;
     return 0;
 }
 
@@ -255,9 +270,14 @@ static void add_stream(const orc_contract *k, const double *q, double v, double 
 
 /* Factor of the level annuity stream for a payment at time T (months after
  * node 0): (1+e)^n(T) with n(T) the anniversaries in (0, T], times 12 at an
- * anniversary and 0 elsewhere for annual payment. */
-static double payment_factor(const orc_portfolio *p, int i, int T)
+ * anniversary and 0 elsewhere for annual payment.  For a cash-flow table the
+ * factor is the table's value for the step ending at T. */
+static double payment_factor(const orc_portfolio *p, int i, int T, const orc_contract *k)
 {
+    if (p->product[i] == O_CF_TABLE) {
+        double c = p->cf[(size_t)p->cf_row[i] * p->cf_len + (T - 1)];
+        return k->gross ? fabs(c) : c;
+    }
     double e = p->escalation ? p->escalation[i] : 0.0;
     int a = p->anniv ? p->anniv[i] : 12;
     int annual = p->annual ? p->annual[i] : 0;
@@ -287,7 +307,7 @@ static void recurrence_one(const orc_basis *b, const orc_portfolio *p, int i,
         for (int j = 0; j < n; ++j) rn[j] = 0.0;
         add_stream(k, q, v, 0.0, k->c_prem, rn);
         double c_pay[ORC_MAX_STATES];
-        double fac = payment_factor(p, i, age_shift + t + (k->f_ann == 1.0 ? 1 : 0));
+        double fac = payment_factor(p, i, age_shift + t + (k->f_ann == 1.0 ? 1 : 0), k);
         for (int j = 0; j < n; ++j) c_pay[j] = fac * k->c_ann[j];
         add_stream(k, q, v, k->f_ann, c_pay, rn);
         add_stream(k, q, v, 1.0, k->c_ben, rn);
@@ -319,6 +339,11 @@ static int validate(const orc_basis *b, const orc_portfolio *p)
         if (p->table1[i] < 0 || p->table1[i] >= b->n_tables) return -1;
         if (p->anniv && (p->anniv[i] < 1 || p->anniv[i] > 12)) return -1;
         if (p->escalation && !(p->escalation[i] >= 0.0)) return -1;
+        if (p->product[i] == O_CF_TABLE) {
+            if (!p->cf_row || !p->cf) return -1;
+            if (p->cf_row[i] < 0 || p->cf_row[i] >= p->n_cf_rows) return -1;
+            if (p->term[i] > p->cf_len) return -1;
+        }
         int two = p->product[i] == O_JL_ANN || p->product[i] == O_REV_ANN ||
                   p->product[i] == O_LS_ANN;
         if (two) {
@@ -468,7 +493,7 @@ int orc_reserve_path_summation(const orc_basis *b, const orc_portfolio *p, int i
                 matmul(P, Wg, n, PW);
                 matvec(PW, streams[st], n, y);
                 double d = D * pow(v, gs[st]);
-                if (st == 1) d *= payment_factor(p, i, shift + u + (k.f_ann == 1.0 ? 1 : 0));
+                if (st == 1) d *= payment_factor(p, i, shift + u + (k.f_ann == 1.0 ? 1 : 0), &k);
                 for (int j = 0; j < n; ++j) r[j] += d * y[j];
             }
             orc_build_w(k.n_lives, k.life_model, q, 1.0, Wg);

@@ -42,7 +42,8 @@ LS_ANN = 3        # last-survivor annuity (Sec. 4.2.1 c)
 TERM = 4          # term assurance (3-state model, Sec. 4.1.3)
 ENDOW = 5         # pure endowment (Sec. 4.1.2)
 ENDOW_ASSUR = 6   # endowment assurance: term assurance + pure endowment
-N_PRODUCTS = 7
+N_PRODUCTS = 7    # products with closed-form cash flows (0..6)
+CF_TABLE = 7      # single life, cash flows amount x cf[row][t] from a table (Sec. 4.4)
 TWO_LIFE = (JL_ANN, REV_ANN, LS_ANN)
 
 ADVANCE = 0       # annuity paid at the start of each month (f = 0)
@@ -145,15 +146,21 @@ class Portfolio:
     escalation: np.ndarray | None = None   # float64 [n] rate e, payments x (1+e) at each anniversary
     anniv_m: np.ndarray | None = None      # int32 [n] months from node 0 to the first anniversary, 1..12
     annual: np.ndarray | None = None       # int32 [n] 1: one payment of `amount` per anniversary
+    # Cash-flow tables (CF_TABLE policies): policy i pays amount[i] x cf[cf_row[i]][T]
+    # at the end of month T after node 0 if alive.
+    cf_row: np.ndarray | None = None       # int32 [n]
+    cf: np.ndarray | None = None           # float64 [n_rows][cf_len]
 
     @property
     def n(self) -> int:
         return int(self.product.shape[0])
 
     def subset(self, idx) -> "Portfolio":
-        return Portfolio(**{f.name: (None if getattr(self, f.name) is None
-                                     else np.ascontiguousarray(getattr(self, f.name)[idx]))
-                            for f in dataclasses.fields(self)})
+        d = {f.name: (None if getattr(self, f.name) is None
+                      else np.ascontiguousarray(getattr(self, f.name)[idx]))
+             for f in dataclasses.fields(self) if f.name != "cf"}
+        d["cf"] = None if self.cf is None else self.cf.copy()   # rows are shared
+        return Portfolio(**d)
 
     def scaled(self, factor: float) -> "Portfolio":
         d = {f.name: (None if getattr(self, f.name) is None else getattr(self, f.name).copy())
@@ -479,6 +486,27 @@ def random_mlp_params(rng, n_feat: int = 17, k_in: int = 32, hidden: int = 256,
             "b2": rng.normal(0.0, bias_sd, hidden).astype(np.float32),
             "W3": rng.normal(0.0, 1.0 / np.sqrt(hidden), hidden).astype(np.float32),
             "b3": np.float32(rng.normal(0.0, bias_sd))}
+
+
+def with_cash_flow_tables(rng, pf: Portfolio, frac: float = 0.3, n_rows: int = 5,
+                          cf_len: int | None = None) -> Portfolio:
+    """Copy of pf in which a share `frac` of the policies become CF_TABLE
+    policies (one life: table1, age1) drawing on `n_rows` random tables of
+    cash flows per unit amount: some rows level, some increasing, some with
+    a single lump, some signed."""
+    n = pf.n
+    out = pf.subset(np.arange(n))
+    L = int(pf.term_m.max()) if cf_len is None else cf_len
+    t = np.arange(L)
+    shapes = [np.full(L, 1.0 / 12.0), (1.0 + t) / 12.0, np.where(t == L // 2, 5.0, 0.0),
+              rng.uniform(-0.2, 1.0, L), np.where(t % 12 == 11, 1.0, 0.0)]
+    cf = np.stack([shapes[r % len(shapes)] * rng.uniform(0.5, 2.0) for r in range(n_rows)])
+    pick = rng.uniform(size=n) < frac
+    out.product = np.where(pick, CF_TABLE, pf.product).astype(np.int32)
+    out.cf_row = rng.integers(0, n_rows, n).astype(np.int32)
+    out.cf = cf
+    out.age2_m = np.where(pick, 0, pf.age2_m).astype(np.int32)
+    return out
 
 
 def with_payment_patterns(rng, pf: Portfolio, frac_escalating: float = 0.5,

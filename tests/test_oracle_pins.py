@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from synth import (ADVANCE, ARREARS, ENDOW, ENDOW_ASSUR, JL_ANN, LS_ANN,
+from synth import (ADVANCE, ARREARS, CF_TABLE, ENDOW, ENDOW_ASSUR, JL_ANN, LS_ANN,
                    REV_ANN, SL_ANN, TERM, Basis, Portfolio)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -490,6 +490,87 @@ def test_payment_patterns_node_shift_equals_path(step):
     pf = _pattern_pf([SL_ANN, SL_ANN, JL_ANN, SL_ANN], [700, 650, 600, 720], [600, 500, 550, 400],
                      [1200.0, 900.0, 600.0, 300.0], [ARREARS, ADVANCE, ARREARS, ARREARS],
                      [0.05, 0.03, 0.0425, 0.0], [3, 12, 7, 1], [0, 1, 0, 1], age2=[0, 0, 700, 0])
+    path, off = oracle.reserve_paths(b, pf, node=0)
+    full = oracle.reserves(b, pf, node_step=step)
+    for k in range(4):
+        for i in range(pf.n):
+            assert full["r_all"][k, i, 0, 0] == path[off[i] + step * k]
+
+
+# --------------------------------------------------------------------------
+# Cash-flow tables (one life, c_t = amount x cf[row][t], Sec. 4.4)
+# --------------------------------------------------------------------------
+def _cf_pf(rows, row_of, age1, term, amount, premium=0.0, table1=0):
+    n = np.broadcast(np.asarray(row_of), np.asarray(age1), np.asarray(term), np.asarray(amount),
+                     np.asarray(premium)).size
+    pf = make_pf([CF_TABLE] * n, age1, term, amount=amount, premium=premium, table1=table1)
+    pf.cf = np.atleast_2d(np.asarray(rows, np.float64))
+    pf.cf_row = np.asarray(np.broadcast_to(row_of, (pf.n,)), np.int32).copy()
+    return pf
+
+
+@pytest.mark.parametrize("S", [1, 2, 37, 600])
+def test_cash_flow_table_closed_form_at_zero_mortality(S):
+    rng = np.random.default_rng(S)
+    v = rng.uniform(0.995, 1.0, 600)
+    b = basis(np.zeros(N_AGES), v)
+    rows = rng.uniform(-1.0, 3.0, (2, 600))
+    pf = _cf_pf(rows, [0, 1], 700, S, [250.0, 40.0], premium=[3.0, 0.0])
+    r = r0(b, pf)[:, 0]
+    D = np.concatenate([[1.0], np.cumprod(v[:S])])          # discount to t = 0..S
+    want = [a * (rows[k, :S] * D[1:S + 1]).sum() - P * D[:S].sum()
+            for k, a, P in ((0, 250.0, 3.0), (1, 40.0, 0.0))]
+    np.testing.assert_allclose(r, want, rtol=1e-12, atol=1e-12 * 250)
+
+
+def test_cash_flow_table_reproduces_level_annuity_and_pure_endowment():
+    b = basis(gm(1.0), np.full(600, V_FLAT))
+    S, theta = 360, 1200.0
+    level = _cf_pf(np.full((1, S), 1.0 / 12.0), 0, 720, S, theta)
+    sl = make_pf([SL_ANN], 720, S, amount=theta, timing=ARREARS)
+    np.testing.assert_allclose(r0(b, level), r0(b, sl), rtol=1e-14)
+    lump = np.zeros((1, S)); lump[0, S - 1] = 1.0
+    pe = _cf_pf(lump, 0, 600, S, 5000.0, premium=7.0)
+    endow = make_pf([ENDOW], 600, S, amount=5000.0, premium=7.0)
+    np.testing.assert_allclose(r0(b, pe), r0(b, endow), rtol=1e-13)
+
+
+def test_cash_flow_table_is_linear_in_the_table():
+    rng = np.random.default_rng(12)
+    w = synth.random_small(rng, n=1, n_steps=200, n_scen=2)
+    rows = rng.uniform(-1.0, 2.0, (2, 200))
+    rows = np.vstack([rows, rows[0] + rows[1]])
+    pf = _cf_pf(rows, [0, 1, 2], [300, 300, 300], 200, 100.0)
+    r = oracle.reserves(w.basis, pf)["r_all"][0, :, :, 0]
+    np.testing.assert_allclose(r[0] + r[1], r[2], rtol=1e-12, atol=1e-12 * np.abs(r).max())
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_cash_flow_tables_recurrence_equals_summation(seed):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=16, n_steps=50, n_scen=2, n_nodes=3, shock=True)
+    pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=0.6)
+    b = w.basis
+    assert (pf.product == CF_TABLE).sum() >= 5
+    for node in range(3):
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=1, node_step=7)
+        for i in np.flatnonzero(pf.product == CF_TABLE):
+            if int(pf.term_m[i]) - 7 * node <= 0:
+                continue
+            summ = oracle.reserve_path_summation(b, pf, i, node=node, scen=1, node_step=7)
+            scale = np.abs(summ).max() + 1e-300
+            np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=0,
+                                       atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("step", [12, 5])
+def test_cash_flow_table_node_shift_equals_path(step):
+    """The table is indexed by time since node 0."""
+    rng = np.random.default_rng(step)
+    b = Basis(q=np.atleast_2d(gm(1.0)), v=np.full((4, 1, 600), V_FLAT))
+    rows = rng.uniform(0.0, 2.0, (3, 600))
+    pf = _cf_pf(rows, [0, 1, 2], [700, 650, 600], [600, 500, 550], [1200.0, 900.0, 600.0],
+                premium=[0.0, 2.0, 1.0])
     path, off = oracle.reserve_paths(b, pf, node=0)
     full = oracle.reserves(b, pf, node_step=step)
     for k in range(4):
