@@ -43,9 +43,10 @@ def scenario_step_work(pf, node=0, node_step=12):
     flops = np.zeros(pf.n)
     ops = np.zeros(pf.n)
     # single-state recurrences: r = a0 + v (p r + c)
-    single = np.isin(prod, (synth.SL_ANN, synth.JL_ANN, synth.TERM, synth.ENDOW, synth.ENDOW_ASSUR))
+    single = np.isin(prod, (synth.SL_ANN, synth.JL_ANN, synth.TERM, synth.ENDOW, synth.ENDOW_ASSUR,
+                            synth.CF_TABLE))
     c_nonzero = ((np.isin(prod, (synth.SL_ANN, synth.JL_ANN)) & arrears) |
-                 np.isin(prod, (synth.TERM, synth.ENDOW_ASSUR)))
+                 np.isin(prod, (synth.TERM, synth.ENDOW_ASSUR, synth.CF_TABLE)))
     a0_nonzero = prem | (np.isin(prod, (synth.SL_ANN, synth.JL_ANN)) & ~arrears)
     flops[single] = (np.where(c_nonzero, 2, 1) + np.where(a0_nonzero, 2, 1))[single]
     ops[single] = 2

@@ -71,6 +71,9 @@ typedef struct rr_ctx rr_ctx;
 #define RR_TERM         4  /* term assurance, 3-state model, c = (0,1,0), r_S = 0 (Sec. 4.1.3) */
 #define RR_ENDOW        5  /* pure endowment, boundary r_S = (SA, 0) (Sec. 4.1.2) */
 #define RR_ENDOW_ASSUR  6  /* endowment assurance: term assurance with r_S = (SA, 0, 0) */
+#define RR_CF_TABLE     7  /* one life, 2-state model; pays amount x cf[cf_row][T] at the end of
+                              month T (months since node 0) if alive, level premium in advance,
+                              r_S = 0 (Sec. 4.4: c_t holds the nominal amounts) */
 
 #define RR_ADVANCE 0       /* annuity paid at the start of each month (f = 0) */
 #define RR_ARREARS 1       /* annuity paid at the end of each month (f = 1) */
@@ -145,6 +148,15 @@ typedef struct {
     const double *escalation;   /* or NULL: payment patterns, see above */
     const int32_t *anniv_m;     /* or NULL */
     const int32_t *annual;      /* or NULL */
+    /* Cash-flow tables of RR_CF_TABLE policies (NULL/0 when there are none):
+     * cf[cf_n_rows][cf_len] cash flows per unit amount, finite; policy i uses
+     * row cf_row[i] (0 <= row < cf_n_rows) and needs term_m[i] <= cf_len.  The
+     * library keeps amount x row values per policy and month in device memory
+     * (8 bytes x policies x longest term). */
+    const int32_t *cf_row;
+    const double *cf;
+    int32_t cf_n_rows;
+    int32_t cf_len;
 } rr_portfolio;
 
 /* One valuation run over nodes [node_begin, node_begin + node_count) and

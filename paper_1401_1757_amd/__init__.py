@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librr.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ERANGE, RR_ESTATE = 0, -1, -2, -3, -4, -5
-SL_ANN, JL_ANN, REV_ANN, LS_ANN, TERM, ENDOW, ENDOW_ASSUR = range(7)
+SL_ANN, JL_ANN, REV_ANN, LS_ANN, TERM, ENDOW, ENDOW_ASSUR, CF_TABLE = range(8)
 ADVANCE, ARREARS = 0, 1
 HOST, DEVICE = 0, 1
 OUT_R0, OUT_TOTALS, OUT_PATH, OUT_ALL_STATES, OUT_STATS = 1, 2, 4, 8, 16
@@ -58,7 +58,9 @@ class Portfolio(ctypes.Structure):
                 ("table2", ctypes.c_void_p), ("timing", ctypes.c_void_p),
                 ("amount", ctypes.c_void_p), ("premium", ctypes.c_void_p),
                 ("mem_kind", ctypes.c_int32), ("escalation", ctypes.c_void_p),
-                ("anniv_m", ctypes.c_void_p), ("annual", ctypes.c_void_p)]
+                ("anniv_m", ctypes.c_void_p), ("annual", ctypes.c_void_p),
+                ("cf_row", ctypes.c_void_p), ("cf", ctypes.c_void_p),
+                ("cf_n_rows", ctypes.c_int32), ("cf_len", ctypes.c_int32)]
 
 
 class Run(ctypes.Structure):
@@ -202,14 +204,20 @@ def portfolio_struct(pf, keep=None):
     arrs = [_np(pf.product, np.int32), _np(pf.age1_m, np.int32), _np(pf.age2_m, np.int32),
             _np(pf.term_m, np.int32), _np(pf.table1, np.int32), _np(pf.table2, np.int32),
             _np(pf.timing, np.int32), _np(pf.amount, np.float64), _np(pf.premium, np.float64)]
-    # Optional annuity payment patterns (None: level payments).
+    # Optional annuity payment patterns (None: level payments) and cash-flow tables.
     opt = [None if getattr(pf, name, None) is None else _np(getattr(pf, name), dt)
-           for name, dt in (("escalation", np.float64), ("anniv_m", np.int32), ("annual", np.int32))]
+           for name, dt in (("escalation", np.float64), ("anniv_m", np.int32), ("annual", np.int32),
+                            ("cf_row", np.int32))]
+    cf = getattr(pf, "cf", None)
+    cf = None if cf is None else np.ascontiguousarray(np.atleast_2d(cf), np.float64)
+    n_rows, cf_len = (0, 0) if cf is None else cf.shape
     if keep is not None:
         keep.extend(arrs)
         keep.extend(opt)
+        keep.append(cf)
     return Portfolio(arrs[0].shape[0], *[a.ctypes.data for a in arrs], HOST,
-                     *[None if a is None else a.ctypes.data for a in opt])
+                     *[None if a is None else a.ctypes.data for a in opt],
+                     None if cf is None else cf.ctypes.data, n_rows, cf_len)
 
 
 def check_portfolio(pf, n_steps, n_ages, n_tables):

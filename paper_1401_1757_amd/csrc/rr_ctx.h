@@ -124,9 +124,11 @@ struct rr_ctx {
     std::vector<int> slot_of_user;       // user index -> sorted slot
     DevBuf<int> age1, age2, term, qoff1, qoff2, uidx;
     DevBuf<double> coef;
-    DevBuf<double> pat_g;                 // [n_pad] (pattern tiles only)
+    DevBuf<double> pat_g;                 // [n_pad] (with pattern or table tiles)
     DevBuf<int> pat_code;
-    bool has_pattern = false;
+    DevBuf<double> cf_t;                  // [cf_steps][cf_cols] (table tiles)
+    int cf_cols = 0;
+    bool has_flow = false;                // some tile is not FLOW_LEVEL
     DevBuf<Tile> tiles;
     int gen = 0;                          // bumps on every upload
 

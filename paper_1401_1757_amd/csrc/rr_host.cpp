@@ -127,16 +127,26 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
                                           const int32_t *timing, const double *amount,
                                           const double *premium, const double *escalation,
                                           const int32_t *anniv, const int32_t *annual,
-                                          int n_steps, int n_ages, int n_tables)
+                                          const int32_t *cf_row, const double *cf, int cf_n_rows,
+                                          int cf_len, int n_steps, int n_ages, int n_tables)
 {
     char b[256];
     if (n < 0) return "portfolio: n must be >= 0";
+    if (cf_n_rows < 0 || cf_len < 0) return "portfolio: cf_n_rows and cf_len must be >= 0";
+    if (cf) {
+        const long long m = (long long)cf_n_rows * cf_len;
+        for (long long k = 0; k < m; ++k)
+            if (!std::isfinite(cf[k])) {
+                snprintf(b, sizeof b, "portfolio: cf[%lld] = %g is not finite", k, cf[k]);
+                return b;
+            }
+    }
     if (n > (1 << 28)) return "portfolio: n too large";
     if (n > 0 && (!product || !age1 || !term || !table1 || !amount))
         return "portfolio: product, age1_m, term_m, table1 and amount must not be NULL";
     for (int i = 0; i < n; ++i) {
         int pr = product[i];
-        if (pr < RR_SL_ANN || pr > RR_ENDOW_ASSUR) {
+        if (pr < RR_SL_ANN || pr > RR_CF_TABLE) {
             snprintf(b, sizeof b, "portfolio: policy %d has unknown product %d", i, pr);
             return b;
         }
@@ -162,6 +172,18 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
             }
             if (table2[i] < 0 || table2[i] >= n_tables) {
                 snprintf(b, sizeof b, "portfolio: policy %d table2 %d outside [0, %d)", i, table2[i], n_tables);
+                return b;
+            }
+        }
+        if (pr == RR_CF_TABLE) {
+            if (!cf_row || !cf) return "portfolio: RR_CF_TABLE policies need cf_row and cf";
+            if (cf_row[i] < 0 || cf_row[i] >= cf_n_rows) {
+                snprintf(b, sizeof b, "portfolio: policy %d cf_row %d outside [0, %d)", i, cf_row[i],
+                         cf_n_rows);
+                return b;
+            }
+            if (term[i] > cf_len) {
+                snprintf(b, sizeof b, "portfolio: policy %d term %d exceeds cf_len %d", i, term[i], cf_len);
                 return b;
             }
         }
@@ -224,6 +246,7 @@ extern "C" int rr_check_portfolio(const rr_portfolio *p, int32_t n_steps, int32_
     std::string s = check_portfolio_arrays(p->n, p->product, p->age1_m, p->age2_m, p->term_m,
                                            p->table1, p->table2, p->timing, p->amount,
                                            p->premium, p->escalation, p->anniv_m, p->annual,
+                                           p->cf_row, p->cf, p->cf_n_rows, p->cf_len,
                                            n_steps, n_ages, n_tables);
     set_msg(msg, msg_len, s);
     return s.empty() ? RR_OK : RR_EINVAL;
@@ -439,8 +462,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     HIPCHK(c, hipSetDevice(c->device));
     const size_t n = (size_t)p->n;
     std::vector<int32_t> product, age1, age2, term, table1, table2, timing;
-    std::vector<double> amount, premium, escalation;
-    std::vector<int32_t> anniv, annual;
+    std::vector<double> amount, premium, escalation, cf;
+    std::vector<int32_t> anniv, annual, cf_row;
     int rc;
     if (n > 0 && (!p->product || !p->age1_m || !p->term_m || !p->table1 || !p->amount))
         return fail(c, RR_EINVAL, "portfolio: product, age1_m, term_m, table1 and amount must not be NULL");
@@ -463,6 +486,11 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     else anniv.assign(n, 12);
     if (p->annual) { if ((rc = fetch(c, p->annual, n, p->mem_kind, annual))) return rc; }
     else annual.assign(n, 0);
+    if (p->cf_n_rows < 0 || p->cf_len < 0) return fail(c, RR_EINVAL, "portfolio: cf_n_rows and cf_len must be >= 0");
+    if (p->cf_row) { if ((rc = fetch(c, p->cf_row, n, p->mem_kind, cf_row))) return rc; }
+    if (p->cf) {
+        if ((rc = fetch(c, p->cf, (size_t)p->cf_n_rows * p->cf_len, p->mem_kind, cf))) return rc;
+    }
     bool any_two = false;
     for (size_t i = 0; i < n; ++i) any_two |= is_two_life(product[i]);
     std::string s = check_portfolio_arrays(p->n, product.data(), age1.data(),
@@ -471,6 +499,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                                            (p->table2 || !any_two) ? table2.data() : nullptr,
                                            timing.data(), amount.data(), premium.data(),
                                            escalation.data(), anniv.data(), annual.data(),
+                                           p->cf_row ? cf_row.data() : nullptr,
+                                           p->cf ? cf.data() : nullptr, p->cf_n_rows, p->cf_len,
                                            c->n_steps, c->n_ages, c->n_tables);
     if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
 
@@ -479,11 +509,14 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     c->tuned.clear();
     c->has_pf = false;
 
-    // Sort: state model, payment pattern, remaining term descending, age
-    // (stable on index).
-    std::vector<int32_t> patterned(n, 0);
-    for (size_t i = 0; i < n; ++i) patterned[i] = (escalation[i] > 0.0 || annual[i] == 1) ? 1 : 0;
-    auto group_of = [&](int u) { return 2 * kind_of(product[u]) + patterned[u]; };
+    // Sort: state model, cash-flow kind (level, payment pattern, table),
+    // remaining term descending, age (stable on index).
+    std::vector<int32_t> patterned(n, 0), flow(n, FLOW_LEVEL);
+    for (size_t i = 0; i < n; ++i) {
+        patterned[i] = (escalation[i] > 0.0 || annual[i] == 1) ? 1 : 0;
+        flow[i] = product[i] == RR_CF_TABLE ? FLOW_TABLE : patterned[i] ? FLOW_PATTERN : FLOW_LEVEL;
+    }
+    auto group_of = [&](int u) { return 3 * kind_of(product[u]) + flow[u]; };
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     // Within a model, remaining terms are bucketed (width term_bucket months,
@@ -512,8 +545,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
         while (i1 < n && group_of(order[i1]) == group) ++i1;
         for (size_t a = i0; a < i1; a += TILE) {
             Tile T;
-            T.kind = group / 2;
-            T.pat = group % 2;
+            T.kind = group / 3;
+            T.flow = group % 3;
             T.first = (int)s_uidx.size();
             T.smax = 0;
             T.smin = 1 << 30;
@@ -551,9 +584,9 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     int head_pad = 0;
     for (size_t t0 = 0; t0 < tiles.size(); ++t0) {
         int smax = 0, smin = 1 << 30;
-        const size_t span = tiles[t0].pat ? 1 : 4;
+        const size_t span = tiles[t0].flow != FLOW_LEVEL ? 1 : 4;
         for (size_t t1 = t0; t1 < tiles.size() && t1 < t0 + span && tiles[t1].kind == tiles[t0].kind &&
-                             tiles[t1].pat == tiles[t0].pat;
+                             tiles[t1].flow == tiles[t0].flow;
              ++t1) {
             smax = std::max(smax, tiles[t1].smax);
             smin = std::min(smin, tiles[t1].smin);
@@ -596,6 +629,9 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
             C(2, j) = amount[u];
             C(3, j) = amount[u];
             break;
+        case RR_CF_TABLE:      // the survival cash flows come from the table
+            C(0, j) = -P;
+            break;
         case RR_REV_ANN:
             C(0, j) = -P;
             C(4, j) = adv ? pay : 0.0;
@@ -619,20 +655,51 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     if ((rc = upload_vec(c, c->uidx, s_uidx))) return rc;
     if ((rc = upload_vec(c, c->coef, coef))) return rc;
     if ((rc = upload_vec(c, c->tiles, tiles))) return rc;
-    // Payment patterns of the slots (level slots: g = 1, anniversary 12).
-    c->has_pattern = false;
-    for (const Tile &T : tiles) c->has_pattern |= T.pat != 0;
-    if (c->has_pattern) {
+    // Payment patterns of the slots (level slots: g = 1, anniversary 12) and
+    // the cash flows of table slots, amount x table value, month-major over
+    // the table tiles' slots (padding slots: 0).
+    c->has_flow = false;
+    for (const Tile &T : tiles) c->has_flow |= T.flow != FLOW_LEVEL;
+    c->cf_cols = 0;
+    if (c->has_flow) {
         std::vector<double> pg(n_pad, 1.0);
         std::vector<int> pc(n_pad, 12);
-        for (int j = 0; j < n_pad; ++j) {
-            const int u = s_uidx[j];
-            if (u < 0) continue;
-            pg[j] = 1.0 + escalation[u];
-            pc[j] = anniv[u] | (annual[u] ? PAT_ANNUAL : 0) | (timing[u] == RR_ARREARS ? PAT_ARREARS : 0);
+        int first_tab = -1, cf_steps = 0;
+        for (const Tile &T : tiles)
+            if (T.flow == FLOW_TABLE) {
+                if (first_tab < 0) first_tab = T.first;
+                c->cf_cols += TILE;
+                cf_steps = std::max(cf_steps, T.smax);
+            }
+        for (const Tile &T : tiles) {
+            for (int l = 0; l < TILE; ++l) {
+                const int j = T.first + l;
+                const int u = s_uidx[j];
+                if (T.flow == FLOW_TABLE) {
+                    pc[j] = j - first_tab;   // table tiles are consecutive
+                } else if (T.flow == FLOW_PATTERN && u >= 0) {
+                    pg[j] = 1.0 + escalation[u];
+                    pc[j] = anniv[u] | (annual[u] ? PAT_ANNUAL : 0) |
+                            (timing[u] == RR_ARREARS ? PAT_ARREARS : 0);
+                }
+            }
         }
         if ((rc = upload_vec(c, c->pat_g, pg))) return rc;
         if ((rc = upload_vec(c, c->pat_code, pc))) return rc;
+        if (c->cf_cols > 0) {
+            std::vector<double> ct((size_t)std::max(cf_steps, 1) * c->cf_cols, 0.0);
+            for (const Tile &T : tiles) {
+                if (T.flow != FLOW_TABLE) continue;
+                for (int l = 0; l < TILE; ++l) {
+                    const int j = T.first + l, u = s_uidx[j];
+                    if (u < 0) continue;
+                    const double *row = cf.data() + (size_t)cf_row[u] * p->cf_len;
+                    for (int t = 0; t < term[u]; ++t)
+                        ct[(size_t)t * c->cf_cols + (j - first_tab)] = amount[u] * row[t];
+                }
+            }
+            if ((rc = upload_vec(c, c->cf_t, ct))) return rc;
+        }
     }
     c->n_user = (int)n;
     c->n_pad = n_pad;
@@ -686,11 +753,11 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
         std::vector<std::pair<int, int>> groups;   // (first tile, count)
         for (int t = 0; t < c->n_tiles;) {
             const int kind = c->tiles_host[t].kind;
-            const int pat = c->tiles_host[t].pat;
-            const int jmax = ((kind == KIND_SINGLE || kind == KIND_JOINT) && !pat) ? J : 1;
+            const int flow = c->tiles_host[t].flow;
+            const int jmax = ((kind == KIND_SINGLE || kind == KIND_JOINT) && flow == FLOW_LEVEL) ? J : 1;
             int count = 1;
             while (count < jmax && t + count < c->n_tiles && c->tiles_host[t + count].kind == kind &&
-                   c->tiles_host[t + count].pat == pat)
+                   c->tiles_host[t + count].flow == flow)
                 ++count;
             groups.push_back({t, count});
             t += count;
@@ -704,7 +771,7 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
                 const long long steps = std::max(smax - shift, 0);
                 const long long cost =
                     steps * g.second *
-                        (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind) + (T.pat ? 16 : 0)) + 64;
+                        (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind) + (T.flow ? 16 : 0)) + 64;
                 for (int b = 0; b < nsb; ++b) {
                     const int qid = queues > 1 ? (int)(((long long)nr * nsb + b) % queues) : 0;
                     qs[qid].push_back({cost, Item{nr, g.first, b * K, g.second}});
@@ -759,8 +826,10 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.qoff2 = c->qoff2.p;
     P.uidx = c->uidx.p;
     P.coef = c->coef.p;
-    P.pat_g = c->has_pattern ? c->pat_g.p : nullptr;
-    P.pat_code = c->has_pattern ? c->pat_code.p : nullptr;
+    P.pat_g = c->has_flow ? c->pat_g.p : nullptr;
+    P.pat_code = c->has_flow ? c->pat_code.p : nullptr;
+    P.cf_t = (c->has_flow && c->cf_cols > 0) ? c->cf_t.p : nullptr;
+    P.cf_cols = c->cf_cols;
     P.n_pad = c->n_pad;
     P.n_user = c->n_user;
     P.tiles = c->tiles.p;

@@ -26,7 +26,8 @@ constexpr int MAX_QUEUES = 8;     // one work queue per XCD
 constexpr int WG_THREADS = RR_WG_THREADS;   // wavefronts per workgroup x 64
 
 // Per-policy coefficients (rows of coef[N_COEF][n_pad]):
-//  KIND_SINGLE / KIND_JOINT:  0: a0 advance amount in state 0 (annuity due - premium)
+//  KIND_SINGLE / KIND_JOINT:  0: a0 advance amount in state 0 (annuity due - premium;
+//                                table policies: - premium)
 //                             1: a1 arrears amount paid if alive at the end of the step
 //                             2: b1 death benefit paid at the end of the step of death
 //                             3: boundary reserve r_S of state 0
@@ -34,18 +35,26 @@ constexpr int WG_THREADS = RR_WG_THREADS;   // wavefronts per workgroup x 64
 //                             2/3: advance/arrears amount in state 01
 //                             4/5: advance/arrears amount in state 10
 
+// How a tile's cash flows vary in time.  Tiles other than level ones run
+// one tile per item.
+enum Flow : int {
+    FLOW_LEVEL = 0,     // level amounts (coef rows)
+    FLOW_PATTERN = 1,   // annuities in payment with escalation or annual payment
+    FLOW_TABLE = 2      // single life, cash flow of step t from a per-policy table
+};
+
 struct Tile {
     int kind;
     int first;    // first sorted slot (multiple of TILE)
     int smax;     // largest remaining term at node 0 among valid lanes
     int smin;     // smallest remaining term at node 0 among valid lanes
-    int pat;      // 1: annuities with a payment pattern (escalation or annual
-                  // payment; premium 0), run one tile per item
+    int flow;     // Flow
 };
 
 // Payment pattern of a slot in a pattern tile: the code packs the months to
 // the first anniversary after node 0 (bits 0-7, 1..12), annual payment (bit 8)
-// and the payment offset f (bit 9: 1 for arrears, payment at t + 1).
+// and the payment offset f (bit 9: 1 for arrears, payment at t + 1).  For a
+// slot of a table tile the code is its column in the table array.
 constexpr int PAT_ANNUAL = 1 << 8;
 constexpr int PAT_ARREARS = 1 << 9;
 
@@ -76,7 +85,9 @@ struct RecParams {
     const int *uidx;          // upload index, -1 for padding
     const double *coef;       // [N_COEF][n_pad]
     const double *pat_g;      // [n_pad] 1 + escalation rate (pattern tiles), or null
-    const int *pat_code;      // [n_pad] anniversary / annual / timing code, or null
+    const int *pat_code;      // [n_pad] anniversary / annual / timing code or table column, or null
+    const double *cf_t;       // [cf_steps][cf_cols] amount x table value of the step, or null
+    int cf_cols;
     int n_pad;
     int n_user;
     const Tile *tiles;

@@ -138,6 +138,7 @@ struct ScalarLane {
     int qa, qb;   // LDS indices of the q of life 1 / life 2 at t = 0
     double a0, a1mb1, b1, a1;
     double rS;    // boundary reserve (state 0)
+    const double *cfb;   // table tiles: cash flow of step t at cfb[t * cf_cols]
 };
 
 // Payment pattern of one lane (escalating or annually paid annuity in
@@ -199,27 +200,39 @@ __device__ __forceinline__ double pat_factor(PatLane &pl, int t)
 // one-step survival probability is px * py).  Per step and scenario:
 //   r <- a0 + v * (p * r + c),  c = p * a1 + q * b1 = b1 + p * (a1 - b1).
 // Each lane carries J policies (one per tile of the item) x K scenarios.
-// ESC: annuities with a payment pattern (J = 1; no death benefit), whose a0
-// and a1 at step t are the level amounts times F of the payment time.
-template <int K, int J, bool LDSQ, bool TWO, bool SHOCK, bool ESC>
+// FLOW_PATTERN: annuities with a payment pattern (J = 1; no death benefit),
+// whose a0 and a1 at step t are the level amounts times F of the payment
+// time.  FLOW_TABLE: one life (J = 1), c at step t = p x the table's cash
+// flow of the step (loaded with the mortality values of the block).
+template <int K, int J, bool LDSQ, bool TWO, bool SHOCK, int FLOW>
 __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
                                              const double *__restrict__ gq,
                                              const double *__restrict__ vb, int stride,
-                                             const ScalarLane (&L)[J], PatLane (&PL)[J], double m,
-                                             int smax, int smin, double (&r)[J][K], double *path)
+                                             const ScalarLane (&L)[J], PatLane (&PL)[J], int cfs,
+                                             double m, int smax, int smin, double (&r)[J][K],
+                                             double *path)
 {
+    // Cash flow of step t from the table (table tiles only).
+    auto cfload = [&](int j, int t) -> double {
+        if constexpr (FLOW == FLOW_TABLE) return L[j].cfb[(ptrdiff_t)t * cfs];
+        else return 0.0;
+    };
     // x1, x2: one-step survival probabilities from the staged table.
-    auto coeffs = [&](int j, int t, double x1, double x2, double &p, double &c, double &a0) {
+    auto coeffs = [&](int j, int t, double x1, double x2, double cv, double &p, double &c,
+                      double &a0) {
         const ScalarLane &l = L[j];
         if constexpr (SHOCK) {
             x1 = 1.0 - fmin(1.0, m * (1.0 - x1));
             if constexpr (TWO) x2 = 1.0 - fmin(1.0, m * (1.0 - x2));
         }
         p = TWO ? x1 * x2 : x1;
-        if constexpr (ESC) {
+        if constexpr (FLOW == FLOW_PATTERN) {
             const double f = pat_factor(PL[j], t);
             c = p * (f * l.a1);
             a0 = f * l.a0;
+        } else if constexpr (FLOW == FLOW_TABLE) {
+            c = p * cv;
+            a0 = l.a0;
         } else {
             c = TWO ? p * l.a1 : fma(p, l.a1mb1, l.b1);
             a0 = l.a0;
@@ -231,7 +244,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
     };
     constexpr int U = StepBlock<K, J>::U;
     auto load_block = [&](int tb, const double *vtb, double (&vk)[U][K], double (&q1)[U][J],
-                          double (&q2)[U][J]) {
+                          double (&q2)[U][J], double (&cv)[U][J]) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -242,17 +255,18 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
             for (int j = 0; j < J; ++j) {
                 q1[u][j] = qload<LDSQ>(lq, gq, L[j].qa + tb - u);
                 q2[u][j] = TWO ? qload<LDSQ>(lq, gq, L[j].qb + tb - u) : 0.0;
+                cv[u][j] = cfload(j, tb - u);
             }
     };
     // One block of U steps, every policy of the block active (t < smin).
     auto run_block = [&](int tb, const double (&vk)[U][K], const double (&q1)[U][J],
-                         const double (&q2)[U][J]) {
+                         const double (&q2)[U][J], const double (&cv)[U][J]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 double p, c, a0;
-                coeffs(j, tb - u, q1[u][j], q2[u][j], p, c, a0);
+                coeffs(j, tb - u, q1[u][j], q2[u][j], cv[u][j], p, c, a0);
                 apply(r[j], vk[u], p, c, a0);
             }
             if constexpr (K == 1 && J == 1) {
@@ -274,7 +288,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
         for (int j = 0; j < J; ++j) {
             double p, c, a0;
             coeffs(j, t, qload<LDSQ>(lq, gq, L[j].qa + t),
-                   TWO ? qload<LDSQ>(lq, gq, L[j].qb + t) : 0.0, p, c, a0);
+                   TWO ? qload<LDSQ>(lq, gq, L[j].qb + t) : 0.0, cfload(j, t), p, c, a0);
             const bool on = t < L[j].S;
             p = on ? p : 0.0;
             c = on ? c : 0.0;
@@ -291,28 +305,29 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
         // prefetch after the last pair is clamped in bounds and unused.
         const int npair = ((t + 1) / U) / 2;
         if (npair > 0) {
-            double av[U][K], aq1[U][J], aq2[U][J], bv[U][K], bq1[U][J], bq2[U][J];
-            load_block(t, vb + (ptrdiff_t)t * stride, av, aq1, aq2);
+            double av[U][K], aq1[U][J], aq2[U][J], acv[U][J];
+            double bv[U][K], bq1[U][J], bq2[U][J], bcv[U][J];
+            load_block(t, vb + (ptrdiff_t)t * stride, av, aq1, aq2, acv);
             for (int i = 0; i < npair; ++i) {
                 wait_for(aq1[0][0], av[0][0]);
                 __builtin_amdgcn_sched_barrier(0);
-                load_block(t - U, vb + (ptrdiff_t)(t - U) * stride, bv, bq1, bq2);
+                load_block(t - U, vb + (ptrdiff_t)(t - U) * stride, bv, bq1, bq2, bcv);
                 __builtin_amdgcn_sched_barrier(0);
-                run_block(t, av, aq1, aq2);
+                run_block(t, av, aq1, aq2, acv);
                 wait_for(bq1[0][0], bv[0][0]);
                 const int tl = max(t - 2 * U, U - 1);
                 __builtin_amdgcn_sched_barrier(0);
-                load_block(tl, vb + (ptrdiff_t)tl * stride, av, aq1, aq2);
+                load_block(tl, vb + (ptrdiff_t)tl * stride, av, aq1, aq2, acv);
                 __builtin_amdgcn_sched_barrier(0);
-                run_block(t - U, bv, bq1, bq2);
+                run_block(t - U, bv, bq1, bq2, bcv);
                 t -= 2 * U;
             }
         }
     }
     for (; t >= U - 1; t -= U) {
-        double vk[U][K], q1[U][J], q2[U][J];
-        load_block(t, vb + (ptrdiff_t)t * stride, vk, q1, q2);
-        run_block(t, vk, q1, q2);
+        double vk[U][K], q1[U][J], q2[U][J], cv[U][J];
+        load_block(t, vb + (ptrdiff_t)t * stride, vk, q1, q2, cv);
+        run_block(t, vk, q1, q2, cv);
     }
     for (; t >= 0; --t) {   // fewer than U steps left
         const double *vt = vb + (ptrdiff_t)t * stride;
@@ -323,7 +338,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
         for (int j = 0; j < J; ++j) {
             double p, c, a0;
             coeffs(j, t, qload<LDSQ>(lq, gq, L[j].qa + t),
-                   TWO ? qload<LDSQ>(lq, gq, L[j].qb + t) : 0.0, p, c, a0);
+                   TWO ? qload<LDSQ>(lq, gq, L[j].qb + t) : 0.0, cfload(j, t), p, c, a0);
             apply(r[j], vk, p, c, a0);
         }
         if constexpr (K == 1 && J == 1) {
@@ -334,7 +349,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
 
 // An item of `count` (<= J) consecutive tiles of one scalar model and a block
 // of K scenarios: lane l carries slot first + 64 j + l of every tile j.
-template <int K, int J, bool LDSQ, bool TWO, bool ESC>
+template <int K, int J, bool LDSQ, bool TWO, int FLOW>
 __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__restrict__ lq,
                                            const double *__restrict__ vcurves, int node_rel,
                                            int tile, int count, const Tile &T0, int item_smax,
@@ -362,7 +377,10 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
             L[j].qa = P.qoff1[slot] + P.age1[slot] + shift;
             L[j].qb = TWO ? P.qoff2[slot] + P.age2[slot] + shift : 0;
             L[j].rS = P.coef[3 * P.n_pad + slot];
-            if constexpr (ESC) PL[j] = pat_init(P, slot, shift, smax - 1);
+            L[j].cfb = nullptr;
+            if constexpr (FLOW == FLOW_PATTERN) PL[j] = pat_init(P, slot, shift, smax - 1);
+            if constexpr (FLOW == FLOW_TABLE)
+                L[j].cfb = P.cf_t + P.pat_code[slot] + (ptrdiff_t)shift * P.cf_cols;
 #pragma unroll
             for (int k = 0; k < K; ++k) r[j][k] = L[j].rS;
         } else {   // missing tile of a short item: an always-inactive lane
@@ -371,7 +389,8 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
             L[j].a0 = L[j].a1 = L[j].b1 = L[j].a1mb1 = L[j].rS = 0.0;
             L[j].qa = shift;
             L[j].qb = shift;
-            if constexpr (ESC) PL[j] = PatLane{0, 12, 0, 1.0, 1.0, 0};
+            L[j].cfb = FLOW == FLOW_TABLE ? P.cf_t + (ptrdiff_t)shift * P.cf_cols : nullptr;
+            if constexpr (FLOW == FLOW_PATTERN) PL[j] = PatLane{0, 12, 0, 1.0, 1.0, 0};
 #pragma unroll
             for (int k = 0; k < K; ++k) r[j][k] = 0.0;
         }
@@ -389,11 +408,11 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
         }
     }
     if (m == 1.0)
-        scalar_steps<K, J, LDSQ, TWO, false, ESC>(lq, P.q, vb, P.scen_pad, L, PL, m, smax, smin, r,
-                                                  path);
+        scalar_steps<K, J, LDSQ, TWO, false, FLOW>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m, smax,
+                                                   smin, r, path);
     else
-        scalar_steps<K, J, LDSQ, TWO, true, ESC>(lq, P.q, vb, P.scen_pad, L, PL, m, smax, smin, r,
-                                                 path);
+        scalar_steps<K, J, LDSQ, TWO, true, FLOW>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m, smax,
+                                                  smin, r, path);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         if (j < count) {
@@ -576,8 +595,8 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
 // hardware places workgroup b on XCD b mod 8), then steals from the others.
 // The read-only inputs are separate __restrict__ arguments so that the
 // compiler may read the wavefront-uniform curve values with scalar loads.
-// PAT: the portfolio has tiles of annuities with payment patterns (run with
-// one policy per lane, whatever J).
+// PAT: the portfolio has tiles whose cash flows vary in time (payment
+// patterns or cash-flow tables), run with one policy per lane whatever J.
 template <int K, int J, bool LDSQ, bool VEC, bool PAT>
 __global__ void __launch_bounds__(WG_THREADS)
 k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__restrict__ items,
@@ -612,7 +631,7 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
         T.first = wave_uniform(T.first);
         T.smax = wave_uniform(T.smax);
         T.smin = wave_uniform(T.smin);
-        T.pat = wave_uniform(T.pat);
+        T.flow = wave_uniform(T.flow);
         // Terms are bucketed, not strictly sorted: take the extremes over the
         // item's tiles.
         int smax = T.smax, smin = T.smin;
@@ -620,25 +639,28 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
             smax = max(smax, wave_uniform(tiles[tile + j].smax));
             smin = min(smin, wave_uniform(tiles[tile + j].smin));
         }
-        if (PAT && T.pat) {
+        if (PAT && T.flow != FLOW_LEVEL) {
             if constexpr (PAT) {
-                if (T.kind == KIND_SINGLE)
-                    run_scalar<K, 1, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, 1, T, T.smax,
-                                                        T.smin, sb, lane);
+                if (T.flow == FLOW_TABLE)
+                    run_scalar<K, 1, LDSQ, false, FLOW_TABLE>(P, s_q, vcurves, node_rel, tile, 1, T,
+                                                              T.smax, T.smin, sb, lane);
+                else if (T.kind == KIND_SINGLE)
+                    run_scalar<K, 1, LDSQ, false, FLOW_PATTERN>(P, s_q, vcurves, node_rel, tile, 1, T,
+                                                                T.smax, T.smin, sb, lane);
                 else if (T.kind == KIND_JOINT)
-                    run_scalar<K, 1, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, 1, T, T.smax,
-                                                       T.smin, sb, lane);
+                    run_scalar<K, 1, LDSQ, true, FLOW_PATTERN>(P, s_q, vcurves, node_rel, tile, 1, T,
+                                                               T.smax, T.smin, sb, lane);
                 else if (T.kind == KIND_REV)
                     run_vector<K, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
                 else
                     run_vector<K, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
             }
         } else if (T.kind == KIND_SINGLE) {
-            run_scalar<K, J, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, count, T, smax,
-                                                 smin, sb, lane);
+            run_scalar<K, J, LDSQ, false, FLOW_LEVEL>(P, s_q, vcurves, node_rel, tile, count, T, smax,
+                                                      smin, sb, lane);
         } else if (T.kind == KIND_JOINT) {
-            run_scalar<K, J, LDSQ, true, false>(P, s_q, vcurves, node_rel, tile, count, T, smax,
-                                                smin, sb, lane);
+            run_scalar<K, J, LDSQ, true, FLOW_LEVEL>(P, s_q, vcurves, node_rel, tile, count, T, smax,
+                                                     smin, sb, lane);
         } else if constexpr (VEC) {
             if (T.kind == KIND_REV)
                 run_vector<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);

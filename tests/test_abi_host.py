@@ -157,3 +157,26 @@ def test_representative_portfolio_law():
     assert np.all(pf.term_m == synth.LIMIT_AGE_M - youngest)
     assert abs(pf.term_m.mean() / 12 - 58) < 1.5     # the paper's average outstanding term
     assert np.all(pf.premium == 0) and np.all(pf.timing == synth.ARREARS)
+
+
+def test_cash_flow_table_checks(rr):
+    rng = np.random.default_rng(3)
+    w = synth.random_small(rng, n=30, n_steps=120, n_scen=1)
+    n_ages = w.basis.q.shape[1]
+    ok = synth.with_cash_flow_tables(rng, w.portfolio, frac=0.5, n_rows=4)
+    tab = np.flatnonzero(ok.product == synth.CF_TABLE)
+    assert tab.size >= 5
+    assert rr.check_portfolio(ok, 120, n_ages, 2) == ""
+    i = int(tab[0])
+    bad = ok.subset(np.arange(ok.n)); bad.cf_row[i] = 4
+    assert f"policy {i} cf_row 4" in rr.check_portfolio(bad, 120, n_ages, 2)
+    bad = ok.subset(np.arange(ok.n)); bad.cf_row[i] = -1
+    assert f"policy {i} cf_row -1" in rr.check_portfolio(bad, 120, n_ages, 2)
+    bad = ok.subset(np.arange(ok.n)); bad.cf = bad.cf[:, :10].copy(); bad.term_m[i] = 11
+    assert f"policy {i} term 11 exceeds cf_len 10" in rr.check_portfolio(bad, 120, n_ages, 2)
+    bad = ok.subset(np.arange(ok.n)); bad.cf[2, 7] = np.nan
+    assert "is not finite" in rr.check_portfolio(bad, 120, n_ages, 2)
+    bad = ok.subset(np.arange(ok.n)); bad.cf = None
+    assert "need cf_row and cf" in rr.check_portfolio(bad, 120, n_ages, 2)
+    bad = ok.subset(np.arange(ok.n)); bad.product[i] = 8
+    assert f"policy {i} has unknown product 8" in rr.check_portfolio(bad, 120, n_ages, 2)

@@ -173,3 +173,57 @@ def test_representative_portfolio_full_size_sampled(ctx):
     got = to_np(win["r0"])[:, idx]
     ref = oracle.reserves(b, pf.subset(idx), 0, 1, 500, 8, 12, n_threads=threads)
     assert_states_close(got, ref["r_all"], ref["gross"])
+
+
+# ---------------------------------------------------------------------------
+# Cash-flow tables (RR_CF_TABLE), alone and beside pattern and level tiles
+# ---------------------------------------------------------------------------
+def table_workload(seed, n, n_steps, n_scen, n_nodes, node_step=7, frac=0.3):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=n, n_steps=n_steps, n_scen=n_scen, n_nodes=n_nodes, shock=True)
+    pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=frac, n_rows=7)
+    pf = synth.with_payment_patterns(rng, pf, 0.4, 0.3)
+    return synth.Workload("tables", w.basis, pf, node_step_m=node_step)
+
+
+@pytest.mark.parametrize("K,J", [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (32, 1), (4, 2),
+                                 (8, 2), (16, 2), (2, 4), (4, 4), (8, 4), (16, 4)])
+def test_cash_flow_tables_with_patterns_and_level(ctx, K, J):
+    w = table_workload(800 + K + 7 * J, n=420, n_steps=100, n_scen=2 * K + 5, n_nodes=3)
+    assert (w.portfolio.product == synth.CF_TABLE).sum() > 80
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(w.portfolio)
+    ctx.set_option(1, K)
+    ctx.set_option(8, J)
+    _say(f"tables K={K} J={J}")
+    compare(ctx, w)
+
+
+def test_cash_flow_table_paths(ctx):
+    w = table_workload(900, n=150, n_steps=160, n_scen=3, n_nodes=2, node_step=12, frac=0.5)
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("table paths")
+    for node, scen in ((0, 1), (1, 2)):
+        po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=node, node_step=12)
+        po["path"].fill_(float("nan"))
+        ctx.reserve_recurrence(node, 1, scen, 1, 12, po)
+        torch.cuda.synchronize()
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=scen, node_step=12)
+        ref = oracle.reserves(b, pf, node, 1, scen, 1, 12)
+        gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+        assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
+
+
+def test_cash_flow_tables_only_full_steps(ctx):
+    """A portfolio of table policies only (600-month tables, 200 policies
+    spanning four tiles and a ragged tail), every output against the oracle."""
+    rng = np.random.default_rng(901)
+    w = synth.random_small(rng, n=200, n_steps=600, n_scen=9, n_nodes=1, products=(0,))
+    pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=1.0, n_rows=11, cf_len=600)
+    w = synth.Workload("tables only", w.basis, pf)
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(pf)
+    _say("tables only")
+    compare(ctx, w)
