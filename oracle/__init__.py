@@ -66,6 +66,13 @@ def _load():
         lib.orc_build_w.restype = ci
         lib.orc_n_states.argtypes = [ci]
         lib.orc_n_states.restype = ci
+        u64, cd = ctypes.c_uint64, ctypes.c_double
+        lib.orc_philox4x64_10.argtypes = [vp, vp, vp]
+        lib.orc_philox4x64_10.restype = None
+        lib.orc_normals.argtypes = [u64, u64, ci, ci, ci, vp]
+        lib.orc_normals.restype = None
+        lib.orc_vasicek_curves.argtypes = [cd, cd, cd, cd, vp, ci, ci, ci, u64, u64, vp, vp]
+        lib.orc_vasicek_curves.restype = ci
         _lib = lib
     return _lib
 
@@ -182,3 +189,39 @@ def node_stats(totals: np.ndarray, tail: float = 0.005):
     j = max(1, int(np.ceil(tail * K - 1e-12)))
     srt = np.sort(totals, axis=1)[:, ::-1]
     return totals.mean(axis=1), srt[:, j - 1]
+
+
+# ---------------------------------------------------------------------------
+# Scenario generation
+# ---------------------------------------------------------------------------
+def philox4x64_10(counter, key):
+    """Philox4x64-10 block of a 4-word counter under a 2-word key (uint64[4])."""
+    lib = _load()
+    c = np.ascontiguousarray(counter, np.uint64)
+    k = np.ascontiguousarray(key, np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib.orc_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def normals(key, node, scen, step):
+    """The two standard normals of (node, scenario, step)."""
+    lib = _load()
+    z = np.zeros(2)
+    lib.orc_normals(int(key[0]), int(key[1]), node, scen, step, _ptr(z))
+    return z
+
+
+def vasicek_curves(a, b, sigma, dt, r0, n_scen, n_steps, key):
+    """Exact-step Vasicek scenarios: (v[n_nodes][n_scen][n_steps] one-step
+    discount factors, r[n_nodes][n_scen][n_steps + 1] short rates)."""
+    lib = _load()
+    r0 = np.ascontiguousarray(np.atleast_1d(r0), np.float64)
+    n_nodes = r0.shape[0]
+    v = np.zeros((n_nodes, n_scen, n_steps))
+    r = np.zeros((n_nodes, n_scen, n_steps + 1))
+    rc = lib.orc_vasicek_curves(a, b, sigma, dt, _ptr(r0), n_nodes, n_scen, n_steps,
+                                int(key[0]), int(key[1]), _ptr(v), _ptr(r))
+    if rc != 0:
+        raise ValueError("orc_vasicek_curves: invalid input")
+    return v, r

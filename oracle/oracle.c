@@ -515,3 +515,97 @@ int orc_n_states(int product)
     if (orc_contract_of(product, 1, 1.0, 0.0, 0, &k)) return -1;
     return k.n_states;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Scenario generation (the interest model of Sec. 3.4 / 3.7.2, here       */
+/* Vasicek): a counter-based generator, normals, and the exact step.       */
+/* ------------------------------------------------------------------------ */
+
+/* Philox4x64-10: ten rounds of the Philox S-box on a 4 x 64-bit counter
+ * under a 2 x 64-bit key, as defined by Salmon, Moraes, Dror and Shaw
+ * ("Parallel random numbers: as easy as 1, 2, 3", SC 2011): per round the
+ * words 0 and 2 are multiplied by the two round multipliers, the high
+ * halves are xored with the other words and the key, and the key is bumped
+ * by the two Weyl increments. */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0, 1) from the top 53 bits. */
+static double orc_u01(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+/* Two independent standard normals for (node, scenario, step) by the
+ * Box-Muller transform of the first two uniforms of the Philox block with
+ * counter (step, scenario, node, 0). */
+void orc_normals(uint64_t key0, uint64_t key1, int node, int scen, int step, double z[2])
+{
+    const uint64_t ctr[4] = {(uint64_t)step, (uint64_t)scen, (uint64_t)node, 0};
+    const uint64_t key[2] = {key0, key1};
+    uint64_t x[4];
+    orc_philox4x64_10(ctr, key, x);
+    double u0 = orc_u01(x[0]), u1 = orc_u01(x[1]);
+    double rad = sqrt(-2.0 * log(u0));
+    double ang = 6.283185307179586476925286766559 * u1;   /* 2 pi u1 */
+    z[0] = rad * cos(ang);
+    z[1] = rad * sin(ang);
+}
+
+/*
+ * Vasicek short rate dr = a (b - r) dt + sigma dW, stepped exactly over dt:
+ * given r_t, (r_{t+dt}, Y_t = integral of r over the step) is Gaussian with
+ *   E r_{t+dt} = b + (r_t - b) e,            e = exp(-a dt)
+ *   E Y_t      = b dt + (r_t - b)(1 - e)/a
+ *   Var r      = sigma^2 (1 - e^2) / (2a)
+ *   Var Y      = sigma^2/a^2 (dt - 2(1 - e)/a + (1 - e^2)/(2a))
+ *   Cov(r, Y)  = sigma^2/(2a^2) (1 - e)^2
+ * sampled as r_{t+dt} = E r + sd_r z0 and Y = E Y + sd_y (rho z0 +
+ * sqrt(1 - rho^2) z1).  The one-step discount factor is v_t = exp(-Y_t).
+ * r0[node] starts node `node`.  Writes v[node][scen][step] and, if r is not
+ * NULL, r[node][scen][0..n_steps].  Returns 0, or -1 on invalid input.
+ */
+int orc_vasicek_curves(double a, double b, double sigma, double dt, const double *r0, int n_nodes,
+                       int n_scen, int n_steps, uint64_t key0, uint64_t key1, double *v, double *r)
+{
+    if (!(a > 0.0) || !(sigma >= 0.0) || !(dt > 0.0) || n_nodes < 0 || n_scen < 0 || n_steps < 0)
+        return -1;
+    double e = exp(-a * dt);
+    double var_r = sigma * sigma * (1.0 - e * e) / (2.0 * a);
+    double var_y = sigma * sigma / (a * a) * (dt - 2.0 * (1.0 - e) / a + (1.0 - e * e) / (2.0 * a));
+    double cov = sigma * sigma / (2.0 * a * a) * (1.0 - e) * (1.0 - e);
+    double sd_r = sqrt(var_r), sd_y = sqrt(var_y);
+    double rho = (sd_r > 0.0 && sd_y > 0.0) ? cov / (sd_r * sd_y) : 0.0;
+    double sd_y_perp = sd_y * sqrt(fmax(0.0, 1.0 - rho * rho));
+    for (int k = 0; k < n_nodes; ++k)
+        for (int s = 0; s < n_scen; ++s) {
+            double rt = r0[k];
+            double *vo = v + ((size_t)k * n_scen + s) * n_steps;
+            double *ro = r ? r + ((size_t)k * n_scen + s) * (n_steps + 1) : NULL;
+            if (ro) ro[0] = rt;
+            for (int t = 0; t < n_steps; ++t) {
+                double z[2];
+                orc_normals(key0, key1, k, s, t, z);
+                double y = b * dt + (rt - b) * (1.0 - e) / a + rho * sd_y * z[0] + sd_y_perp * z[1];
+                rt = b + (rt - b) * e + sd_r * z[0];
+                vo[t] = exp(-y);
+                if (ro) ro[t + 1] = rt;
+            }
+        }
+    return 0;
+}
