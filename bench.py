@@ -185,6 +185,42 @@ def surrogate_leg(rr, synth, ctx, w, exact_totals, n_val, exact_ms, steps, sync,
     }
 
 
+def generated_scenarios_leg(rr, synth, sync, steps=20):
+    """C3 with its 1,000 Vasicek scenarios generated on the device each step
+    (a fresh Philox key per step): generation alone, and generation plus the
+    recurrence, totals and tail statistic."""
+    w = synth.config_c3()
+    b, pf = w.basis, w.portfolio
+    a, mean, sig, dt = synth.VAS_A, synth.VAS_B, synth.VAS_SIGMA, 1.0 / 12.0
+    ctx = rr.Context(0)
+    try:
+        ctx.basis_generate_vasicek(b.q, b.n_scen, b.n_steps, [synth.VAS_R0], a, mean, sig, dt, (1, 0))
+        ctx.portfolio_upload(pf)
+        o = ctx.alloc_outputs(1, b.n_scen, stats=True)
+        key = [0]
+
+        def gen():
+            key[0] += 1
+            ctx.curves_generate_vasicek([synth.VAS_R0], a, mean, sig, dt, (1, key[0]))
+
+        def full():
+            gen()
+            ctx.reserve_recurrence(0, 1, 0, b.n_scen, 12, o)
+
+        for _ in range(3):
+            full()
+        sync()
+        eg = timed_steps(gen, steps, sync)
+        ef = timed_steps(full, steps, sync)
+        _, _, live, _ = scenario_step_work(pf)
+        return {"workload": w.name + ", scenarios generated on the device each step",
+                "generation_ms": 1e3 * eg / steps, "ms_per_step": 1e3 * ef / steps,
+                "valuations_per_s": live * b.n_scen / (ef / steps),
+                "generated_values": b.n_scen * b.n_steps}
+    finally:
+        ctx.close()
+
+
 def representative_leg(rr, synth, sync, steps=5):
     """The representative annuity portfolio (Sec. 5.3, Table 2): 500,000
     annuities x 1,000 Vasicek scenarios over the 756 monthly steps to the
@@ -243,6 +279,8 @@ def main():
                     help="only run a plain 1 GiB device copy (traffic counter calibration)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the timed region of the headline workload (for profiling)")
+    ap.add_argument("--generated-only", action="store_true",
+                    help="only the device-generated-scenario leg (for profiling)")
     ap.add_argument("--representative-only", action="store_true",
                     help="only the representative 500,000-annuity portfolio leg (for profiling)")
     ap.add_argument("--block-k", type=int, default=0, help="pin scenarios per lane (0 = autotune)")
@@ -276,6 +314,9 @@ def main():
     sync = torch.cuda.synchronize
     if args.representative_only:
         print(json.dumps(representative_leg(rr, synth, sync, steps=args.steps)))
+        return
+    if args.generated_only:
+        print(json.dumps(generated_scenarios_leg(rr, synth, sync, steps=args.steps)))
         return
     w = synth.config_c3()
     b, pf = w.basis, w.portfolio
@@ -407,6 +448,7 @@ def main():
                                      "live_valuations": live4 * w4.basis.n_scen,
                                      "nominal_valuations": w4.portfolio.n * w4.basis.n_nodes * w4.basis.n_scen}
         sec["representative_500k_annuities"] = representative_leg(rr, synth, sync)
+        sec["C3_device_generated_scenarios"] = generated_scenarios_leg(rr, synth, sync)
         result["secondary"] = sec
     ctx.close()
 

@@ -220,6 +220,44 @@ int rr_basis_upload(rr_ctx *ctx, const rr_basis *b);
  * paper balances uneven terms with a dynamic schedule, Sec. 5.1.1). */
 int rr_portfolio_upload(rr_ctx *ctx, const rr_portfolio *p);
 
+/*
+ * Interest scenarios generated on the device (Sec. 3.4 and 3.7.2 leave the
+ * interest model open; this is the Vasicek short rate dr = a (b - r) dt +
+ * sigma dW).  Scenario s of node k starts from r0[k]; over each step of dt
+ * years the short rate r and its integral Y are drawn from their exact joint
+ * Gaussian law given r at the start of the step, and the step's discount
+ * factor is v = exp(-Y).  The two normals of (node k, scenario s, step t) are
+ * the Box-Muller transform of the uniforms ((x >> 11) + 0.5) 2^-53 of the
+ * first two words x of the Philox4x64-10 block with counter (t, s, k, 0) under
+ * `key`, so a scenario's numbers do not depend on how many are drawn.
+ */
+typedef struct {
+    double a;            /* mean-reversion speed, > 0 */
+    double b;            /* long-run mean, finite */
+    double sigma;        /* volatility, >= 0 */
+    double dt;           /* years per step, > 0 (1/12: monthly) */
+    const double *r0;    /* host [n_nodes] short rate at the start of each node */
+    uint64_t key[2];     /* Philox4x64-10 key */
+} rr_vasicek;
+
+/* Install a basis whose curves are generated on the device: q, shock and
+ * the sizes come from b (b->v must be NULL), the curves from vs.  Otherwise
+ * as rr_basis_upload (synchronous; drops a portfolio the basis does not
+ * cover). */
+int rr_basis_generate_vasicek(rr_ctx *ctx, const rr_basis *b, const rr_vasicek *vs);
+
+/* Regenerate the installed basis's curves in place (same sizes), e.g. for the
+ * next outer node of a nested valuation: asynchronous on the context's stream;
+ * portfolio, plans and captured graphs stay valid.  Waits for the stream only
+ * when vs->r0 differs from the values of the previous generation. */
+int rr_curves_generate_vasicek(rr_ctx *ctx, const rr_vasicek *vs);
+
+/* The curves of a generator in caller-owned device memory (asynchronous):
+ * v[n_nodes][n_scen][n_steps] and, if r is not NULL, the short rates
+ * r[n_nodes][n_scen][n_steps + 1] (r[..][0] = r0). */
+int rr_vasicek_curves(rr_ctx *ctx, const rr_vasicek *vs, int32_t n_nodes, int32_t n_scen,
+                      int32_t n_steps, double *v, double *r);
+
 /* Length in doubles of the RR_OUT_PATH buffer for a node. */
 int rr_path_size(rr_ctx *ctx, int32_t node, int32_t node_step_m, int64_t *n_out);
 

@@ -17,6 +17,18 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ERANGE, RR_ESTATE = 0, -1, -2, -3, -4, -5
 SL_ANN, JL_ANN, REV_ANN, LS_ANN, TERM, ENDOW, ENDOW_ASSUR, CF_TABLE = range(8)
+
+
+class Vasicek(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("dt", ctypes.c_double), ("r0", ctypes.c_void_p), ("key", ctypes.c_uint64 * 2)]
+
+
+def vasicek_struct(a, b, sigma, dt, r0, key, keep):
+    r0 = _np(np.atleast_1d(r0), np.float64)
+    keep.append(r0)
+    k = (ctypes.c_uint64 * 2)(int(key[0]), int(key[1]))
+    return Vasicek(a, b, sigma, dt, r0.ctypes.data, k)
 ADVANCE, ARREARS = 0, 1
 HOST, DEVICE = 0, 1
 OUT_R0, OUT_TOTALS, OUT_PATH, OUT_ALL_STATES, OUT_STATS = 1, 2, 4, 8, 16
@@ -31,6 +43,7 @@ EXPORTS = (
     "rr_kernel_times", "rr_surrogate_train", "rr_surrogate_get_weights",
     "rr_surrogate_set_weights", "rr_surrogate_infer", "rr_surrogate_forward",
     "rr_surrogate_gradients", "rr_surrogate_adam_step", "rr_surrogate_features",
+    "rr_basis_generate_vasicek", "rr_curves_generate_vasicek", "rr_vasicek_curves",
 )
 
 # Surrogate dimensions (include/rr.h).
@@ -176,6 +189,9 @@ def load_library(path: str = LIB_PATH):
         "rr_surrogate_gradients": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
         "rr_surrogate_adam_step": ([vp, vp, ctypes.c_float], ctypes.c_int),
         "rr_surrogate_features": ([vp, ctypes.POINTER(Run), vp, vp, vp, vp], ctypes.c_int),
+        "rr_basis_generate_vasicek": ([vp, ctypes.POINTER(Basis), ctypes.POINTER(Vasicek)], ctypes.c_int),
+        "rr_curves_generate_vasicek": ([vp, ctypes.POINTER(Vasicek)], ctypes.c_int),
+        "rr_vasicek_curves": ([vp, ctypes.POINTER(Vasicek), i32, i32, i32, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -292,6 +308,39 @@ class Context:
         st = basis_struct(q, v, shock, keep)
         self._check(self.lib.rr_basis_upload(self.h, ctypes.byref(st)))
         self.n_nodes, self.n_scen, self.n_steps = st.n_nodes, st.n_scen, st.n_steps
+
+    def basis_generate_vasicek(self, q, n_scen, n_steps, r0, a, b, sigma, dt, key, shock=None):
+        """Install a basis (q, shock) whose curves are generated on the device:
+        len(r0) nodes x n_scen scenarios x n_steps steps."""
+        keep = []
+        q = _np(q, np.float64)
+        r0 = _np(np.atleast_1d(r0), np.float64)
+        sh = None if shock is None else _np(shock, np.float64)
+        keep.extend([q, sh])
+        bs = Basis(q.shape[0], q.shape[1], q.ctypes.data, r0.shape[0], n_scen, n_steps, None,
+                   None if sh is None else sh.ctypes.data, HOST)
+        vs = vasicek_struct(a, b, sigma, dt, r0, key, keep)
+        self._check(self.lib.rr_basis_generate_vasicek(self.h, ctypes.byref(bs), ctypes.byref(vs)))
+        self.n_nodes, self.n_scen, self.n_steps = r0.shape[0], n_scen, n_steps
+
+    def curves_generate_vasicek(self, r0, a, b, sigma, dt, key):
+        """Regenerate the installed basis's curves in place (asynchronous)."""
+        keep = []
+        vs = vasicek_struct(a, b, sigma, dt, r0, key, keep)
+        self._check(self.lib.rr_curves_generate_vasicek(self.h, ctypes.byref(vs)))
+
+    def vasicek_curves(self, n_scen, n_steps, r0, a, b, sigma, dt, key, rates=True):
+        """Device tensors v [n_nodes][n_scen][n_steps] (and r [..][n_steps + 1])."""
+        torch = self._torch
+        keep = []
+        vs = vasicek_struct(a, b, sigma, dt, r0, key, keep)
+        n_nodes = len(np.atleast_1d(r0))
+        dev = torch.device("cuda", self.device)
+        v = torch.empty((n_nodes, n_scen, n_steps), dtype=torch.float64, device=dev)
+        r = torch.empty((n_nodes, n_scen, n_steps + 1), dtype=torch.float64, device=dev) if rates else None
+        self._check(self.lib.rr_vasicek_curves(self.h, ctypes.byref(vs), n_nodes, n_scen, n_steps,
+                                               v.data_ptr(), None if r is None else r.data_ptr()))
+        return v, r
 
     def portfolio_upload(self, pf):
         keep = []

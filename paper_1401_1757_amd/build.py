@@ -23,7 +23,7 @@ DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++
                 "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
 HOST_FLAGS = ["-x", "c++", "-O2", "-fPIC", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-Wall"]
 
-DEVICE_SOURCES = ["rr_kernels.hip", "rr_kernels_pat.hip", "rr_mlp.hip"]
+DEVICE_SOURCES = ["rr_kernels.hip", "rr_kernels_pat.hip", "rr_mlp.hip", "rr_scen.hip"]
 HOST_SOURCES = ["rr_host.cpp", "rr_surrogate.cpp"]
 
 
@@ -33,19 +33,34 @@ def _sources():
     return dev, host
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    """Compile every source and link librr.so.  Always recompiles."""
+def _stale(obj: str, src: str) -> bool:
+    """The object is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    headers = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    headers += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE) if h.endswith(".h")]
+    return any(os.path.getmtime(f) > t for f in [src, *headers])
+
+
+def build(verbose: bool = False, jobs: int = 4, incremental: bool = False) -> str:
+    """Compile every source and link librr.so.  Recompiles everything unless
+    incremental, which keeps objects newer than their source and every header."""
     os.makedirs(OBJDIR, exist_ok=True)
     dev, host = _sources()
     inc = ["-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include"]
     cmds, objs = [], []
     for s in dev:
         o = os.path.join(OBJDIR, s + ".o")
-        cmds.append([HIPCC, *DEVICE_FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o])
+        src = os.path.join(CSRC, s)
+        if not incremental or _stale(o, src):
+            cmds.append([HIPCC, *DEVICE_FLAGS, *inc, "-c", src, "-o", o])
         objs.append(o)
     for s in host:
         o = os.path.join(OBJDIR, s + ".o")
-        cmds.append([HIPCC, *HOST_FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o])
+        src = os.path.join(CSRC, s)
+        if not incremental or _stale(o, src):
+            cmds.append([HIPCC, *HOST_FLAGS, *inc, "-c", src, "-o", o])
         objs.append(o)
     from concurrent.futures import ThreadPoolExecutor
 
@@ -69,5 +84,5 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print(LIB)

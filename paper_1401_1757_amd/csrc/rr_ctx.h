@@ -109,6 +109,9 @@ struct rr_ctx {
     DevBuf<double> v;                    // [n_nodes][n_steps][scen_pad]
     DevBuf<double> shock;                // [n_nodes]
     DevBuf<double> q_stage;              // [n_tables][n_ages_stage]
+    DevBuf<double> vas_work;             // normals and short rates of the generator
+    DevBuf<double> vas_r0;               // [n_nodes] start rates on the device
+    std::vector<double> vas_r0_host;     // their values (the last generation's)
     int n_ages_stage = 0;
     std::vector<double> shock_host;
 

@@ -88,16 +88,18 @@ static int fetch(rr_ctx *c, const T *src, size_t n, int mem_kind, std::vector<T>
 // ---------------------------------------------------------------------------
 // Validation (host only)
 // ---------------------------------------------------------------------------
+// v == nullptr with generated = true: the curves come from a generator.
 static std::string check_basis_arrays(int n_tables, int n_ages, const double *q, int n_nodes,
                                       int n_scen, int n_steps, const double *v,
-                                      const double *shock)
+                                      const double *shock, bool generated = false)
 {
     char b[256];
     if (n_tables < 1 || n_ages < 2) return "basis: need n_tables >= 1 and n_ages >= 2";
     if (n_nodes < 1 || n_scen < 1 || n_steps < 1) return "basis: need n_nodes, n_scen, n_steps >= 1";
     if ((long long)n_nodes * n_steps * (((long long)n_scen + 31) / 32 * 32 + 32) > (1LL << 31))
         return "basis: curve array exceeds 2^31 values";
-    if (!q || !v) return "basis: q and v must not be NULL";
+    if (!q || (!v && !generated)) return "basis: q and v must not be NULL";
+    if (v && generated) return "basis: v must be NULL when the curves are generated";
     for (long long i = 0; i < (long long)n_tables * n_ages; ++i) {
         double x = q[i];
         if (!(x >= 0.0 && x <= 1.0)) {
@@ -105,7 +107,7 @@ static std::string check_basis_arrays(int n_tables, int n_ages, const double *q,
             return b;
         }
     }
-    for (long long i = 0; i < (long long)n_nodes * n_scen * n_steps; ++i) {
+    for (long long i = 0; v && i < (long long)n_nodes * n_scen * n_steps; ++i) {
         double x = v[i];
         if (!(x > 0.0) || !std::isfinite(x)) {
             snprintf(b, sizeof b, "basis: v[%lld] = %g is not a positive finite discount factor", i, x);
@@ -392,23 +394,76 @@ static int stage_tables(rr_ctx *c)
     return RR_OK;
 }
 
-extern "C" int rr_basis_upload(rr_ctx *c, const rr_basis *b)
+// Constants of the exact Vasicek step (see rr_vasicek in rr.h) after
+// checking the parameters; r0 gets the n_nodes start rates.
+static int vasicek_params(rr_ctx *c, const rr_vasicek *vs, int n_nodes, int n_scen, int n_steps,
+                          int scen_pad, VasParams *P, std::vector<double> *r0)
 {
-    if (!c) return RR_EINVAL;
-    if (!b) return fail(c, RR_EINVAL, "basis is NULL");
-    if (b->mem_kind != RR_HOST && b->mem_kind != RR_DEVICE) return fail(c, RR_EINVAL, "bad mem_kind");
-    HIPCHK(c, hipSetDevice(c->device));
-    if (b->n_tables < 1 || b->n_ages < 2 || b->n_nodes < 1 || b->n_scen < 1 || b->n_steps < 1)
-        return fail(c, RR_EINVAL, "basis: sizes must be positive (n_ages >= 2)");
-    std::vector<double> q, v, sh;
-    int rc;
-    size_t nv = (size_t)b->n_nodes * b->n_scen * b->n_steps;
-    if ((rc = fetch(c, b->q, (size_t)b->n_tables * b->n_ages, b->mem_kind, q))) return rc;
-    if ((rc = fetch(c, b->v, nv, b->mem_kind, v))) return rc;
-    if (b->shock && (rc = fetch(c, b->shock, (size_t)b->n_nodes, b->mem_kind, sh))) return rc;
-    std::string s = check_basis_arrays(b->n_tables, b->n_ages, q.data(), b->n_nodes, b->n_scen,
-                                       b->n_steps, v.data(), b->shock ? sh.data() : nullptr);
-    if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
+    if (!vs) return fail(c, RR_EINVAL, "vasicek: parameters are NULL");
+    if (!vs->r0) return fail(c, RR_EINVAL, "vasicek: r0 must not be NULL");
+    if (!(vs->a > 0.0) || !std::isfinite(vs->a)) return fail(c, RR_EINVAL, "vasicek: a must be finite and > 0");
+    if (!std::isfinite(vs->b)) return fail(c, RR_EINVAL, "vasicek: b must be finite");
+    if (!(vs->sigma >= 0.0) || !std::isfinite(vs->sigma))
+        return fail(c, RR_EINVAL, "vasicek: sigma must be finite and >= 0");
+    if (!(vs->dt > 0.0) || !std::isfinite(vs->dt)) return fail(c, RR_EINVAL, "vasicek: dt must be finite and > 0");
+    if (n_nodes < 1 || n_scen < 1 || n_steps < 1)
+        return fail(c, RR_EINVAL, "vasicek: n_nodes, n_scen and n_steps must be >= 1");
+    if ((long long)n_nodes * scen_pad * (3LL * n_steps + 1) > (1LL << 31))
+        return fail(c, RR_EINVAL, "vasicek: more than 2^31 generated values");
+    r0->assign(vs->r0, vs->r0 + n_nodes);
+    for (int k = 0; k < n_nodes; ++k)
+        if (!std::isfinite((*r0)[k])) return fail(c, RR_EINVAL, "vasicek: r0[%d] is not finite", k);
+    const double a = vs->a, sg = vs->sigma, dt = vs->dt;
+    const double e = std::exp(-a * dt);
+    const double var_r = sg * sg * (1.0 - e * e) / (2.0 * a);
+    const double var_y =
+        std::max(0.0, sg * sg / (a * a) * (dt - 2.0 * (1.0 - e) / a + (1.0 - e * e) / (2.0 * a)));
+    const double cov = sg * sg / (2.0 * a * a) * (1.0 - e) * (1.0 - e);
+    const double sd_r = std::sqrt(var_r), sd_y = std::sqrt(var_y);
+    const double rho = (sd_r > 0.0 && sd_y > 0.0) ? cov / (sd_r * sd_y) : 0.0;
+    P->b = vs->b;
+    P->dt = dt;
+    P->e = e;
+    P->om = (1.0 - e) / a;
+    P->sd_r = sd_r;
+    P->rho_sd_y = rho * sd_y;
+    P->sd_y_perp = sd_y * std::sqrt(std::max(0.0, 1.0 - rho * rho));
+    P->key0 = vs->key[0];
+    P->key1 = vs->key[1];
+    P->n_nodes = n_nodes;
+    P->n_scen = n_scen;
+    P->n_steps = n_steps;
+    P->scen_pad = scen_pad;
+    return RR_OK;
+}
+
+// Enqueue a generation: start rates to the device (waiting for the stream
+// first if they change while earlier work may still read them), the work
+// buffer sized, then the kernels.
+static int enqueue_vasicek(rr_ctx *c, const VasParams &P, const std::vector<double> &r0, double *v,
+                           int month_major, double *r_out)
+{
+    const size_t need = vasicek_work_doubles(P.n_nodes, P.n_scen, P.n_steps, P.scen_pad);
+    const bool new_r0 = r0 != c->vas_r0_host;
+    if (need > c->vas_work.n || new_r0 || r0.size() > c->vas_r0.n)
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, c->vas_work.alloc(need));
+    if (new_r0 || r0.size() > c->vas_r0.n) {
+        HIPCHK(c, c->vas_r0.alloc(r0.size()));
+        HIPCHK(c, hipMemcpy(c->vas_r0.p, r0.data(), r0.size() * sizeof(double), hipMemcpyHostToDevice));
+        c->vas_r0_host = r0;
+    }
+    HIPCHK(c, launch_vasicek(P, c->vas_r0.p, c->vas_work.p, v, month_major, r_out, c->stream));
+    return RR_OK;
+}
+
+// Shared tail of rr_basis_upload and rr_basis_generate_vasicek: install the
+// checked mortality part and the sizes, then the curves from the host copy
+// `v` (scenario-major) or from the generator.
+static int install_basis(rr_ctx *c, const rr_basis *b, std::vector<double> &q,
+                         const std::vector<double> &sh, const std::vector<double> *v,
+                         const VasParams *gen, const std::vector<double> *gen_r0)
+{
     // A loaded portfolio that the new basis does not cover is dropped.
     bool keep_pf = c->has_pf;
     if (keep_pf) {
@@ -433,13 +488,21 @@ extern "C" int rr_basis_upload(rr_ctx *c, const rr_basis *b)
     c->q_host.swap(q);
     c->shock_host.assign((size_t)b->n_nodes, 1.0);
     if (b->shock) c->shock_host = sh;
-    // curves: upload as given, transpose to month-major on the device
-    DevBuf<double> tmp;
-    HIPCHK(c, tmp.alloc(nv));
-    HIPCHK(c, hipMemcpy(tmp.p, v.data(), nv * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(c, c->v.alloc((size_t)b->n_nodes * b->n_steps * c->scen_pad));
-    HIPCHK(c, launch_transpose_curves(tmp.p, c->v.p, b->n_nodes, b->n_scen, b->n_steps, c->scen_pad,
-                                      c->stream));
+    int rc;
+    if (v) {   // curves as given, transposed to month-major on the device
+        const size_t nv = v->size();
+        DevBuf<double> tmp;
+        HIPCHK(c, tmp.alloc(nv));
+        HIPCHK(c, hipMemcpy(tmp.p, v->data(), nv * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, launch_transpose_curves(tmp.p, c->v.p, b->n_nodes, b->n_scen, b->n_steps,
+                                          c->scen_pad, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        VasParams P = *gen;
+        P.scen_pad = c->scen_pad;
+        if ((rc = enqueue_vasicek(c, P, *gen_r0, c->v.p, 1, nullptr))) return rc;
+    }
     HIPCHK(c, c->shock.alloc((size_t)b->n_nodes));
     HIPCHK(c, hipMemcpy(c->shock.p, c->shock_host.data(), sizeof(double) * b->n_nodes,
                         hipMemcpyHostToDevice));
@@ -450,7 +513,75 @@ extern "C" int rr_basis_upload(rr_ctx *c, const rr_basis *b)
     return RR_OK;
 }
 
+extern "C" int rr_basis_upload(rr_ctx *c, const rr_basis *b)
+{
+    if (!c) return RR_EINVAL;
+    if (!b) return fail(c, RR_EINVAL, "basis is NULL");
+    if (b->mem_kind != RR_HOST && b->mem_kind != RR_DEVICE) return fail(c, RR_EINVAL, "bad mem_kind");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (b->n_tables < 1 || b->n_ages < 2 || b->n_nodes < 1 || b->n_scen < 1 || b->n_steps < 1)
+        return fail(c, RR_EINVAL, "basis: sizes must be positive (n_ages >= 2)");
+    if (!b->q || !b->v) return fail(c, RR_EINVAL, "basis: q and v must not be NULL");
+    std::vector<double> q, v, sh;
+    int rc;
+    size_t nv = (size_t)b->n_nodes * b->n_scen * b->n_steps;
+    if ((rc = fetch(c, b->q, (size_t)b->n_tables * b->n_ages, b->mem_kind, q))) return rc;
+    if ((rc = fetch(c, b->v, nv, b->mem_kind, v))) return rc;
+    if (b->shock && (rc = fetch(c, b->shock, (size_t)b->n_nodes, b->mem_kind, sh))) return rc;
+    std::string s = check_basis_arrays(b->n_tables, b->n_ages, q.data(), b->n_nodes, b->n_scen,
+                                       b->n_steps, v.data(), b->shock ? sh.data() : nullptr);
+    if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
+    return install_basis(c, b, q, sh, &v, nullptr, nullptr);
+}
 
+extern "C" int rr_basis_generate_vasicek(rr_ctx *c, const rr_basis *b, const rr_vasicek *vs)
+{
+    if (!c) return RR_EINVAL;
+    if (!b) return fail(c, RR_EINVAL, "basis is NULL");
+    if (b->mem_kind != RR_HOST && b->mem_kind != RR_DEVICE) return fail(c, RR_EINVAL, "bad mem_kind");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (b->n_tables < 1 || b->n_ages < 2 || b->n_nodes < 1 || b->n_scen < 1 || b->n_steps < 1)
+        return fail(c, RR_EINVAL, "basis: sizes must be positive (n_ages >= 2)");
+    if (!b->q) return fail(c, RR_EINVAL, "basis: q must not be NULL");
+    if (b->v) return fail(c, RR_EINVAL, "basis: v must be NULL when the curves are generated");
+    std::vector<double> q, sh, r0;
+    int rc;
+    if ((rc = fetch(c, b->q, (size_t)b->n_tables * b->n_ages, b->mem_kind, q))) return rc;
+    if (b->shock && (rc = fetch(c, b->shock, (size_t)b->n_nodes, b->mem_kind, sh))) return rc;
+    std::string s = check_basis_arrays(b->n_tables, b->n_ages, q.data(), b->n_nodes, b->n_scen,
+                                       b->n_steps, nullptr, b->shock ? sh.data() : nullptr, true);
+    if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
+    VasParams P;
+    const int scen_pad = (b->n_scen + 31) / 32 * 32 + 32;
+    if ((rc = vasicek_params(c, vs, b->n_nodes, b->n_scen, b->n_steps, scen_pad, &P, &r0))) return rc;
+    return install_basis(c, b, q, sh, nullptr, &P, &r0);
+}
+
+extern "C" int rr_curves_generate_vasicek(rr_ctx *c, const rr_vasicek *vs)
+{
+    if (!c) return RR_EINVAL;
+    if (!c->has_basis) return fail(c, RR_ESTATE, "no basis installed");
+    HIPCHK(c, hipSetDevice(c->device));
+    VasParams P;
+    std::vector<double> r0;
+    int rc;
+    if ((rc = vasicek_params(c, vs, c->n_nodes, c->n_scen, c->n_steps, c->scen_pad, &P, &r0))) return rc;
+    return enqueue_vasicek(c, P, r0, c->v.p, 1, nullptr);
+}
+
+extern "C" int rr_vasicek_curves(rr_ctx *c, const rr_vasicek *vs, int32_t n_nodes, int32_t n_scen,
+                                 int32_t n_steps, double *v, double *r)
+{
+    if (!c) return RR_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    VasParams P;
+    std::vector<double> r0;
+    int rc;
+    const int scen_pad = (n_scen + 63) / 64 * 64;
+    if ((rc = vasicek_params(c, vs, n_nodes, n_scen, n_steps, scen_pad, &P, &r0))) return rc;
+    if (!v) return fail(c, RR_EINVAL, "vasicek: v must not be NULL");
+    return enqueue_vasicek(c, P, r0, v, 0, r);
+}
 
 extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
 {

@@ -124,6 +124,21 @@ hipError_t launch_fill(double *dst, long long n, double value, hipStream_t strea
 hipError_t launch_fill_int(int *dst, int n, int value, hipStream_t stream);
 hipError_t launch_transpose_curves(const double *src, double *dst, int n_nodes, int n_scen,
                                    int n_steps, int scen_pad, hipStream_t stream);
+// Vasicek scenario generation (rr_scen.hip).  Constants of the exact step
+// (e = exp(-a dt), om = (1 - e)/a, the standard deviations and the
+// correlation part) are computed on the host.
+struct VasParams {
+    double b, dt, e, om, sd_r, rho_sd_y, sd_y_perp;
+    unsigned long long key0, key1;
+    int n_nodes, n_scen, n_steps, scen_pad;
+};
+// work: vasicek_work_doubles(...) doubles (normals and short rates, month-
+// major with stride scen_pad); r0: device [n_nodes]; v: month-major with
+// stride scen_pad (the library's curves) or [node][scen][step]; r_out:
+// [node][scen][step + 1] or null.
+hipError_t launch_vasicek(const VasParams &P, const double *r0, double *work, double *v,
+                          int month_major, double *r_out, hipStream_t stream);
+size_t vasicek_work_doubles(int n_nodes, int n_scen, int n_steps, int scen_pad);
 int max_lds_tables_doubles();
 bool supported_k(int K);
 bool supported_kj(int K, int J);   // (scenarios, policies) per lane
