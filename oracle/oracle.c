@@ -53,7 +53,8 @@
 /* Product codes (input format). */
 enum {
     O_SL_ANN = 0, O_JL_ANN = 1, O_REV_ANN = 2, O_LS_ANN = 3,
-    O_TERM = 4, O_ENDOW = 5, O_ENDOW_ASSUR = 6, O_CF_TABLE = 7, O_N_PRODUCTS = 8
+    O_TERM = 4, O_ENDOW = 5, O_ENDOW_ASSUR = 6, O_CF_TABLE = 7,
+    O_JL_ENDOW = 8, O_JL_ASSUR1 = 9, O_JL_ASSUR2 = 10, O_N_PRODUCTS = 11
 };
 
 #define ORC_MAX_STATES 9
@@ -225,6 +226,20 @@ int orc_contract_of(int product, int timing, double amount, double premium,
         k->n_lives = 2; k->life_model = 2; k->n_states = 4;
         k->c_ann[0] = pay; k->c_ann[1] = pay; k->c_ann[2] = pay;
         break;
+    case O_JL_ENDOW:     /* Sec. 4.2.2: two-life pure endowment, boundary (1, 0, 0, 0) x SA */
+        k->n_lives = 2; k->life_model = 2; k->n_states = 4;
+        k->boundary[0] = sa;
+        break;
+    case O_JL_ASSUR1:    /* Sec. 4.2.3, 9-state model: benefit on the first death,
+                            c = (0, 1, 0, 1, 1, 0, 0, 0, 0) x SA */
+        k->n_lives = 2; k->life_model = 3; k->n_states = 9;
+        k->c_ben[1] = sa; k->c_ben[3] = sa; k->c_ben[4] = sa;
+        break;
+    case O_JL_ASSUR2:    /* Sec. 4.2.3: benefit on the second death,
+                            c = (0, 0, 0, 0, 1, 1, 0, 1, 0) x SA */
+        k->n_lives = 2; k->life_model = 3; k->n_states = 9;
+        k->c_ben[4] = sa; k->c_ben[5] = sa; k->c_ben[7] = sa;
+        break;
     case O_CF_TABLE:     /* single life, c_t = amount x table value, at f = 1
                             (Sec. 4.4: c_t holds the nominal amounts) */
         k->n_lives = 1; k->life_model = 2; k->n_states = 2;
@@ -345,7 +360,8 @@ static int validate(const orc_basis *b, const orc_portfolio *p)
             if (p->term[i] > p->cf_len) return -1;
         }
         int two = p->product[i] == O_JL_ANN || p->product[i] == O_REV_ANN ||
-                  p->product[i] == O_LS_ANN;
+                  p->product[i] == O_LS_ANN || p->product[i] == O_JL_ENDOW ||
+                  p->product[i] == O_JL_ASSUR1 || p->product[i] == O_JL_ASSUR2;
         if (two) {
             if (p->age2[i] < 0 || p->age2[i] + p->term[i] > b->n_ages - 1) return -1;
             if (p->table2[i] < 0 || p->table2[i] >= b->n_tables) return -1;
@@ -357,7 +373,8 @@ static int validate(const orc_basis *b, const orc_portfolio *p)
 /*
  * Reserves of every policy at nodes [node0, node0+nnode) and scenarios
  * [scen0, scen0+nscen).
- *   r_all  [nnode][n][nscen][4]  reserve vector at t = 0 (states >= n_states: 0)
+ *   r_all  [nnode][n][nscen][4]  reserve vector at t = 0 (states >= n_states: 0;
+ *                                two-life 9-state models: states 0, 2, 6, 8)
  *   gross  [nnode][n][nscen]     PV(benefits) + PV(premiums), state 0 (or NULL)
  *   totals [nnode][nscen]        sum over live policies of state-0 reserves
  *   gross_totals [nnode][nscen]  same for gross (or NULL)
@@ -392,7 +409,14 @@ int orc_reserves(const orc_basis *b, const orc_portfolio *p, int node0, int nnod
                 if (S <= 0) { r0s[o] = 0.0; g0s[o] = 0.0; if (gross) gross[o] = 0.0; continue; }
                 const double *vc = b->v + ((size_t)node * b->n_scen + (scen0 + s)) * b->n_steps;
                 recurrence_one(b, p, i, &k, node, shift, S, vc, r0, NULL);
-                if (ro) for (int j = 0; j < k.n_states && j < ORC_OUT_STATES; ++j) ro[j] = r0[j];
+                if (ro && k.n_states == 9) {
+                    /* two-life 3-state models in the 4-state labelling (both
+                     * alive, x only, y only, none): the dead states 2, 6, 8
+                     * (the died-in-step states carry the same reserves) */
+                    ro[0] = r0[0]; ro[1] = r0[2]; ro[2] = r0[6]; ro[3] = r0[8];
+                } else if (ro) {
+                    for (int j = 0; j < k.n_states && j < ORC_OUT_STATES; ++j) ro[j] = r0[j];
+                }
                 r0s[o] = r0[0];
                 if (gross || gross_totals) {
                     recurrence_one(b, p, i, &kg, node, shift, S, vc, g0, NULL);

@@ -44,7 +44,11 @@ ENDOW = 5         # pure endowment (Sec. 4.1.2)
 ENDOW_ASSUR = 6   # endowment assurance: term assurance + pure endowment
 N_PRODUCTS = 7    # products with closed-form cash flows (0..6)
 CF_TABLE = 7      # single life, cash flows amount x cf[row][t] from a table (Sec. 4.4)
-TWO_LIFE = (JL_ANN, REV_ANN, LS_ANN)
+JL_ENDOW = 8      # two-life pure endowment: SA at maturity if both alive (Sec. 4.2.2)
+JL_ASSUR1 = 9     # two-life term assurance, SA on the first death (9-state model, Sec. 4.2.3)
+JL_ASSUR2 = 10    # two-life term assurance, SA on the second death (Sec. 4.2.3)
+TWO_LIFE_INS = (JL_ENDOW, JL_ASSUR1, JL_ASSUR2)
+TWO_LIFE = (JL_ANN, REV_ANN, LS_ANN, 8, 9, 10)   # with the two-life endowment and assurances
 
 ADVANCE = 0       # annuity paid at the start of each month (f = 0)
 ARREARS = 1       # annuity paid at the end of each month (f = 1)

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from synth import (ADVANCE, ARREARS, CF_TABLE, ENDOW, ENDOW_ASSUR, JL_ANN, LS_ANN,
+from synth import (ADVANCE, ARREARS, CF_TABLE, ENDOW, ENDOW_ASSUR, JL_ASSUR1, JL_ASSUR2, JL_ENDOW, JL_ANN, LS_ANN,
                    REV_ANN, SL_ANN, TERM, Basis, Portfolio)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -338,7 +338,7 @@ def test_oracle_rejects_invalid_input():
     with pytest.raises(ValueError):
         oracle.reserves(b, make_pf([SL_ANN], 700, 601))
     with pytest.raises(ValueError):
-        oracle.reserves(b, make_pf([9], 700, 10))
+        oracle.reserves(b, make_pf([11], 700, 10))
     with pytest.raises(ValueError):
         oracle.reserves(b, make_pf([SL_ANN], N_AGES - 5, 10))
 
@@ -576,3 +576,81 @@ def test_cash_flow_table_node_shift_equals_path(step):
     for k in range(4):
         for i in range(pf.n):
             assert full["r_all"][k, i, 0, 0] == path[off[i] + step * k]
+
+
+# --------------------------------------------------------------------------
+# Two-life endowment and assurances (Sec. 4.2.2, 4.2.3; 9-state Kronecker W)
+# --------------------------------------------------------------------------
+def _two(product, q2, premium=0.0, S=240, amount=1000.0, age1=700, age2=650, v=None):
+    """Life 1 on GM, life 2 on table 1 = q2 (scalar or table)."""
+    q = np.vstack([gm(1.0), np.broadcast_to(np.asarray(q2, float), (N_AGES,))])
+    b = basis(q, np.full(600, V_FLAT) if v is None else v)
+    pf = make_pf([product], age1, S, amount=amount, premium=premium, age2=age2, table1=0, table2=1)
+    return b, pf
+
+
+def test_two_life_reduce_to_single_life_when_life_two_never_dies():
+    for two, one in ((JL_ENDOW, ENDOW), (JL_ASSUR1, TERM)):
+        b, pf2 = _two(two, 0.0, premium=3.0)
+        pf1 = make_pf([one], 700, 240, amount=1000.0, premium=3.0)
+        np.testing.assert_allclose(r0(b, pf2)[:, 0], r0(b, pf1)[:, 0], rtol=1e-13)
+
+
+def test_second_death_assurance_is_single_life_when_life_two_dies_at_once():
+    b, pf2 = _two(JL_ASSUR2, 1.0)
+    pf1 = make_pf([TERM], 700, 240, amount=1000.0)
+    np.testing.assert_allclose(r0(b, pf2)[:, 0], r0(b, pf1)[:, 0], rtol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_first_plus_second_death_equals_two_single_life_assurances(seed):
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(0.0, 0.05, (2, N_AGES))
+    v = rng.uniform(0.99, 1.0, (3, 300))
+    b = Basis(q=q, v=v[None])
+    mk = lambda prod, a1, t1: make_pf([prod], a1, 300, amount=500.0, age2=620, table1=t1, table2=1)
+    first = oracle.reserves(b, mk(JL_ASSUR1, 710, 0))["r_all"][0, 0, :, 0]
+    second = oracle.reserves(b, mk(JL_ASSUR2, 710, 0))["r_all"][0, 0, :, 0]
+    tx = oracle.reserves(b, make_pf([TERM], 710, 300, amount=500.0, table1=0))["r_all"][0, 0, :, 0]
+    ty = oracle.reserves(b, make_pf([TERM], 620, 300, amount=500.0, table1=1))["r_all"][0, 0, :, 0]
+    np.testing.assert_allclose(first + second, tx + ty, rtol=1e-12)
+
+
+def test_second_death_states_are_the_single_life_assurances():
+    """The reserve with one life already dead is the other life's assurance."""
+    rng = np.random.default_rng(3)
+    q = rng.uniform(0.0, 0.05, (2, N_AGES))
+    b = basis(q, rng.uniform(0.99, 1.0, 300))
+    pf = make_pf([JL_ASSUR2], 710, 300, amount=500.0, age2=620, table1=0, table2=1)
+    r = oracle.reserves(b, pf)["r_all"][0, 0, 0]
+    tx = r0(b, make_pf([TERM], 710, 300, amount=500.0, table1=0))[0, 0]
+    ty = r0(b, make_pf([TERM], 620, 300, amount=500.0, table1=1))[0, 0]
+    np.testing.assert_allclose([r[1], r[2], r[3]], [tx, ty, 0.0], rtol=1e-13, atol=1e-12)
+
+
+def test_joint_endowment_brute_force():
+    rng = np.random.default_rng(4)
+    q = rng.uniform(0.0, 0.05, (2, N_AGES))
+    v = rng.uniform(0.99, 1.0, 300)
+    b = basis(q, v)
+    S = 180
+    pf = make_pf([JL_ENDOW], 700, S, amount=800.0, age2=640, table1=0, table2=1)
+    want = 800.0 * np.prod(v[:S]) * np.prod(1 - q[0, 700:700 + S]) * np.prod(1 - q[1, 640:640 + S])
+    np.testing.assert_allclose(r0(b, pf)[0, 0], want, rtol=1e-13)
+
+
+@pytest.mark.parametrize("product", [JL_ENDOW, JL_ASSUR1, JL_ASSUR2])
+def test_two_life_insurance_recurrence_equals_summation(product):
+    rng = np.random.default_rng(product)
+    w = synth.random_small(rng, n=6, n_steps=40, n_scen=2, n_nodes=2, shock=True,
+                           products=(product,))
+    b, pf = w.basis, w.portfolio
+    for node in range(2):
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=1, node_step=5)
+        for i in range(pf.n):
+            if int(pf.term_m[i]) - 5 * node <= 0:
+                continue
+            summ = oracle.reserve_path_summation(b, pf, i, node=node, scen=1, node_step=5)
+            scale = np.abs(summ).max() + 1e-300
+            np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=0,
+                                       atol=1e-12 * scale)
