@@ -56,6 +56,13 @@ def scenario_step_work(pf, node=0, node_step=12):
     ls = prod == synth.LS_ANN
     flops[ls] = (6 + np.where(prem | ~arrears, 2, 1) + 2 * (2 + np.where(~arrears, 2, 1)))[ls]
     ops[ls] = 8
+    # two-life endowment / first-death assurance: scalar chains; second death: 3-vector
+    jl_end, jl_a1, jl_a2 = prod == synth.JL_ENDOW, prod == synth.JL_ASSUR1, prod == synth.JL_ASSUR2
+    flops[jl_end] = (1 + np.where(prem, 2, 1))[jl_end]
+    flops[jl_a1] = (2 + np.where(prem, 2, 1))[jl_a1]
+    ops[jl_end | jl_a1] = 2
+    flops[jl_a2] = (6 + np.where(prem, 2, 1) + 2 * 3)[jl_a2]
+    ops[jl_a2] = 8
     return float((flops * S).sum()), float((ops * S).sum()), int((S > 0).sum()), int(S.sum())
 
 

@@ -74,6 +74,15 @@ typedef struct rr_ctx rr_ctx;
 #define RR_CF_TABLE     7  /* one life, 2-state model; pays amount x cf[cf_row][T] at the end of
                               month T (months since node 0) if alive, level premium in advance,
                               r_S = 0 (Sec. 4.4: c_t holds the nominal amounts) */
+#define RR_JL_ENDOW     8  /* two-life pure endowment: SA at the end of the term if both lives are
+                              alive, r_S = (SA, 0, 0, 0) (Sec. 4.2.2) */
+#define RR_JL_ASSUR1    9  /* two-life term assurance, SA at the end of the month of the first
+                              death, 9-state model, c = (0,1,0,1,1,0,0,0,0) SA (Sec. 4.2.3) */
+#define RR_JL_ASSUR2   10  /* two-life term assurance, SA at the end of the month of the second
+                              death, c = (0,0,0,0,1,1,0,1,0) SA (Sec. 4.2.3).  Premiums of the
+                              two-life products are paid while both lives are alive.  With
+                              RR_OUT_ALL_STATES the 9-state reserves are reported as (both alive,
+                              life 1 only, life 2 only, none). */
 
 #define RR_ADVANCE 0       /* annuity paid at the start of each month (f = 0) */
 #define RR_ARREARS 1       /* annuity paid at the end of each month (f = 1) */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ERANGE, RR_ESTATE = 0, -1, -2, -3, -4, -5
 SL_ANN, JL_ANN, REV_ANN, LS_ANN, TERM, ENDOW, ENDOW_ASSUR, CF_TABLE = range(8)
+JL_ENDOW, JL_ASSUR1, JL_ASSUR2 = 8, 9, 10
 
 
 class Vasicek(ctypes.Structure):

@@ -46,15 +46,22 @@ static void set_msg(char *msg, size_t len, const std::string &s)
 
 static bool is_two_life(int product)
 {
-    return product == RR_JL_ANN || product == RR_REV_ANN || product == RR_LS_ANN;
+    return product == RR_JL_ANN || product == RR_REV_ANN || product == RR_LS_ANN ||
+           product == RR_JL_ENDOW || product == RR_JL_ASSUR1 || product == RR_JL_ASSUR2;
 }
 
+// State model after the zero-reserve states are removed (Sec. 3.6.4): the
+// first-death assurance and the two-life endowment keep only state 00, the
+// second-death assurance keeps 00 and the two one-life-dead states.
 static int kind_of(int product)
 {
     switch (product) {
-    case RR_JL_ANN: return KIND_JOINT;
+    case RR_JL_ANN:
+    case RR_JL_ENDOW:
+    case RR_JL_ASSUR1: return KIND_JOINT;
     case RR_REV_ANN: return KIND_REV;
-    case RR_LS_ANN: return KIND_LAST;
+    case RR_LS_ANN:
+    case RR_JL_ASSUR2: return KIND_LAST;
     default: return KIND_SINGLE;
     }
 }
@@ -148,7 +155,7 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
         return "portfolio: product, age1_m, term_m, table1 and amount must not be NULL";
     for (int i = 0; i < n; ++i) {
         int pr = product[i];
-        if (pr < RR_SL_ANN || pr > RR_CF_TABLE) {
+        if (pr < RR_SL_ANN || pr > RR_JL_ASSUR2) {
             snprintf(b, sizeof b, "portfolio: policy %d has unknown product %d", i, pr);
             return b;
         }
@@ -762,6 +769,18 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
             break;
         case RR_CF_TABLE:      // the survival cash flows come from the table
             C(0, j) = -P;
+            break;
+        case RR_JL_ENDOW:
+            C(0, j) = -P;
+            C(3, j) = amount[u];
+            break;
+        case RR_JL_ASSUR1:     // c = p a1 + (1 - p) b1 with p = px py
+            C(0, j) = -P;
+            C(2, j) = amount[u];
+            break;
+        case RR_JL_ASSUR2:
+            C(0, j) = -P;
+            C(6, j) = amount[u];
             break;
         case RR_REV_ANN:
             C(0, j) = -P;

@@ -11,14 +11,16 @@ namespace rr {
 // removed).  Every policy in a tile shares its model.
 enum Kind : int {
     KIND_SINGLE = 0,   // one life, scalar reserve (annuity, assurance, endowment)
-    KIND_JOINT = 1,    // two lives, joint-life annuity: scalar reserve, p = px * py
+    KIND_JOINT = 1,    // two lives, scalar reserve in state 00, p = px * py (joint-life
+                       // annuity, two-life endowment, first-death assurance)
     KIND_REV = 2,      // two lives, states {00, 10} of the 4-state model
-    KIND_LAST = 3,     // two lives, states {00, 01, 10}
+    KIND_LAST = 3,     // two lives, states {00, 01, 10} (last-survivor annuity,
+                       // second-death assurance)
     N_KINDS = 4
 };
 
 constexpr int TILE = 64;          // policies per tile = lanes per wavefront
-constexpr int N_COEF = 6;         // per-policy cash-flow coefficients
+constexpr int N_COEF = 7;         // per-policy cash-flow coefficients
 constexpr int MAX_QUEUES = 8;     // one work queue per XCD
 #ifndef RR_WG_THREADS
 #define RR_WG_THREADS 256
@@ -34,6 +36,7 @@ constexpr int WG_THREADS = RR_WG_THREADS;   // wavefronts per workgroup x 64
 //  KIND_REV / KIND_LAST:      0/1: advance/arrears amount in state 00
 //                             2/3: advance/arrears amount in state 01
 //                             4/5: advance/arrears amount in state 10
+//                             6: KIND_LAST: benefit on the second death (end of its step)
 
 // How a tile's cash flows vary in time.  Tiles other than level ones run
 // one tile per item.

@@ -196,9 +196,10 @@ __device__ __forceinline__ double pat_factor(PatLane &pl, int t)
 
 // Scalar-reserve models: one life (annuity, term assurance, endowment,
 // endowment assurance; Sec. 4.1 with the zero-reserve states removed) and the
-// joint-life annuity (Sec. 4.2.1 b: only state 00 carries a reserve, and its
-// one-step survival probability is px * py).  Per step and scenario:
-//   r <- a0 + v * (p * r + c),  c = p * a1 + q * b1 = b1 + p * (a1 - b1).
+// two-life models whose only reserve is state 00 (joint-life annuity, Sec.
+// 4.2.1 b; two-life endowment, Sec. 4.2.2; first-death assurance, Sec. 4.2.3),
+// with one-step survival probability p = px * py.  Per step and scenario:
+//   r <- a0 + v * (p * r + c),  c = p * a1 + (1 - p) * b1 = b1 + p * (a1 - b1).
 // Each lane carries J policies (one per tile of the item) x K scenarios.
 // FLOW_PATTERN: annuities with a payment pattern (J = 1; no death benefit),
 // whose a0 and a1 at step t are the level amounts times F of the payment
@@ -234,7 +235,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
             c = p * cv;
             a0 = l.a0;
         } else {
-            c = TWO ? p * l.a1 : fma(p, l.a1mb1, l.b1);
+            c = fma(p, l.a1mb1, l.b1);   // p a1 + (1 - p) b1: arrears amount, death benefit
             a0 = l.a0;
         }
     };
@@ -438,7 +439,7 @@ template <int K, bool LDSQ, bool LAST, bool SHOCK, bool ESC>
 __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
                                              const double *__restrict__ gq,
                                              const double *__restrict__ vb, int stride, int qa,
-                                             int qb, double m, const double (&cf)[6], PatLane &pl,
+                                             int qb, double m, const double (&cf)[7], PatLane &pl,
                                              int S, int smax, int smin, double (&r0)[K],
                                              double (&r1)[K], double (&r2)[K], double *path)
 {
@@ -451,10 +452,14 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
         const double qx = 1.0 - px, qy = 1.0 - py;
         const double w00 = px * py, w10 = qx * py;
         const double w01 = px * qy;
+        // y-independent terms: arrears amounts and, for LAST, the benefit d
+        // paid on the second death (from 00 both die: qx qy; from 01 x dies:
+        // qx; from 10 y dies: qy); d = 0 leaves every value unchanged.
+        const double d = cf[6];
         double cw0 = fma(w10, c10r, w00 * c00r);
-        if constexpr (LAST) cw0 = fma(w01, c01r, cw0);
-        const double cw1 = px * c01r;
-        const double cw2 = py * c10r;
+        if constexpr (LAST) cw0 = fma(qx * qy, d, fma(w01, c01r, cw0));
+        const double cw1 = LAST ? fma(qx, d, px * c01r) : px * c01r;
+        const double cw2 = LAST ? fma(qy, d, py * c10r) : py * c10r;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double a = fma(w00, r0[k], cw0);
@@ -559,9 +564,10 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
     const int smax = T.smax - shift;
     const int smin = max(T.smin - shift, 0);
     const double m = P.shock[node];
-    double cf[6];
+    double cf[7];
 #pragma unroll
     for (int j = 0; j < 6; ++j) cf[j] = P.coef[j * P.n_pad + slot];
+    cf[6] = LAST ? P.coef[6 * P.n_pad + slot] : 0.0;
     const int qa = P.qoff1[slot] + P.age1[slot] + shift;
     const int qb = P.qoff2[slot] + P.age2[slot] + shift;
     const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);

@@ -56,7 +56,7 @@ def test_portfolio_checks(rr):
     cases = {
         "term": ("term_m", 7, 601, "policy 7 term 601"),
         "term0": ("term_m", 3, 0, "policy 3 term 0"),
-        "product": ("product", 11, 9, "policy 11 has unknown product 9"),
+        "product": ("product", 11, 12, "policy 11 has unknown product 12"),
         "age": ("age1_m", 5, n_ages, "policy 5 age"),
         "table": ("table1", 2, 3, "policy 2 table1 3"),
         "timing": ("timing", 9, 2, "policy 9 timing 2"),
@@ -178,5 +178,5 @@ def test_cash_flow_table_checks(rr):
     assert "is not finite" in rr.check_portfolio(bad, 120, n_ages, 2)
     bad = ok.subset(np.arange(ok.n)); bad.cf = None
     assert "need cf_row and cf" in rr.check_portfolio(bad, 120, n_ages, 2)
-    bad = ok.subset(np.arange(ok.n)); bad.product[i] = 8
-    assert f"policy {i} has unknown product 8" in rr.check_portfolio(bad, 120, n_ages, 2)
+    bad = ok.subset(np.arange(ok.n)); bad.product[i] = 11
+    assert f"policy {i} has unknown product 11" in rr.check_portfolio(bad, 120, n_ages, 2)

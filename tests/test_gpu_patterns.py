@@ -227,3 +227,59 @@ def test_cash_flow_tables_only_full_steps(ctx):
     ctx.portfolio_upload(pf)
     _say("tables only")
     compare(ctx, w)
+
+
+# ---------------------------------------------------------------------------
+# Two-life endowment and first/second-death assurances (Sec. 4.2.2, 4.2.3)
+# ---------------------------------------------------------------------------
+TWO_LIFE_INS = (synth.JL_ENDOW, synth.JL_ASSUR1, synth.JL_ASSUR2)
+
+
+@pytest.mark.parametrize("product", TWO_LIFE_INS)
+def test_two_life_insurance_all_states(ctx, product):
+    rng = np.random.default_rng(1000 + product)
+    w = synth.random_small(rng, n=200, n_steps=150, n_scen=11, n_nodes=2, shock=True,
+                           products=(product,))
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(w.portfolio)
+    _say(f"two-life product {product}")
+    compare(ctx, w)
+
+
+@pytest.mark.parametrize("K,J", [(1, 1), (4, 1), (16, 1), (32, 1), (8, 2), (16, 2), (2, 4), (8, 4),
+                                 (16, 4)])
+def test_every_product_together(ctx, K, J):
+    """All eleven products, payment patterns and cash-flow tables in one
+    portfolio, three nodes with shocks."""
+    rng = np.random.default_rng(1100 + K + 7 * J)
+    w = synth.random_small(rng, n=600, n_steps=90, n_scen=2 * K + 1, n_nodes=3, shock=True,
+                           products=tuple(range(7)) + TWO_LIFE_INS)
+    pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=0.1, n_rows=4)
+    pf = synth.with_payment_patterns(rng, pf, 0.5, 0.3)
+    w = synth.Workload("all products", w.basis, pf, node_step_m=7)
+    assert set(np.unique(pf.product)) == set(range(11))
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(pf)
+    ctx.set_option(1, K)
+    ctx.set_option(8, J)
+    _say(f"every product K={K} J={J}")
+    compare(ctx, w)
+
+
+def test_two_life_insurance_paths(ctx):
+    rng = np.random.default_rng(1200)
+    w = synth.random_small(rng, n=90, n_steps=140, n_scen=2, n_nodes=2, shock=True,
+                           products=TWO_LIFE_INS)
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("two-life insurance paths")
+    for node, scen in ((0, 0), (1, 1)):
+        po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=node, node_step=12)
+        po["path"].fill_(float("nan"))
+        ctx.reserve_recurrence(node, 1, scen, 1, 12, po)
+        torch.cuda.synchronize()
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=scen, node_step=12)
+        ref = oracle.reserves(b, pf, node, 1, scen, 1, 12)
+        gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+        assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
