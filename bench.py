@@ -228,6 +228,53 @@ def generated_scenarios_leg(rr, synth, sync, steps=20):
         ctx.close()
 
 
+def node_means_leg(rr, synth, sync, steps=10):
+    """C4 (60 annual nodes x 500 inner scenarios): the expected portfolio
+    reserve per node three ways: all inner scenarios (exact, the mean of the
+    scenario totals), the mean discount curve (exact by linearity, one
+    recurrence per node and policy), and the node-level surrogate (trained
+    on the node training workload)."""
+    w = synth.config_c4()
+    b, pf = w.basis, w.portfolio
+    K, S = b.n_nodes, b.n_scen
+    ctx = rr.Context(0)
+    try:
+        tw = synth.node_training_workload()
+        ctx.basis_upload(tw.basis.q, tw.basis.v, tw.basis.shock)
+        ctx.portfolio_upload(tw.portfolio)
+        t0 = time.perf_counter()
+        rep = ctx.node_surrogate_train(node_step=tw.node_step_m, epochs=60, batch=4096, lr=2e-3,
+                                       lr_final=1e-5, holdout=0.02, seed=3)
+        sync()
+        train_s = time.perf_counter() - t0
+        ctx.basis_upload(b.q, b.v, b.shock)
+        ctx.portfolio_upload(pf)
+        ex = ctx.alloc_outputs(K, S, r0=False, stats=True)
+        f_all = lambda: ctx.reserve_recurrence(0, K, 0, S, 12, ex)
+        f_mean = lambda: ctx.node_expected_reserves(0, K, 0, S, 12, r0=False)
+        f_sur = lambda: ctx.node_surrogate_infer(0, K, 0, S, 12, r0=False, report=False)
+        res = {}
+        for name, fn in (("all_scenarios", f_all), ("mean_curve", f_mean), ("surrogate", f_sur)):
+            fn()
+            sync()
+            res[name] = 1e3 * timed_steps(fn, steps, sync) / steps
+        exact = ex["stats"].cpu().numpy()[:, 0]
+        mc = f_mean()["totals"].cpu().numpy()
+        so = ctx.node_surrogate_infer(0, K, 0, S, 12, r0=False)
+        su = so["totals"].cpu().numpy()
+        live = np.abs(exact) > 0
+        rel = lambda x: float(np.max(np.abs(x[live] - exact[live]) / np.abs(exact[live])))
+        return {"workload": w.name + ": expected portfolio reserve per node",
+                "ms_all_scenarios": res["all_scenarios"], "ms_mean_curve": res["mean_curve"],
+                "ms_surrogate": res["surrogate"],
+                "max_rel_err_mean_curve": rel(mc), "max_rel_err_surrogate": rel(su),
+                "surrogate_rows": so["report"],
+                "surrogate_train_s": train_s, "surrogate_train_samples": rep["n_samples"],
+                "reference": "mean over the 500 scenarios of the exact portfolio totals"}
+    finally:
+        ctx.close()
+
+
 def representative_leg(rr, synth, sync, steps=5):
     """The representative annuity portfolio (Sec. 5.3, Table 2): 500,000
     annuities x 1,000 Vasicek scenarios over the 756 monthly steps to the
@@ -286,6 +333,8 @@ def main():
                     help="only run a plain 1 GiB device copy (traffic counter calibration)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the timed region of the headline workload (for profiling)")
+    ap.add_argument("--node-means-only", action="store_true",
+                    help="only the C4 expected-reserve-per-node leg")
     ap.add_argument("--generated-only", action="store_true",
                     help="only the device-generated-scenario leg (for profiling)")
     ap.add_argument("--representative-only", action="store_true",
@@ -321,6 +370,9 @@ def main():
     sync = torch.cuda.synchronize
     if args.representative_only:
         print(json.dumps(representative_leg(rr, synth, sync, steps=args.steps)))
+        return
+    if args.node_means_only:
+        print(json.dumps(node_means_leg(rr, synth, sync)))
         return
     if args.generated_only:
         print(json.dumps(generated_scenarios_leg(rr, synth, sync, steps=args.steps)))
@@ -456,6 +508,7 @@ def main():
                                      "nominal_valuations": w4.portfolio.n * w4.basis.n_nodes * w4.basis.n_scen}
         sec["representative_500k_annuities"] = representative_leg(rr, synth, sync)
         sec["C3_device_generated_scenarios"] = generated_scenarios_leg(rr, synth, sync)
+        sec["C4_node_means"] = node_means_leg(rr, synth, sync)
         result["secondary"] = sec
     ctx.close()
 

@@ -420,6 +420,43 @@ int rr_surrogate_infer(rr_ctx *ctx, const rr_run *run, const rr_outputs *out,
                        rr_infer_report *rep);
 
 /*
+ * Node-level surrogate (not in the paper): the reserve of each policy
+ * averaged over a node's scenarios, predicted by the same network from the
+ * policy features and the node's scenario features averaged over its
+ * scenarios (short rate, curve scores, shock; state 0) -- a regression of
+ * inner-scenario averages on the node's risk factors, for nested valuations
+ * where one expected reserve per node replaces its inner recurrences.
+ *   train:  as rr_surrogate_train, on one row per live (node, policy) of
+ *           cfg->run: the state-0 reserve averaged over the run's scenarios
+ *           (exact recurrence) per unit amount.  Own model slot; blob as for
+ *           rr_surrogate_get_weights with magic "RRSURN01".
+ *   infer:  for the run's nodes, node_r0[node_count][n] (upload order) and
+ *           node_totals[node_count] (sum over policies, fixed order), device
+ *           memory, either may be NULL.  Rows of policies and nodes inside
+ *           the training box come from the network, the others are exact
+ *           (rr_node_expected_reserves); expired policies 0.  rep counts
+ *           (node, policy) rows (may be NULL).
+ */
+int rr_node_surrogate_train(rr_ctx *ctx, const rr_train_cfg *cfg, rr_train_report *rep);
+
+/*
+ * The exact scenario average of every reserve at the run's nodes, by the
+ * linearity of Eq. (3.5) in the discount products D_t = v_0 ... v_{t-1}
+ * (mortality does not depend on the interest path and the cash flows are
+ * fixed in advance): the reserve on the curve whose products are the means of
+ * D_t over the run's scenarios.  One recurrence per (node, policy) instead of
+ * scen_count.  node_r0[node_count][n] and node_totals[node_count] (device,
+ * either may be NULL), asynchronous on the context's stream; run->out_mask
+ * and run->tail are ignored.  The node-level surrogate below predicts the same
+ * quantity.
+ */
+int rr_node_expected_reserves(rr_ctx *ctx, const rr_run *run, double *node_r0, double *node_totals);
+int rr_node_surrogate_infer(rr_ctx *ctx, const rr_run *run, double *node_r0, double *node_totals,
+                            rr_infer_report *rep);
+int rr_node_surrogate_get_weights(rr_ctx *ctx, void *host, size_t bytes, size_t *needed);
+int rr_node_surrogate_set_weights(rr_ctx *ctx, const void *host, size_t bytes);
+
+/*
  * Layer-level calls on the loaded model (device pointers, asynchronous on
  * the context's stream):
  *   forward:   y[n] = network(z[n][32]) for standardised inputs z (FP32,

@@ -45,6 +45,8 @@ Definitions (the same ones the GPU library documents):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 N_FEAT = 17
@@ -235,6 +237,27 @@ def samples(workload, node_begin, node_count, scen_begin, scen_count, node_step,
                 for j in states:
                     X.append(assemble(pol[i], sc[s], j))
                     T.append(r_all[kr, i, s, j] / pf.amount[i])
+    return np.array(X).reshape(-1, N_FEAT), np.array(T)
+
+
+def node_samples(workload, node_begin, node_count, scen_begin, scen_count, node_step, r_all, zbar, E):
+    """Rows (node-major, then policy) of the node-level model: the policy
+    features, the node's scenario features averaged over its scenarios and
+    state 0; the target is the policy's state-0 reserve averaged over the
+    node's scenarios, per unit amount.  r_all as for ``samples``."""
+    b, pf = workload.basis, workload.portfolio
+    X, T = [], []
+    for kr in range(node_count):
+        k = node_begin + kr
+        pol, ok = policy_features(pf, k, node_step)
+        shock = b.shock[k] if b.shock is not None else 1.0
+        sc = scenario_features(b.v[k, scen_begin:scen_begin + scen_count], shock, zbar, E)
+        nsc = np.array([math.fsum(sc[:, j]) / scen_count for j in range(5)])
+        for i in range(pf.n):
+            if not ok[i] or pf.term_m[i] - k * node_step <= 0:
+                continue
+            X.append(assemble(pol[i], nsc, 0))
+            T.append(math.fsum(r_all[kr, i, :, 0]) / scen_count / pf.amount[i])
     return np.array(X).reshape(-1, N_FEAT), np.array(T)
 
 

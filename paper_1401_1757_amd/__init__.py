@@ -45,6 +45,8 @@ EXPORTS = (
     "rr_surrogate_set_weights", "rr_surrogate_infer", "rr_surrogate_forward",
     "rr_surrogate_gradients", "rr_surrogate_adam_step", "rr_surrogate_features",
     "rr_basis_generate_vasicek", "rr_curves_generate_vasicek", "rr_vasicek_curves",
+    "rr_node_surrogate_train", "rr_node_surrogate_infer", "rr_node_surrogate_get_weights",
+    "rr_node_surrogate_set_weights", "rr_node_expected_reserves",
 )
 
 # Surrogate dimensions (include/rr.h).
@@ -119,11 +121,12 @@ _BLOB_F64 = [("mu", SG_FEATURES), ("sd", SG_FEATURES), ("lo", SG_FEATURES), ("hi
 
 
 def pack_surrogate_blob(params, mu, sd, lo, hi, tmu, tsd, zbar, evec, signature,
-                        adam_m=None, adam_v=None, adam_step=0) -> bytes:
-    """Serialise a model into the blob rr_surrogate_set_weights reads.
+                        adam_m=None, adam_v=None, adam_step=0, node=False) -> bytes:
+    """Serialise a model into the blob rr_surrogate_set_weights (node: the
+    node-level rr_node_surrogate_set_weights) reads.
     params: FP32 vector [SG_PARAMS]; evec: [3][50]; signature: [4][3]."""
     h = np.zeros((), _BLOB_HEADER)
-    h["magic"] = b"RRSURR01"
+    h["magic"] = b"RRSURN01" if node else b"RRSURR01"
     for k, v in (("version", 1), ("n_feat", SG_FEATURES), ("k_in", SG_INPUTS),
                  ("hidden", SG_HIDDEN), ("n_tenors", SG_TENORS), ("n_factors", SG_FACTORS),
                  ("n_params", SG_PARAMS), ("adam_step", adam_step)):
@@ -193,6 +196,13 @@ def load_library(path: str = LIB_PATH):
         "rr_basis_generate_vasicek": ([vp, ctypes.POINTER(Basis), ctypes.POINTER(Vasicek)], ctypes.c_int),
         "rr_curves_generate_vasicek": ([vp, ctypes.POINTER(Vasicek)], ctypes.c_int),
         "rr_vasicek_curves": ([vp, ctypes.POINTER(Vasicek), i32, i32, i32, vp, vp], ctypes.c_int),
+        "rr_node_surrogate_train": ([vp, ctypes.POINTER(TrainCfg), ctypes.POINTER(TrainReport)], ctypes.c_int),
+        "rr_node_surrogate_infer": ([vp, ctypes.POINTER(Run), vp, vp, ctypes.POINTER(InferReport)],
+                                    ctypes.c_int),
+        "rr_node_surrogate_get_weights": ([vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+                                          ctypes.c_int),
+        "rr_node_surrogate_set_weights": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "rr_node_expected_reserves": ([vp, ctypes.POINTER(Run), vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -453,6 +463,65 @@ class Context:
         if report:
             outputs["report"] = {"n_in_range": rep.n_in_range, "n_fallback": rep.n_fallback}
         return outputs
+
+    def node_expected_reserves(self, node_begin=0, node_count=None, scen_begin=0, scen_count=None,
+                               node_step=12, r0=True, totals=True):
+        """Exact scenario-averaged reserves (mean discount curve): device
+        tensors r0 [node_count][n] and totals [node_count]."""
+        torch = self._torch
+        node_count = self.n_nodes - node_begin if node_count is None else node_count
+        scen_count = self.n_scen - scen_begin if scen_count is None else scen_count
+        dev = torch.device("cuda", self.device)
+        out = {"r0": torch.empty((node_count, self.n), dtype=torch.float64, device=dev) if r0 else None,
+               "totals": torch.empty(node_count, dtype=torch.float64, device=dev) if totals else None}
+        run = Run(node_begin, node_count, scen_begin, scen_count, node_step, 0, 0.0)
+        self._check(self.lib.rr_node_expected_reserves(self.h, ctypes.byref(run), _ptr(out["r0"]),
+                                                       _ptr(out["totals"])))
+        return out
+
+    # -- node-level surrogate ------------------------------------------------
+    def node_surrogate_train(self, node_begin=0, node_count=None, scen_begin=0, scen_count=None,
+                             node_step=12, epochs=20, batch=4096, lr=2e-3, lr_final=1e-5,
+                             holdout=0.02, init=True, seed=7):
+        node_count = self.n_nodes - node_begin if node_count is None else node_count
+        scen_count = self.n_scen - scen_begin if scen_count is None else scen_count
+        run = Run(node_begin, node_count, scen_begin, scen_count, node_step, 0, 0.0)
+        cfg = TrainCfg(run, epochs, batch, lr, lr_final, holdout, 1 if init else 0, seed)
+        rep = TrainReport()
+        self._check(self.lib.rr_node_surrogate_train(self.h, ctypes.byref(cfg), ctypes.byref(rep)))
+        out = {k: getattr(rep, k) for k, _ in TrainReport._fields_}
+        out["calibration"] = list(rep.calibration)
+        return out
+
+    def node_surrogate_get_weights(self) -> bytes:
+        need = ctypes.c_size_t()
+        self._check(self.lib.rr_node_surrogate_get_weights(self.h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        self._check(self.lib.rr_node_surrogate_get_weights(self.h, buf, need.value, ctypes.byref(need)))
+        return buf.raw
+
+    def node_surrogate_set_weights(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self.lib.rr_node_surrogate_set_weights(self.h, buf, len(blob)))
+
+    def node_surrogate_infer(self, node_begin=0, node_count=None, scen_begin=0, scen_count=None,
+                             node_step=12, r0=True, totals=True, report=True):
+        """Expected (scenario-averaged) reserves: dict with device tensors
+        r0 [node_count][n] and totals [node_count] (None when not asked)."""
+        torch = self._torch
+        node_count = self.n_nodes - node_begin if node_count is None else node_count
+        scen_count = self.n_scen - scen_begin if scen_count is None else scen_count
+        dev = torch.device("cuda", self.device)
+        out = {"r0": torch.empty((node_count, self.n), dtype=torch.float64, device=dev) if r0 else None,
+               "totals": torch.empty(node_count, dtype=torch.float64, device=dev) if totals else None}
+        run = Run(node_begin, node_count, scen_begin, scen_count, node_step, 0, 0.0)
+        rep = InferReport()
+        self._check(self.lib.rr_node_surrogate_infer(self.h, ctypes.byref(run), _ptr(out["r0"]),
+                                                     _ptr(out["totals"]),
+                                                     ctypes.byref(rep) if report else None))
+        if report:
+            out["report"] = {"n_in_range": rep.n_in_range, "n_fallback": rep.n_fallback}
+        return out
 
     def surrogate_forward(self, z):
         """z: device float32 [n][32] standardised inputs -> device float32 [n]."""

@@ -110,6 +110,9 @@ struct rr_ctx {
     DevBuf<double> shock;                // [n_nodes]
     DevBuf<double> q_stage;              // [n_tables][n_ages_stage]
     DevBuf<double> vas_work;             // normals and short rates of the generator
+    DevBuf<double> mean_D, mean_v;       // scenario-mean discount products and curve
+    const double *v_override = nullptr;  // curves read instead of v (stride pad_override)
+    int pad_override = 0;
     DevBuf<double> vas_r0;               // [n_nodes] start rates on the device
     std::vector<double> vas_r0_host;     // their values (the last generation's)
     int n_ages_stage = 0;
@@ -161,6 +164,7 @@ struct rr_ctx {
 
     // surrogate
     rr::Surrogate *sur = nullptr;
+    rr::Surrogate *nsur = nullptr;       // node-level model (scenario-averaged reserves)
 };
 
 namespace rr {

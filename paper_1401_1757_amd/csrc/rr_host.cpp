@@ -306,6 +306,8 @@ extern "C" int rr_destroy(rr_ctx *c)
     for (auto &e : c->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     rr::surrogate_destroy(c->sur);
     c->sur = nullptr;
+    rr::surrogate_destroy(c->nsur);
+    c->nsur = nullptr;
     c->plans.clear();
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -872,6 +874,45 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     return RR_OK;
 }
 
+extern "C" int rr_node_expected_reserves(rr_ctx *c, const rr_run *run, double *node_r0,
+                                         double *node_totals)
+{
+    if (!c) return RR_EINVAL;
+    if (!c->has_basis || !c->has_pf) return fail(c, RR_ESTATE, "upload a basis and a portfolio first");
+    if (!run) return fail(c, RR_EINVAL, "run must not be NULL");
+    if (run->node_count < 0 || run->scen_count < 1) return fail(c, RR_EINVAL, "need node_count >= 0 and scen_count >= 1");
+    if (run->node_begin < 0 || run->node_begin + run->node_count > c->n_nodes)
+        return fail(c, RR_EINVAL, "node range outside the basis");
+    if (run->scen_begin < 0 || run->scen_begin + run->scen_count > c->n_scen)
+        return fail(c, RR_EINVAL, "scenario range outside the basis");
+    if (run->node_count == 0 || (!node_r0 && !node_totals)) return RR_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, c->mean_D.alloc((size_t)run->node_count * c->n_steps * run->scen_count));
+    HIPCHK(c, c->mean_v.alloc((size_t)c->n_nodes * c->n_steps * 64));
+    HIPCHK(c, launch_mean_curve(c->v.p, c->n_steps, c->scen_pad, run->node_begin, run->node_count,
+                                run->scen_begin, run->scen_count, c->mean_D.p, c->mean_v.p,
+                                c->stream));
+    // One scenario per node on the mean curve, through the ordinary path
+    // (direct launches: a captured graph would hold the curve pointer).
+    rr_run r = *run;
+    r.scen_begin = 0;
+    r.scen_count = 1;
+    r.out_mask = (node_r0 ? RR_OUT_R0 : 0u) | (node_totals ? RR_OUT_TOTALS : 0u);
+    rr_outputs o;
+    memset(&o, 0, sizeof o);
+    o.r0 = node_r0;
+    o.totals = node_totals;
+    const int graph = c->opt_graph;
+    c->opt_graph = 0;
+    c->v_override = c->mean_v.p;
+    c->pad_override = 64;
+    const int rc = rr_reserve_recurrence(c, &r, &o);
+    c->v_override = nullptr;
+    c->pad_override = 0;
+    c->opt_graph = graph;
+    return rc;
+}
+
 extern "C" int rr_path_size(rr_ctx *c, int32_t node, int32_t node_step_m, int64_t *n_out)
 {
     if (!c || !n_out) return RR_EINVAL;
@@ -965,9 +1006,9 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.n_ages_stage = c->n_ages_stage;
     P.n_q = c->n_tables * c->n_ages_stage;
     P.q_in_lds = (P.n_q <= max_lds_tables_doubles() && (size_t)P.n_q * 8 <= c->lds_per_block) ? 1 : 0;
-    P.v = c->v.p;
+    P.v = c->v_override ? c->v_override : c->v.p;
     P.n_steps = c->n_steps;
-    P.scen_pad = c->scen_pad;
+    P.scen_pad = c->v_override ? c->pad_override : c->scen_pad;
     P.shock = c->shock.p;
     P.age1 = c->age1.p;
     P.age2 = c->age2.p;

@@ -142,6 +142,12 @@ struct VasParams {
 hipError_t launch_vasicek(const VasParams &P, const double *r0, double *work, double *v,
                           int month_major, double *r_out, hipStream_t stream);
 size_t vasicek_work_doubles(int n_nodes, int n_scen, int n_steps, int scen_pad);
+// Mean discount curve of the run's scenarios per node (rr_kernels.hip): D
+// holds node_count * n_steps * scen_count doubles; vbar is [n_nodes][n_steps][64]
+// with the curve at lane 0 of the run's nodes.
+hipError_t launch_mean_curve(const double *v, int n_steps, int scen_pad, int node_begin,
+                             int node_count, int scen_begin, int scen_count, double *D,
+                             double *vbar, hipStream_t stream);
 int max_lds_tables_doubles();
 bool supported_k(int K);
 bool supported_kj(int K, int J);   // (scenarios, policies) per lane

@@ -384,4 +384,86 @@ hipError_t launch_transpose_curves(const double *src, double *dst, int n_nodes, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Mean discount curve of a node's scenarios: the reserve is linear in the
+// discount products D_t = v_0 ... v_{t-1} (Eq. (3.5) with mortality independent
+// of the interest path), so the scenario-averaged reserve is the reserve on
+// the curve whose products are the scenario means of D_t.
+// ---------------------------------------------------------------------------
+constexpr int DISC_CHUNK = 32;
+
+// D[(kr * n_steps + t) * sc + s] = product of v over steps 0..t of scenario
+// scen_begin + s of node node_begin + kr (the one-step factors are loaded a
+// chunk ahead: they do not depend on the product).
+__global__ void __launch_bounds__(64) k_disc_products(const double *__restrict__ v, int n_steps,
+                                                     int scen_pad, int node_begin, int node_count,
+                                                     int scen_begin, int sc, double *__restrict__ D)
+{
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= node_count * sc) return;
+    const int kr = id / sc, s = id % sc;
+    const double *vk = v + (size_t)(node_begin + kr) * n_steps * scen_pad + scen_begin + s;
+    double *dk = D + (size_t)kr * n_steps * sc + s;
+    double prod = 1.0;
+    double cur[DISC_CHUNK];
+#pragma unroll
+    for (int i = 0; i < DISC_CHUNK; ++i) cur[i] = i < n_steps ? vk[(size_t)i * scen_pad] : 1.0;
+    for (int t0 = 0; t0 < n_steps; t0 += DISC_CHUNK) {
+        double nxt[DISC_CHUNK];
+#pragma unroll
+        for (int i = 0; i < DISC_CHUNK; ++i) {
+            const int t = t0 + DISC_CHUNK + i;
+            nxt[i] = t < n_steps ? vk[(size_t)t * scen_pad] : 1.0;
+        }
+#pragma unroll
+        for (int i = 0; i < DISC_CHUNK; ++i) {
+            const int t = t0 + i;
+            if (t < n_steps) {
+                prod *= cur[i];
+                dk[(size_t)t * sc] = prod;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < DISC_CHUNK; ++i) cur[i] = nxt[i];
+    }
+}
+
+// Mean over scenarios (in order) of D, then the one-step factors of the mean
+// curve, written at scenario 0 of vbar[node][t][64] (other lanes 1).
+__global__ void __launch_bounds__(256) k_mean_curve(const double *__restrict__ D, int n_steps,
+                                                    int node_begin, int node_count, int sc,
+                                                    double *__restrict__ vbar)
+{
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= node_count * n_steps) return;
+    const int kr = id / n_steps, t = id % n_steps;
+    const double *row = D + ((size_t)kr * n_steps + t) * sc;
+    double acc = 0.0;
+    for (int s = 0; s < sc; ++s) acc += row[s];
+    double prev = 1.0;
+    if (t > 0) {
+        const double *pr = D + ((size_t)kr * n_steps + t - 1) * sc;
+        double a = 0.0;
+        for (int s = 0; s < sc; ++s) a += pr[s];
+        prev = a / sc;
+    }
+    double *o = vbar + ((size_t)(node_begin + kr) * n_steps + t) * 64;
+    o[0] = (acc / sc) / prev;
+    for (int j = 1; j < 64; ++j) o[j] = 1.0;
+}
+
+hipError_t launch_mean_curve(const double *v, int n_steps, int scen_pad, int node_begin,
+                             int node_count, int scen_begin, int scen_count, double *D,
+                             double *vbar, hipStream_t stream)
+{
+    if (node_count <= 0 || scen_count <= 0 || n_steps <= 0) return hipSuccess;
+    const int nt = node_count * scen_count;
+    hipLaunchKernelGGL(k_disc_products, dim3((nt + 63) / 64), dim3(64), 0, stream, v, n_steps,
+                       scen_pad, node_begin, node_count, scen_begin, scen_count, D);
+    const int nm = node_count * n_steps;
+    hipLaunchKernelGGL(k_mean_curve, dim3((nm + 255) / 256), dim3(256), 0, stream, D, n_steps,
+                       node_begin, node_count, scen_count, vbar);
+    return hipGetLastError();
+}
+
 }  // namespace rr

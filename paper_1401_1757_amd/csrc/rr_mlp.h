@@ -186,5 +186,21 @@ int residual_blocks(int n);
 hipError_t launch_residuals(const float *y, const float *t, const unsigned char *prod, int n,
                             double *out, hipStream_t s);
 
+// ---- node-level model -------------------------------------------------------
+// out[r * out_stride + j] = (sum over i < n_inner, in order, of
+// x[(r * n_inner + i) * width + j]) / n_inner.
+hipError_t launch_mean_inner(const double *x, long long rows, int n_inner, int width, double *out,
+                             int out_stride, hipStream_t s);
+// Predictions of rows (node k, policy i) = rowmap[j]: out[k * n + i] =
+// y[j] * scale[k * n + i] + offset[k * n + i].
+hipError_t launch_node_scatter(const float *y, const int2 *rowmap, long long rows, int n,
+                               const double *scale, const double *offset, double *out,
+                               hipStream_t s);
+// out[j] = src[j] where mask[j] != 0, for j < count.
+hipError_t launch_select(const double *src, const unsigned char *mask, long long count, double *out,
+                         hipStream_t s);
+// out[r] = sum over i < n of x[r * n + i] (fixed-order tree, one block per row).
+hipError_t launch_row_sums(const double *x, int rows, int n, double *out, hipStream_t s);
+
 }  // namespace mlp
 }  // namespace rr

@@ -1110,5 +1110,96 @@ hipError_t launch_residuals(const float *y, const float *t, const unsigned char 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Node-level model helpers
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_mean_inner(const double *__restrict__ x, long long rows,
+                                                    int n_inner, int width,
+                                                    double *__restrict__ out, int out_stride)
+{
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= rows * width) return;
+    const long long r = id / width;
+    const int j = (int)(id % width);
+    const double *p = x + (size_t)r * n_inner * width + j;
+    double acc = 0.0;
+    for (int i = 0; i < n_inner; ++i) acc += p[(size_t)i * width];
+    out[(size_t)r * out_stride + j] = acc / (double)n_inner;
+}
+
+hipError_t launch_mean_inner(const double *x, long long rows, int n_inner, int width, double *out,
+                             int out_stride, hipStream_t s)
+{
+    const long long n = rows * width;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mean_inner, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, rows,
+                       n_inner, width, out, out_stride);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_node_scatter(const float *__restrict__ y,
+                                                      const int2 *__restrict__ rowmap,
+                                                      long long rows, int n,
+                                                      const double *__restrict__ scale,
+                                                      const double *__restrict__ offset,
+                                                      double *__restrict__ out)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= rows) return;
+    const int2 ki = rowmap[j];
+    const size_t o = (size_t)ki.x * n + ki.y;
+    out[o] = (double)y[j] * scale[o] + offset[o];
+}
+
+hipError_t launch_node_scatter(const float *y, const int2 *rowmap, long long rows, int n,
+                               const double *scale, const double *offset, double *out,
+                               hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_node_scatter, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, y,
+                       rowmap, rows, n, scale, offset, out);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_select(const double *__restrict__ src,
+                                                const unsigned char *__restrict__ mask,
+                                                long long count, double *__restrict__ out)
+{
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < count && mask[j]) out[j] = src[j];
+}
+
+hipError_t launch_select(const double *src, const unsigned char *mask, long long count, double *out,
+                         hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src, mask,
+                       count, out);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_row_sums(const double *__restrict__ x, int n,
+                                                  double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    const double *p = x + (size_t)blockIdx.x * n;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += p[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+hipError_t launch_row_sums(const double *x, int rows, int n, double *out, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_sums, dim3(rows), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
 }  // namespace mlp
 }  // namespace rr

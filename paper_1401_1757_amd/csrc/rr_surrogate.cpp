@@ -22,6 +22,7 @@ namespace M = rr::mlp;
 namespace {
 
 constexpr char kMagic[8] = {'R', 'R', 'S', 'U', 'R', 'R', '0', '1'};
+constexpr char kMagicNode[8] = {'R', 'R', 'S', 'U', 'R', 'N', '0', '1'};   // node-level model
 constexpr int kVersion = 1;
 constexpr int kProducts[4] = {RR_SL_ANN, RR_JL_ANN, RR_TERM, RR_ENDOW};
 constexpr int kChunk = 16;   // policies per work unit of the fused inference kernel
@@ -135,6 +136,14 @@ struct rr::Surrogate {
     DevBuf<uint16_t> sfeat, pfeat, pfeat2;
     DevBuf<int> sok, pflag;
     DevBuf<double> partial, exact, totals_tmp, oscale, ooffset, ct_work;
+    // node-level inference workspaces
+    DevBuf<double> nraw, node_vals, node_dummy, node_X, node_T, node_means;
+    DevBuf<float> node_y, node_t;
+    DevBuf<uint16_t> node_xq;
+    DevBuf<unsigned char> node_prod, node_fbmask;
+    DevBuf<int> node_perm;
+    DevBuf<int2> node_rowmap, node_pairs;
+    DevBuf<long long> node_poff, node_roff;
 
     // fallback plan cache
     std::vector<uint64_t> plan_key;
@@ -165,6 +174,12 @@ Surrogate *sur_of(rr_ctx *c)
 {
     if (!c->sur) c->sur = new Surrogate();
     return c->sur;
+}
+
+Surrogate *nsur_of(rr_ctx *c)
+{
+    if (!c->nsur) c->nsur = new Surrogate();
+    return c->nsur;
 }
 
 int alloc_model(rr_ctx *c, Surrogate *S)
@@ -505,11 +520,11 @@ int fit_components(rr_ctx *c, Surrogate *S, long long ns)
 // ---------------------------------------------------------------------------
 // Model blob
 // ---------------------------------------------------------------------------
-extern "C" int rr_surrogate_get_weights(rr_ctx *c, void *host, size_t bytes, size_t *needed)
+static int get_weights(rr_ctx *c, Surrogate *S, const char *magic, void *host, size_t bytes,
+                       size_t *needed)
 {
     if (!c) return RR_EINVAL;
     if (needed) *needed = kBlobBytes;
-    Surrogate *S = c->sur;
     int rc;
     if ((rc = check_model(c, S))) return rc;
     if (!host) return RR_OK;
@@ -517,7 +532,7 @@ extern "C" int rr_surrogate_get_weights(rr_ctx *c, void *host, size_t bytes, siz
     HIPCHK(c, hipSetDevice(c->device));
     BlobHeader h;
     memset(&h, 0, sizeof h);
-    memcpy(h.magic, kMagic, 8);
+    memcpy(h.magic, magic, 8);
     h.version = kVersion;
     h.n_feat = M::N_FEAT;
     h.k_in = M::K_IN;
@@ -547,13 +562,14 @@ extern "C" int rr_surrogate_get_weights(rr_ctx *c, void *host, size_t bytes, siz
     return RR_OK;
 }
 
-extern "C" int rr_surrogate_set_weights(rr_ctx *c, const void *host, size_t bytes)
+static int set_weights(rr_ctx *c, bool node, const void *host, size_t bytes)
 {
     if (!c) return RR_EINVAL;
     if (!host || bytes < kBlobBytes) return fail(c, RR_EINVAL, "blob must hold %zu bytes", kBlobBytes);
     BlobHeader h;
     memcpy(&h, host, sizeof h);
-    if (memcmp(h.magic, kMagic, 8) != 0 || h.version != kVersion) return fail(c, RR_EINVAL, "not a surrogate blob");
+    if (memcmp(h.magic, node ? kMagicNode : kMagic, 8) != 0 || h.version != kVersion)
+        return fail(c, RR_EINVAL, node ? "not a node-level surrogate blob" : "not a surrogate blob");
     if (h.n_feat != M::N_FEAT || h.k_in != M::K_IN || h.hidden != M::HID || h.n_tenors != M::N_TENORS ||
         h.n_factors != M::N_FACTORS || h.n_params != M::N_PARAMS || h.adam_step < 0)
         return fail(c, RR_EINVAL, "blob dimensions do not match this library");
@@ -575,7 +591,7 @@ extern "C" int rr_surrogate_set_weights(rr_ctx *c, const void *host, size_t byte
         if (h.signature[3 * j] < -1 || h.signature[3 * j + 1] < -1 || h.signature[3 * j + 2] < -1)
             return fail(c, RR_EINVAL, "bad product signature");
     HIPCHK(c, hipSetDevice(c->device));
-    Surrogate *S = sur_of(c);
+    Surrogate *S = node ? nsur_of(c) : sur_of(c);
     int rc;
     if ((rc = alloc_model(c, S))) return rc;
     size_t k = 0;
@@ -598,6 +614,26 @@ extern "C" int rr_surrogate_set_weights(rr_ctx *c, const void *host, size_t byte
     S->has_model = true;
     S->version += 1;
     return RR_OK;
+}
+
+extern "C" int rr_surrogate_get_weights(rr_ctx *c, void *host, size_t bytes, size_t *needed)
+{
+    return c ? get_weights(c, c->sur, kMagic, host, bytes, needed) : RR_EINVAL;
+}
+
+extern "C" int rr_surrogate_set_weights(rr_ctx *c, const void *host, size_t bytes)
+{
+    return set_weights(c, false, host, bytes);
+}
+
+extern "C" int rr_node_surrogate_get_weights(rr_ctx *c, void *host, size_t bytes, size_t *needed)
+{
+    return c ? get_weights(c, c->nsur, kMagicNode, host, bytes, needed) : RR_EINVAL;
+}
+
+extern "C" int rr_node_surrogate_set_weights(rr_ctx *c, const void *host, size_t bytes)
+{
+    return set_weights(c, true, host, bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -674,7 +710,10 @@ extern "C" int rr_surrogate_features(rr_ctx *c, const rr_run *run, double *pol, 
 // ---------------------------------------------------------------------------
 // Training
 // ---------------------------------------------------------------------------
-extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_report *rep)
+// Training of the per-scenario model (rows: node, scenario, policy, state)
+// or, with node_level, of the node-level model (rows: node, policy; features
+// of the node's scenarios and the state-0 reserves averaged over them).
+static int train_impl(rr_ctx *c, const rr_train_cfg *cfg, rr_train_report *rep, bool node_level)
 {
     if (!c) return RR_EINVAL;
     if (!cfg) return fail(c, RR_EINVAL, "cfg must not be NULL");
@@ -689,7 +728,7 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
         return fail(c, RR_EINVAL, "lr must be > 0 and lr_final >= 0");
     if (!(cfg->holdout >= 0.f && cfg->holdout <= 0.5f)) return fail(c, RR_EINVAL, "holdout must be in [0, 0.5]");
     if (cfg->init != 0 && cfg->init != 1) return fail(c, RR_EINVAL, "init must be 0 or 1");
-    Surrogate *S = sur_of(c);
+    Surrogate *S = node_level ? nsur_of(c) : sur_of(c);
     if (!cfg->init && !S->has_model) return fail(c, RR_ESTATE, "init = 0 needs a loaded model");
     if (run->node_count == 0 || run->scen_count == 0 || c->n_user == 0)
         return fail(c, RR_EINVAL, "the run has no samples");
@@ -706,14 +745,14 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
         if ((rc = upload_vec(c, S->d_sig, sg))) return rc;
     }
 
-    // Exact reserves of every state.
+    // Exact reserves of every state (the node-level model: state 0).
     const int n = c->n_user;
     const long long ns = (long long)run->node_count * run->scen_count;
     DevBuf<double> r_all;
-    HIPCHK(c, r_all.alloc((size_t)ns * n * 4));
+    HIPCHK(c, r_all.alloc((size_t)ns * n * (node_level ? 1 : 4)));
     {
         rr_run er = *run;
-        er.out_mask = RR_OUT_R0 | RR_OUT_ALL_STATES;
+        er.out_mask = node_level ? RR_OUT_R0 : (RR_OUT_R0 | RR_OUT_ALL_STATES);
         rr_outputs eo;
         memset(&eo, 0, sizeof eo);
         eo.r0 = r_all.p;
@@ -735,11 +774,11 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
     for (int k = 0; k < run->node_count; ++k) {
         for (int i = 0; i < n; ++i) {
             if (flags[(size_t)k * n + i] != 1) continue;
-            const int states = c->h_product[i] == RR_JL_ANN ? 3 : 1;
+            const int states = (c->h_product[i] == RR_JL_ANN && !node_level) ? 3 : 1;
             for (int j = 0; j < states; ++j) pairs.push_back(make_int2(i, j));
         }
         pair_off[k + 1] = (long long)pairs.size();
-        row_off[k + 1] = row_off[k] + (pair_off[k + 1] - pair_off[k]) * run->scen_count;
+        row_off[k + 1] = row_off[k] + (pair_off[k + 1] - pair_off[k]) * (node_level ? 1 : run->scen_count);
     }
     const long long N = row_off[run->node_count];
     const long long n_hold_min = (long long)std::ceil((double)cfg->holdout * (double)N);
@@ -755,8 +794,24 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
     DevBuf<double> X, T;
     HIPCHK(c, X.alloc((size_t)N * M::N_FEAT));
     HIPCHK(c, T.alloc((size_t)N));
-    HIPCHK(c, M::launch_samples(S->praw.p, S->sraw.p, r_all.p, S->amount.p, d_pairs.p, d_poff.p,
-                                d_roff.p, run->node_count, n, run->scen_count, N, X.p, T.p, st));
+    if (node_level) {
+        // One row per (node, policy): the node's scenario features and the
+        // state-0 reserves averaged over its scenarios, laid out as a run of
+        // one scenario per node with four state slots.
+        DevBuf<double> nraw, rmean;
+        HIPCHK(c, nraw.alloc((size_t)run->node_count * 5));
+        HIPCHK(c, rmean.alloc((size_t)run->node_count * n * 4));
+        HIPCHK(c, launch_fill(rmean.p, (long long)run->node_count * n * 4, 0.0, st));
+        HIPCHK(c, M::launch_mean_inner(S->sraw.p, run->node_count, run->scen_count, 5, nraw.p, 5, st));
+        HIPCHK(c, M::launch_mean_inner(r_all.p, (long long)run->node_count * n, run->scen_count, 1,
+                                       rmean.p, 4, st));
+        HIPCHK(c, M::launch_samples(S->praw.p, nraw.p, rmean.p, S->amount.p, d_pairs.p, d_poff.p,
+                                    d_roff.p, run->node_count, n, 1, N, X.p, T.p, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+    } else {
+        HIPCHK(c, M::launch_samples(S->praw.p, S->sraw.p, r_all.p, S->amount.p, d_pairs.p, d_poff.p,
+                                    d_roff.p, run->node_count, n, run->scen_count, N, X.p, T.p, st));
+    }
     r_all.release();
 
     // Standardisation and box (new model).
@@ -908,6 +963,16 @@ extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_r
     return RR_OK;
 }
 
+extern "C" int rr_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_report *rep)
+{
+    return train_impl(c, cfg, rep, false);
+}
+
+extern "C" int rr_node_surrogate_train(rr_ctx *c, const rr_train_cfg *cfg, rr_train_report *rep)
+{
+    return train_impl(c, cfg, rep, true);
+}
+
 // ---------------------------------------------------------------------------
 // Inference
 // ---------------------------------------------------------------------------
@@ -1049,6 +1114,123 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
     if (rep) {
         rep->n_in_range = S->in_rows;
         rep->n_fallback = S->fb_rows;
+    }
+    return RR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Node-level model: scenario-averaged reserves per (node, policy)
+// ---------------------------------------------------------------------------
+extern "C" int rr_node_surrogate_infer(rr_ctx *c, const rr_run *run, double *node_r0,
+                                       double *node_totals, rr_infer_report *rep)
+{
+    if (!c) return RR_EINVAL;
+    int rc;
+    if ((rc = check_model(c, c->nsur))) return rc;
+    if (!c->has_basis || !c->has_pf) return fail(c, RR_ESTATE, "upload a basis and a portfolio first");
+    if ((rc = check_run(c, run))) return rc;
+    if (rep) memset(rep, 0, sizeof *rep);
+    if (run->node_count == 0) return RR_OK;
+    if (run->scen_count == 0) return fail(c, RR_EINVAL, "node features need at least one scenario");
+    HIPCHK(c, hipSetDevice(c->device));
+    Surrogate *S = c->nsur;
+    const hipStream_t st = c->stream;
+    const int n = c->n_user;
+    const int K = run->node_count;
+    const long long nk = (long long)K * n;
+    double *vals = node_r0;
+    if (!vals) {
+        HIPCHK(c, S->node_vals.alloc((size_t)std::max(1LL, nk)));
+        vals = S->node_vals.p;
+    }
+    if (nk > 0) HIPCHK(c, launch_fill(vals, nk, 0.0, st));   // expired policies: 0
+    if (n == 0) {
+        if (node_totals) HIPCHK(c, launch_fill(node_totals, K, 0.0, st));
+        return RR_OK;
+    }
+    if ((rc = compute_features(c, S, run, true, true, false))) return rc;
+    HIPCHK(c, S->nraw.alloc((size_t)K * 5));
+    HIPCHK(c, M::launch_mean_inner(S->sraw.p, K, run->scen_count, 5, S->nraw.p, 5, st));
+    std::vector<double> hn((size_t)K * 5);
+    std::vector<int> pf((size_t)nk);
+    HIPCHK(c, hipMemcpyAsync(hn.data(), S->nraw.p, hn.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(pf.data(), S->pflag.p, pf.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    // A node is in the model's domain when its mean scenario features (8..12)
+    // and the state-0 one-hot (13..15) lie in the training box.
+    const double st0[3] = {1.0, 0.0, 0.0};
+    std::vector<int2> rowmap, pairs;
+    std::vector<long long> poff(K + 1, 0), roff(K + 1, 0);
+    std::vector<unsigned char> fbmask((size_t)nk, 0);
+    int64_t n_fb = 0;
+    for (int k = 0; k < K; ++k) {
+        bool ok = true;
+        for (int j = 0; j < 5; ++j) {
+            const double x = hn[(size_t)k * 5 + j];
+            ok = ok && x >= S->lo[8 + j] && x <= S->hi[8 + j];
+        }
+        for (int j = 0; j < 3; ++j) ok = ok && st0[j] >= S->lo[13 + j] && st0[j] <= S->hi[13 + j];
+        for (int i = 0; i < n; ++i) {
+            const int f = pf[(size_t)k * n + i];
+            if (f == 1 && ok) {
+                rowmap.push_back(make_int2(k, i));
+                pairs.push_back(make_int2(i, 0));
+            } else if (f != 2) {
+                fbmask[(size_t)k * n + i] = 1;
+                ++n_fb;
+            }
+        }
+        poff[k + 1] = (long long)pairs.size();
+        roff[k + 1] = poff[k + 1];
+    }
+    const long long N = (long long)rowmap.size();
+    if (N > 0) {
+        const long long N_pad = pad64(N);
+        if ((rc = upload_vec(c, S->node_rowmap, rowmap))) return rc;
+        if ((rc = upload_vec(c, S->node_pairs, pairs))) return rc;
+        if ((rc = upload_vec(c, S->node_poff, poff))) return rc;
+        if ((rc = upload_vec(c, S->node_roff, roff))) return rc;
+        std::vector<int> perm((size_t)N);
+        std::iota(perm.begin(), perm.end(), 0);
+        if ((rc = upload_vec(c, S->node_perm, perm))) return rc;
+        HIPCHK(c, S->node_dummy.alloc((size_t)nk * 4));
+        HIPCHK(c, launch_fill(S->node_dummy.p, nk * 4, 0.0, st));
+        HIPCHK(c, S->node_X.alloc((size_t)N * M::N_FEAT));
+        HIPCHK(c, S->node_T.alloc((size_t)N));
+        HIPCHK(c, S->node_xq.alloc((size_t)N_pad * M::K_IN));
+        HIPCHK(c, S->node_t.alloc((size_t)N_pad));
+        HIPCHK(c, S->node_prod.alloc((size_t)N_pad));
+        HIPCHK(c, S->node_y.alloc((size_t)N_pad));
+        HIPCHK(c, hipMemsetAsync(S->node_xq.p, 0, (size_t)N_pad * M::K_IN * 2, st));
+        HIPCHK(c, M::launch_samples(S->praw.p, S->nraw.p, S->node_dummy.p, S->amount.p,
+                                    S->node_pairs.p, S->node_poff.p, S->node_roff.p, K, n, 1, N,
+                                    S->node_X.p, S->node_T.p, st));
+        HIPCHK(c, M::launch_build(S->node_X.p, S->node_T.p, N, S->node_perm.p, S->d_mu.p, S->d_sd.p,
+                                  S->d_tmu.p, S->d_tsd.p, S->node_xq.p, S->node_t.p,
+                                  S->node_prod.p, st));
+        const long long B = 65536;   // rows per network pass
+        if ((rc = ensure_ws(c, S, B))) return rc;
+        for (long long r0 = 0; r0 < N; r0 += B) {
+            const long long nb = std::min(B, N - r0);
+            if ((rc = network_pass(c, S, S->node_xq.p + r0 * M::K_IN, nb, pad64(nb), nullptr, false,
+                                   nullptr, nullptr, S->node_y.p + r0)))
+                return rc;
+        }
+        HIPCHK(c, M::launch_node_scatter(S->node_y.p, S->node_rowmap.p, N, n, S->oscale.p,
+                                         S->ooffset.p, vals, st));
+    }
+    if (n_fb > 0) {
+        // Exact scenario averages of the fallback rows: the reserves on the
+        // node's mean discount curve (linearity in the discount products).
+        HIPCHK(c, S->node_means.alloc((size_t)nk));
+        if ((rc = rr_node_expected_reserves(c, run, S->node_means.p, nullptr))) return rc;
+        if ((rc = upload_vec(c, S->node_fbmask, fbmask))) return rc;
+        HIPCHK(c, M::launch_select(S->node_means.p, S->node_fbmask.p, nk, vals, st));
+    }
+    if (node_totals) HIPCHK(c, M::launch_row_sums(vals, K, n, node_totals, st));
+    if (rep) {
+        rep->n_in_range = N;
+        rep->n_fallback = n_fb;
     }
     return RR_OK;
 }

@@ -478,6 +478,30 @@ def surrogate_training_workload(seed: int = 1005, n: int = 5000, n_nodes: int = 
                     note=f"node short rates {np.round(r0[:4], 4)}...")
 
 
+def node_training_workload(seed: int = 1007, n: int = 5000, n_nodes: int = 120,
+                           node_step_m: int = 6, n_scen: int = 32, n_steps: int = 600,
+                           shock_sd: float = 0.05) -> Workload:
+    """Training inputs for the node-level surrogate: C2-law policies at nodes
+    node_step_m months apart (policies age and terms shorten with the node);
+    node k draws its own inner short rate from the outer Vasicek law at its
+    horizon, a mortality shock N(1, shock_sd) and n_scen inner scenarios, so
+    the rate is not tied to the node's time."""
+    rng = np.random.default_rng(seed)
+    pf = portfolio_mixed(rng, n)
+    q = mortality_tables(max_attained_age(pf) + 1, C2_LOADINGS)
+    T = np.arange(n_nodes) * node_step_m / 12.0
+    m = VAS_B + (VAS_R0 - VAS_B) * np.exp(-VAS_A * T)
+    sd = VAS_SIGMA * np.sqrt((1.0 - np.exp(-2.0 * VAS_A * T)) / (2.0 * VAS_A))
+    r0 = m + sd * rng.standard_normal(n_nodes)
+    v = np.empty((n_nodes, n_scen, n_steps))
+    for k in range(n_nodes):
+        v[k], _ = vasicek_paths(rng, n_scen, n_steps, r0[k])
+    shock = rng.normal(1.0, shock_sd, n_nodes)
+    return Workload(f"node-level surrogate training: {n:,} C2-law policies x {n_nodes} nodes "
+                    f"({node_step_m} months apart) x {n_scen} scenarios",
+                    Basis(q=q, v=v, shock=shock), pf, node_step_m=node_step_m)
+
+
 def random_mlp_params(rng, n_feat: int = 17, k_in: int = 32, hidden: int = 256,
                       bias_sd: float = 0.1) -> dict:
     """Random surrogate weights: W1 [k_in][hidden] (rows >= n_feat zero),

@@ -1,0 +1,274 @@
+"""GPU parity of the node-level surrogate (scenario-averaged reserves per
+(node, policy)) against the oracle, and its accuracy and speed on nodes of
+the nested workload.
+
+Inference rows inside the box are compared with the oracle's bfloat16
+forward pass allowing rounding flips of the bfloat16 inputs (as for the
+per-scenario model); fallback rows are the exact reserves averaged over the
+node's scenarios, at the FP64 bound."""
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp
+from tests._helpers import RTOL, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1401_1757_amd as rr
+    return rr
+
+
+@pytest.fixture()
+def ctx(rr):
+    c = rr.Context(0)
+    yield c
+    c.close()
+
+
+def node_model(seed=60, n=300, n_nodes=12, n_scen=8):
+    """Standardisation, box, components and signature of the node-level model
+    fitted by the oracle on a small node training workload."""
+    tw = synth.node_training_workload(seed=seed, n=n, n_nodes=n_nodes, node_step_m=12, n_scen=n_scen)
+    b, pf = tw.basis, tw.portfolio
+    ref = oracle.reserves(b, pf, 0, n_nodes, 0, n_scen, 12)
+    zbar, E, _ = mlp.fit_pca(mlp.zero_rates(b.v.reshape(-1, b.n_steps)))
+    X, T = mlp.node_samples(tw, 0, n_nodes, 0, n_scen, 12, ref["r_all"], zbar, E)
+    mu, sd, lo, hi, tmu, tsd = mlp.normalisation(X, T)
+    sig = mlp.product_signature(pf)
+    sig_arr = np.array([s if s is not None else (-1, -1, -1) for s in sig])
+    return dict(mu=mu, sd=sd, lo=lo, hi=hi, tmu=tmu, tsd=tsd, zbar=zbar, E=E, sig=sig,
+                sig_arr=sig_arr, X=X, T=T, workload=tw)
+
+
+@pytest.fixture(scope="module")
+def nmodel():
+    return node_model()
+
+
+def blob_of(rr, om, params):
+    return rr.pack_surrogate_blob(mlp.flatten(params), om["mu"], om["sd"], om["lo"], om["hi"],
+                                  om["tmu"], om["tsd"], om["zbar"], om["E"].T, om["sig_arr"],
+                                  node=True)
+
+
+def eval_workload(seed=61, n=300, n_nodes=3, n_scen=40):
+    """C2-law policies plus out-of-domain ones; nodes with Vasicek scenarios
+    and shocks, one node far outside the training rates."""
+    rng = np.random.default_rng(seed)
+    pf = synth.portfolio_mixed(rng, n)
+    pf.product[np.flatnonzero(pf.product == synth.SL_ANN)[0]] = synth.REV_ANN
+    pf.age2_m[np.flatnonzero(pf.product == synth.REV_ANN)] = 700
+    pf.amount[np.flatnonzero(pf.product == synth.TERM)[0]] *= 1e4
+    pf.term_m[np.flatnonzero(pf.product == synth.ENDOW)[:2]] = 12
+    q = synth.mortality_tables(synth.max_attained_age(pf) + 1, synth.C2_LOADINGS)
+    v = np.empty((n_nodes, n_scen, 600))
+    for k in range(n_nodes):
+        v[k], _ = synth.vasicek_paths(rng, n_scen, 600, 0.03 + 0.005 * k)
+    v[n_nodes - 1] = v[n_nodes - 1] ** 4     # rates far outside the training box
+    shock = np.linspace(1.0, 1.03, n_nodes)
+    return synth.Workload("node eval", synth.Basis(q=q, v=v, shock=shock), pf)
+
+
+def oracle_node_predictions(om, params, w, node_step):
+    b, pf = w.basis, w.portfolio
+    K, n = b.n_nodes, pf.n
+    pred = np.full((K, n), np.nan)
+    use = np.zeros((K, n), bool)
+    pidx = list(range(8)) + [16]
+    for k in range(K):
+        pol, ok = mlp.policy_features(pf, k, node_step, om["sig"])
+        sc = mlp.scenario_features(b.v[k], b.shock[k], om["zbar"], om["E"])
+        nsc = np.array([math.fsum(sc[:, j]) / b.n_scen for j in range(5)])
+        node_ok = (np.all((nsc >= om["lo"][8:13]) & (nsc <= om["hi"][8:13])) and
+                   np.all((np.array([1.0, 0, 0]) >= om["lo"][13:16]) &
+                          (np.array([1.0, 0, 0]) <= om["hi"][13:16])))
+        inbox = np.all((pol >= om["lo"][pidx]) & (pol <= om["hi"][pidx]), axis=1)
+        live = pf.term_m - k * node_step > 0
+        for i in range(n):
+            if live[i] and ok[i] and inbox[i] and node_ok:
+                X = mlp.assemble(pol[i], nsc, 0)[None]
+                pred[k, i] = mlp.predict_reserves(params, X, pf.amount[i], om["mu"], om["sd"],
+                                                  om["tmu"], om["tsd"])[0]
+                use[k, i] = True
+    return pred, use
+
+
+def test_node_infer_matches_oracle(ctx, rr, nmodel):
+    rng = np.random.default_rng(62)
+    p = synth.random_mlp_params(rng)
+    w = eval_workload()
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    ctx.node_surrogate_set_weights(blob_of(rr, nmodel, p))
+    _say("node-level inference")
+    out = ctx.node_surrogate_infer(0, b.n_nodes, 0, b.n_scen, 12)
+    torch.cuda.synchronize()
+    got = to_np(out["r0"])
+    tot = to_np(out["totals"])
+    pred, use = oracle_node_predictions(nmodel, p, w, 12)
+    ref = oracle.reserves(b, pf, 0, b.n_nodes, 0, b.n_scen, 12)
+    exact_mean = np.array([[math.fsum(ref["r_all"][k, i, :, 0]) / b.n_scen for i in range(pf.n)]
+                           for k in range(b.n_nodes)])
+    gross_mean = ref["gross"].mean(axis=2)
+    live = np.array([[pf.term_m[i] - 12 * k > 0 for i in range(pf.n)] for k in range(b.n_nodes)])
+    fb = live & ~use
+    assert out["report"]["n_in_range"] == int(use.sum())
+    assert out["report"]["n_fallback"] == int(fb.sum())
+    assert fb.sum() >= pf.n + 3 and use.sum() > pf.n     # the far node and the odd policies
+    assert np.all(got[~live] == 0.0)
+    scale = np.maximum(np.abs(exact_mean), gross_mean)
+    assert np.all(np.abs(got - exact_mean)[fb] <= RTOL * scale[fb])
+    slot = np.select([pf.product == c for c in mlp.SURROGATE_PRODUCTS], [0, 1, 2, 3], 0)
+    ys = (pf.amount * nmodel["tsd"][slot])[None, :] * np.ones_like(got)
+    d = np.abs(got[use] - pred[use]) / ys[use]
+    # bfloat16 inputs may round the other way on either side: a few rows differ
+    assert np.quantile(d, 0.95) < 1e-5 and d.max() < 0.05, (np.quantile(d, 0.95), d.max())
+    assert np.allclose(tot, got.sum(axis=1), rtol=1e-12, atol=1e-6)
+
+
+def test_node_training_statistics_match_oracle(ctx, rr, nmodel):
+    tw = nmodel["workload"]
+    b, pf = tw.basis, tw.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("node-level training")
+    rep = ctx.node_surrogate_train(0, b.n_nodes, 0, b.n_scen, 12, epochs=20, batch=256, lr=3e-3,
+                                   lr_final=1e-4, holdout=0.1, seed=5)
+    _say(f"  {rep}")
+    assert rep["n_samples"] == nmodel["X"].shape[0]
+    assert rep["final_loss"] < rep["first_loss"]
+    blob = ctx.node_surrogate_get_weights()
+    assert blob[:8] == b"RRSURN01"
+    m = rr.unpack_surrogate_blob(blob)
+    np.testing.assert_allclose(m["mu"], nmodel["mu"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(m["sd"], nmodel["sd"], rtol=1e-9)
+    np.testing.assert_allclose(m["lo"], nmodel["lo"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(m["hi"], nmodel["hi"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(m["tsd"], nmodel["tsd"], rtol=1e-9)
+    cal = np.array(rep["calibration"], np.float64)
+    np.testing.assert_allclose(m["tmu"] - m["tsd"] * cal, nmodel["tmu"], rtol=1e-6, atol=1e-6)
+    with pytest.raises(rr.RRError, match="not a surrogate blob"):
+        ctx.surrogate_set_weights(blob)
+
+
+def test_node_expected_reserves_match_oracle(ctx):
+    """The exact scenario average by the mean discount curve, every product
+    with payment patterns and cash-flow tables, three nodes with shocks."""
+    rng = np.random.default_rng(63)
+    w = synth.random_small(rng, n=500, n_steps=100, n_scen=37, n_nodes=3, shock=True,
+                           products=tuple(range(7)) + synth.TWO_LIFE_INS)
+    pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=0.1, n_rows=4)
+    pf = synth.with_payment_patterns(rng, pf, 0.5, 0.3)
+    b = w.basis
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("node expected reserves")
+    for node0, nn, s0, ns in ((0, 3, 0, 37), (1, 2, 5, 20)):
+        out = ctx.node_expected_reserves(node0, nn, s0, ns, 7)
+        torch.cuda.synchronize()
+        ref = oracle.reserves(b, pf, node0, nn, s0, ns, 7)
+        mean = np.array([[math.fsum(ref["r_all"][k, i, :, 0]) / ns for i in range(pf.n)]
+                         for k in range(nn)])
+        scale = np.maximum(np.abs(mean), ref["gross"].mean(axis=2))
+        assert np.all(np.abs(to_np(out["r0"]) - mean) <= RTOL * scale)
+        tmean = np.array([math.fsum(ref["totals"][k]) / ns for k in range(nn)])
+        gtot = ref["gross_totals"].mean(axis=1)
+        assert np.all(np.abs(to_np(out["totals"]) - tmean) <= RTOL * gtot)
+    # the ordinary run afterwards still reads the scenario curves
+    full = ctx.alloc_outputs(3, 37, r0=False)
+    ctx.reserve_recurrence(0, 3, 0, 37, 7, full)
+    torch.cuda.synchronize()
+    ref = oracle.reserves(b, pf, 0, 3, 0, 37, 7)
+    assert np.all(np.abs(to_np(full["totals"]) - ref["totals"]) <= RTOL * ref["gross_totals"])
+
+
+def test_node_surrogate_accuracy_and_speed_on_nested_nodes(ctx):
+    """Trained on the node training workload (C2-law policies at 120 nodes six
+    months apart, own short rate and shock per node, 32 scenarios each);
+    evaluated on six nodes of the nested workload (10,000 policies, 100 of
+    its 500 inner scenarios) against the oracle's exact scenario means."""
+    threads = int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
+    tw = synth.node_training_workload()
+    _say("node training workload")
+    ctx.basis_upload(tw.basis.q, tw.basis.v, tw.basis.shock)
+    ctx.portfolio_upload(tw.portfolio)
+    rep = ctx.node_surrogate_train(node_step=tw.node_step_m, epochs=60, batch=4096, lr=2e-3,
+                                   lr_final=1e-5, holdout=0.02, seed=3)
+    _say(f"  {rep}")
+    w = synth.config_c4()
+    nodes = [0, 8, 16, 24, 32, 40]
+    v = w.basis.v[nodes, :100]
+    b = synth.Basis(q=w.basis.q, v=np.ascontiguousarray(v), shock=w.basis.shock[nodes])
+    # nodes keep their ages and terms: value each picked node as its own node
+    # index of a basis holding only the picked nodes, with node_step scaled
+    sub = []
+    for j, k in enumerate(nodes):
+        pf = w.portfolio.subset(np.arange(w.portfolio.n))
+        pf.age1_m = pf.age1_m + 12 * k
+        pf.age2_m = np.where(np.isin(pf.product, synth.TWO_LIFE), pf.age2_m + 12 * k, pf.age2_m)
+        pf.term_m = pf.term_m - 12 * k
+        keep = pf.term_m > 0
+        sub.append((j, pf.subset(np.flatnonzero(keep))))
+    errs, errs_mean, exact_tot, sur_tot = [], [], [], []
+    t_sur = t_exact = t_mean = 0.0
+    for j, pf in sub:
+        bj = synth.Basis(q=b.q, v=b.v[j:j + 1], shock=b.shock[j:j + 1])
+        ctx.basis_upload(bj.q, bj.v, bj.shock)
+        ctx.portfolio_upload(pf)
+        out = ctx.node_surrogate_infer(0, 1, 0, 100, 12)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.node_surrogate_infer(0, 1, 0, 100, 12, r0=False, report=False)
+        torch.cuda.synchronize()
+        t_sur += (time.perf_counter() - t0) / 5
+        ex = ctx.alloc_outputs(1, 100, r0=False, stats=True)
+        ctx.reserve_recurrence(0, 1, 0, 100, 12, ex)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.reserve_recurrence(0, 1, 0, 100, 12, ex)
+        torch.cuda.synchronize()
+        t_exact += (time.perf_counter() - t0) / 5
+        mc = ctx.node_expected_reserves(0, 1, 0, 100, 12, r0=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.node_expected_reserves(0, 1, 0, 100, 12, r0=False)
+        torch.cuda.synchronize()
+        t_mean += (time.perf_counter() - t0) / 5
+        ref = oracle.reserves(bj, pf, 0, 1, 0, 100, 12, want_gross=False, n_threads=threads)
+        em = math.fsum(ref["totals"][0]) / 100
+        sm = float(to_np(out["totals"])[0])
+        mm = float(to_np(mc["totals"])[0])
+        exact_tot.append(em)
+        sur_tot.append(sm)
+        errs.append(abs(sm - em) / abs(em))
+        errs_mean.append(abs(mm - em) / abs(em))
+        _say(f"  node {nodes[j]}: exact mean {em:.6e} surrogate {sm:.6e} rel err {errs[-1]:.2e} "
+             f"mean-curve rel err {errs_mean[-1]:.1e} ({out['report']})")
+    _say(f"  max rel err: surrogate {max(errs):.3e}, mean curve {max(errs_mean):.1e}; time over the six "
+         f"nodes x 100 scenarios: surrogate {t_sur * 1e3:.3f} ms, mean curve {t_mean * 1e3:.3f} ms, "
+         f"all scenarios {t_exact * 1e3:.3f} ms")
+    assert max(errs_mean) < 1e-10
+    assert max(errs) < 1e-2

@@ -654,3 +654,23 @@ def test_two_life_insurance_recurrence_equals_summation(product):
             scale = np.abs(summ).max() + 1e-300
             np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=0,
                                        atol=1e-12 * scale)
+
+
+def test_scenario_average_is_the_reserve_on_the_mean_discount_curve():
+    """Eq. (3.5) is linear in the discount products D_t = v_0 ... v_{t-1}
+    (mortality does not depend on the interest path): the reserve averaged
+    over scenarios equals the reserve on the curve whose products are the
+    scenario means of D_t."""
+    rng = np.random.default_rng(21)
+    w = synth.random_small(rng, n=40, n_steps=120, n_scen=25, n_nodes=2, shock=True,
+                           products=tuple(range(7)) + (JL_ENDOW, JL_ASSUR1, JL_ASSUR2))
+    b, pf = w.basis, w.portfolio
+    ref = oracle.reserves(b, pf, 0, 2, 0, 25, 12)
+    D = np.cumprod(b.v, axis=2)                                   # D_{t+1}
+    Dbar = D.mean(axis=1)                                         # [node][t]
+    vbar = Dbar / np.concatenate([np.ones((2, 1)), Dbar[:, :-1]], axis=1)
+    mb = synth.Basis(q=b.q, v=vbar[:, None, :], shock=b.shock)
+    mean_ref = oracle.reserves(mb, pf, 0, 2, 0, 1, 12)
+    avg = ref["r_all"][..., 0].mean(axis=2)
+    scale = np.maximum(np.abs(avg), ref["gross"].mean(axis=2))
+    assert np.all(np.abs(mean_ref["r_all"][:, :, 0, 0] - avg) <= 1e-12 * scale + 1e-300)
