@@ -32,6 +32,9 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+MAX_STATES = 9          # largest state model of the oracle
+
+
 class _Basis(ctypes.Structure):
     _fields_ = [("n_ages", ctypes.c_int), ("n_tables", ctypes.c_int),
                 ("q", ctypes.c_void_p), ("n_nodes", ctypes.c_int),
@@ -47,7 +50,9 @@ class _Portfolio(ctypes.Structure):
                 ("amount", ctypes.c_void_p), ("premium", ctypes.c_void_p),
                 ("escalation", ctypes.c_void_p), ("anniv", ctypes.c_void_p),
                 ("annual", ctypes.c_void_p), ("cf_row", ctypes.c_void_p),
-                ("cf", ctypes.c_void_p), ("n_cf_rows", ctypes.c_int), ("cf_len", ctypes.c_int)]
+                ("cf", ctypes.c_void_p), ("n_cf_rows", ctypes.c_int), ("cf_len", ctypes.c_int),
+                ("mk_models", ctypes.c_int), ("mk_states", ctypes.c_int), ("mk_ages", ctypes.c_int),
+                ("mk_w", ctypes.c_void_p), ("mk_c", ctypes.c_void_p)]
 
 
 def _load():
@@ -101,8 +106,17 @@ class _Args:
         cf = getattr(pf, "cf", None)
         self.cf = None if cf is None else np.ascontiguousarray(np.atleast_2d(cf), np.float64)
         n_rows, cf_len = (0, 0) if self.cf is None else self.cf.shape
+        mk = getattr(pf, "markov", None)      # (w [models][ages][m][m], c [models][m]) or None
+        if mk is None:
+            self.mk_w = self.mk_c = None
+            mk_dims = (0, 0, 0)
+        else:
+            self.mk_w = np.ascontiguousarray(mk[0], np.float64)
+            self.mk_c = np.ascontiguousarray(mk[1], np.float64)
+            mk_dims = (self.mk_w.shape[0], self.mk_w.shape[2], self.mk_w.shape[1])
         self.p = _Portfolio(int(pf.product.shape[0]), *[_ptr(a) for a in self.arrs], _ptr(self.cf),
-                            n_rows, cf_len)
+                            n_rows, cf_len, mk_dims[0], mk_dims[1], mk_dims[2], _ptr(self.mk_w),
+                            _ptr(self.mk_c))
         self.n = int(pf.product.shape[0])
 
 
@@ -158,13 +172,12 @@ def reserve_path_summation(basis, pf, i, node=0, scen=0, node_step=12):
     lib = _load()
     a = _Args(basis, pf)
     S = int(pf.term_m[i]) - node * node_step
-    n_states = lib.orc_n_states(int(pf.product[i]))
-    out = np.zeros((S + 1) * max(n_states, 1))
+    out = np.zeros((S + 1) * MAX_STATES)     # room for any model's states
     rc = lib.orc_reserve_path_summation(ctypes.byref(a.b), ctypes.byref(a.p), i, node, scen,
                                         node_step, _ptr(out))
     if rc < 0:
         raise ValueError("oracle rejected the input")
-    return out.reshape(S + 1, n_states)
+    return out[: (S + 1) * rc].reshape(S + 1, rc)
 
 
 def build_w(n_lives: int, model: int, q, g: float = 1.0) -> np.ndarray:

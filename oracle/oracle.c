@@ -54,7 +54,7 @@
 enum {
     O_SL_ANN = 0, O_JL_ANN = 1, O_REV_ANN = 2, O_LS_ANN = 3,
     O_TERM = 4, O_ENDOW = 5, O_ENDOW_ASSUR = 6, O_CF_TABLE = 7,
-    O_JL_ENDOW = 8, O_JL_ASSUR1 = 9, O_JL_ASSUR2 = 10, O_N_PRODUCTS = 11
+    O_JL_ENDOW = 8, O_JL_ASSUR1 = 9, O_JL_ASSUR2 = 10, O_MARKOV = 11, O_N_PRODUCTS = 12
 };
 
 #define ORC_MAX_STATES 9
@@ -89,6 +89,15 @@ typedef struct {
     const double *cf;        /* [n_cf_rows][cf_len] cash flow per unit amount, or NULL */
     int n_cf_rows;
     int cf_len;
+    /* Uploaded Markov models (O_MARKOV; table1 = model): one-step matrices
+     * mk_w[model][age][m][m] by attained age in months (row = state at the
+     * start of the month) and benefits mk_c[model][m] per unit amount, paid
+     * at the end of a month that ends in the state. */
+    int mk_models;
+    int mk_states;
+    int mk_ages;
+    const double *mk_w;
+    const double *mk_c;
 } orc_portfolio;
 
 /* A contract in the paper's state-space form (Sec. 3.1, Sec. 4). */
@@ -240,6 +249,11 @@ int orc_contract_of(int product, int timing, double amount, double premium,
         k->n_lives = 2; k->life_model = 3; k->n_states = 9;
         k->c_ben[4] = sa; k->c_ben[5] = sa; k->c_ben[7] = sa;
         break;
+    case O_MARKOV:       /* Sec. 4.7: an uploaded state model; the benefit vector
+                            and the size are set by contract_for */
+        k->n_lives = 1; k->life_model = 2; k->n_states = 2;
+        k->f_ann = 1.0;
+        break;
     case O_CF_TABLE:     /* single life, c_t = amount x table value, at f = 1
                             (Sec. 4.4: c_t holds the nominal amounts) */
         k->n_lives = 1; k->life_model = 2; k->n_states = 2;
@@ -265,19 +279,57 @@ static double q_at(const orc_basis *b, int table, int age, double m)
 static void step_q(const orc_basis *b, const orc_portfolio *p, int i,
                    int age_shift, double m, int t, double *q)
 {
+    if (p->product[i] == O_MARKOV) {   /* an uploaded model carries its own transitions */
+        q[0] = q[1] = 0.0;
+        return;
+    }
     q[0] = q_at(b, p->table1[i], p->age1[i] + age_shift + t, m);
     q[1] = q_at(b, p->table2[i], p->age2[i] + age_shift + t, m);
 }
 
+/* The contract of policy i (an uploaded model: its size and benefits). */
+static void contract_for(const orc_portfolio *p, int i, int gross, orc_contract *k)
+{
+    orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], gross, k);
+    if (p->product[i] == O_MARKOV) {
+        int m = p->mk_states;
+        const double *c = p->mk_c + (size_t)p->table1[i] * m;
+        k->n_states = m;
+        for (int j = 0; j < m; ++j) {
+            double x = p->amount[i] * c[j];
+            k->c_ann[j] = gross ? fabs(x) : x;
+        }
+    }
+}
+
+/* One-step matrix over a fraction g of step t: the Kronecker product of the
+ * lives' models (Sec. 4.3), or an uploaded model's table at the attained age
+ * (g = 1; g = 0 is the identity). */
+static void step_w(const orc_portfolio *p, int i, const orc_contract *k, const double *q,
+                   int age_shift, int t, double g, double *W)
+{
+    if (p->product[i] != O_MARKOV) {
+        orc_build_w(k->n_lives, k->life_model, q, g, W);
+        return;
+    }
+    int m = p->mk_states;
+    if (g == 0.0) {
+        for (int a = 0; a < m * m; ++a) W[a] = 0.0;
+        for (int a = 0; a < m; ++a) W[a * m + a] = 1.0;
+        return;
+    }
+    int age = p->age1[i] + age_shift + t;
+    memcpy(W, p->mk_w + (((size_t)p->table1[i] * p->mk_ages + age) * m) * m, sizeof(double) * m * m);
+}
+
 /* Add v^g W_g c to acc, one cash-flow stream of Eq. (3.1). */
-static void add_stream(const orc_contract *k, const double *q, double v, double g,
+static void add_stream(const orc_contract *k, const double *W, double v, double g,
                        const double *c, double *acc)
 {
     int n = k->n_states, any = 0;
     for (int j = 0; j < n; ++j) any |= (c[j] != 0.0);
     if (!any) return;
-    double W[ORC_MAX_STATES * ORC_MAX_STATES], y[ORC_MAX_STATES];
-    orc_build_w(k->n_lives, k->life_model, q, g, W);
+    double y[ORC_MAX_STATES];
     matvec(W, c, n, y);
     double vg = pow(v, g);
     for (int j = 0; j < n; ++j) acc[j] += vg * y[j];
@@ -320,13 +372,17 @@ static void recurrence_one(const orc_basis *b, const orc_portfolio *p, int i,
         double v = vcurve[t];
         step_q(b, p, i, age_shift, m, t, q);
         for (int j = 0; j < n; ++j) rn[j] = 0.0;
-        add_stream(k, q, v, 0.0, k->c_prem, rn);
+        double Wg[ORC_MAX_STATES * ORC_MAX_STATES];
+        step_w(p, i, k, q, age_shift, t, 0.0, Wg);
+        add_stream(k, Wg, v, 0.0, k->c_prem, rn);
         double c_pay[ORC_MAX_STATES];
         double fac = payment_factor(p, i, age_shift + t + (k->f_ann == 1.0 ? 1 : 0), k);
         for (int j = 0; j < n; ++j) c_pay[j] = fac * k->c_ann[j];
-        add_stream(k, q, v, k->f_ann, c_pay, rn);
-        add_stream(k, q, v, 1.0, k->c_ben, rn);
-        orc_build_w(k->n_lives, k->life_model, q, 1.0, W1);
+        step_w(p, i, k, q, age_shift, t, k->f_ann, Wg);
+        add_stream(k, Wg, v, k->f_ann, c_pay, rn);
+        step_w(p, i, k, q, age_shift, t, 1.0, Wg);
+        add_stream(k, Wg, v, 1.0, k->c_ben, rn);
+        step_w(p, i, k, q, age_shift, t, 1.0, W1);
         matvec(W1, r, n, y);
         for (int j = 0; j < n; ++j) rn[j] += v * y[j];
         for (int j = 0; j < n; ++j) r[j] = rn[j];
@@ -350,10 +406,16 @@ static int validate(const orc_basis *b, const orc_portfolio *p)
     for (int i = 0; i < p->n; ++i) {
         if (p->product[i] < 0 || p->product[i] >= O_N_PRODUCTS) return -1;
         if (p->term[i] < 1 || p->term[i] > b->n_steps) return -1;
-        if (p->age1[i] < 0 || p->age1[i] + p->term[i] > b->n_ages - 1) return -1;
-        if (p->table1[i] < 0 || p->table1[i] >= b->n_tables) return -1;
         if (p->anniv && (p->anniv[i] < 1 || p->anniv[i] > 12)) return -1;
         if (p->escalation && !(p->escalation[i] >= 0.0)) return -1;
+        if (p->product[i] == O_MARKOV) {   /* table1 is the model, ages index its tables */
+            if (!p->mk_w || !p->mk_c || p->mk_states < 2 || p->mk_states > 4) return -1;
+            if (p->table1[i] < 0 || p->table1[i] >= p->mk_models) return -1;
+            if (p->age1[i] < 0 || p->age1[i] + p->term[i] > p->mk_ages - 1) return -1;
+            continue;
+        }
+        if (p->age1[i] < 0 || p->age1[i] + p->term[i] > b->n_ages - 1) return -1;
+        if (p->table1[i] < 0 || p->table1[i] >= b->n_tables) return -1;
         if (p->product[i] == O_CF_TABLE) {
             if (!p->cf_row || !p->cf) return -1;
             if (p->cf_row[i] < 0 || p->cf_row[i] >= p->n_cf_rows) return -1;
@@ -395,8 +457,8 @@ int orc_reserves(const orc_basis *b, const orc_portfolio *p, int node0, int nnod
 #pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
     for (int i = 0; i < n; ++i) {
         orc_contract k, kg;
-        orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], 0, &k);
-        orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], 1, &kg);
+        contract_for(p, i, 0, &k);
+        contract_for(p, i, 1, &kg);
         double r0[ORC_MAX_STATES], g0[ORC_MAX_STATES];
         for (int a = 0; a < nnode; ++a) {
             int node = node0 + a;
@@ -468,7 +530,7 @@ int orc_reserve_paths(const orc_basis *b, const orc_portfolio *p, int node, int 
         if (S <= 0) { path[off[i]] = 0.0; continue; }
         orc_contract k;
         double r0[ORC_MAX_STATES];
-        orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], 0, &k);
+        contract_for(p, i, 0, &k);
         const double *vc = b->v + ((size_t)node * b->n_scen + scen) * b->n_steps;
         recurrence_one(b, p, i, &k, node, node * node_step, S, vc, r0, path + off[i]);
     }
@@ -494,7 +556,7 @@ int orc_reserve_path_summation(const orc_basis *b, const orc_portfolio *p, int i
     int S = p->term[i] - shift;
     if (S <= 0) return -1;
     orc_contract k;
-    orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], 0, &k);
+    contract_for(p, i, 0, &k);
     int n = k.n_states;
     double m = b->shock ? b->shock[node] : 1.0;
     const double *vc = b->v + ((size_t)node * b->n_scen + scen) * b->n_steps;
@@ -513,14 +575,14 @@ int orc_reserve_path_summation(const orc_basis *b, const orc_portfolio *p, int i
             step_q(b, p, i, shift, m, u, q);
             double v = vc[u];
             for (int st = 0; st < 3; ++st) {
-                orc_build_w(k.n_lives, k.life_model, q, gs[st], Wg);
+                step_w(p, i, &k, q, shift, u, gs[st], Wg);
                 matmul(P, Wg, n, PW);
                 matvec(PW, streams[st], n, y);
                 double d = D * pow(v, gs[st]);
                 if (st == 1) d *= payment_factor(p, i, shift + u + (k.f_ann == 1.0 ? 1 : 0), &k);
                 for (int j = 0; j < n; ++j) r[j] += d * y[j];
             }
-            orc_build_w(k.n_lives, k.life_model, q, 1.0, Wg);
+            step_w(p, i, &k, q, shift, u, 1.0, Wg);
             matmul(P, Wg, n, T);
             memcpy(P, T, sizeof(double) * n * n);
             D *= v;

@@ -48,6 +48,7 @@ JL_ENDOW = 8      # two-life pure endowment: SA at maturity if both alive (Sec. 
 JL_ASSUR1 = 9     # two-life term assurance, SA on the first death (9-state model, Sec. 4.2.3)
 JL_ASSUR2 = 10    # two-life term assurance, SA on the second death (Sec. 4.2.3)
 TWO_LIFE_INS = (JL_ENDOW, JL_ASSUR1, JL_ASSUR2)
+MARKOV = 11       # one life on an uploaded Markov model (table1 = model; Sec. 4.7)
 TWO_LIFE = (JL_ANN, REV_ANN, LS_ANN, 8, 9, 10)   # with the two-life endowment and assurances
 
 ADVANCE = 0       # annuity paid at the start of each month (f = 0)
@@ -154,6 +155,10 @@ class Portfolio:
     # at the end of month T after node 0 if alive.
     cf_row: np.ndarray | None = None       # int32 [n]
     cf: np.ndarray | None = None           # float64 [n_rows][cf_len]
+    # Uploaded Markov models (MARKOV policies, table1 = model): (w, c) with
+    # w [models][ages][m][m] monthly one-step matrices (row = state at the
+    # start of the month) and c [models][m] benefits per unit amount.
+    markov: tuple | None = None
 
     @property
     def n(self) -> int:
@@ -162,8 +167,9 @@ class Portfolio:
     def subset(self, idx) -> "Portfolio":
         d = {f.name: (None if getattr(self, f.name) is None
                       else np.ascontiguousarray(getattr(self, f.name)[idx]))
-             for f in dataclasses.fields(self) if f.name != "cf"}
+             for f in dataclasses.fields(self) if f.name not in ("cf", "markov")}
         d["cf"] = None if self.cf is None else self.cf.copy()   # rows are shared
+        d["markov"] = self.markov
         return Portfolio(**d)
 
     def scaled(self, factor: float) -> "Portfolio":
@@ -534,6 +540,43 @@ def with_cash_flow_tables(rng, pf: Portfolio, frac: float = 0.3, n_rows: int = 5
     out.cf_row = rng.integers(0, n_rows, n).astype(np.int32)
     out.cf = cf
     out.age2_m = np.where(pick, 0, pf.age2_m).astype(np.int32)
+    return out
+
+
+def phi_models(n_ages: int, loadings=(1.0, 1.3), recovery: float = 0.08,
+               incidence_scale: float = 0.3) -> tuple:
+    """Permanent-health-insurance models (Sec. 4.7: a reversible state model,
+    not upper triangular): states healthy, sick, dead; monthly sickness
+    incidence proportional to the GM death probability, recovery at a fixed
+    monthly rate, sick lives dying at twice the healthy rate; benefit
+    1/12 of the amount for each month ending sick.  One model per loading."""
+    q = mortality_tables(n_ages, loadings)
+    w = np.zeros((len(loadings), n_ages, 3, 3))
+    for m in range(len(loadings)):
+        qh = q[m]
+        inc = np.minimum(incidence_scale * np.sqrt(qh), 0.5)
+        qs = np.minimum(2.0 * qh, 1.0)
+        w[m, :, 0, 2] = qh
+        w[m, :, 0, 1] = (1.0 - qh) * inc
+        w[m, :, 0, 0] = 1.0 - qh - (1.0 - qh) * inc
+        w[m, :, 1, 2] = qs
+        w[m, :, 1, 0] = (1.0 - qs) * recovery
+        w[m, :, 1, 1] = 1.0 - qs - (1.0 - qs) * recovery
+        w[m, :, 2, 2] = 1.0
+    c = np.tile(np.array([0.0, 1.0 / 12.0, 0.0]), (len(loadings), 1))
+    return w, c
+
+
+def with_markov_policies(rng, pf: Portfolio, models: tuple, frac: float = 0.3) -> Portfolio:
+    """Copy of pf in which a share `frac` of the policies become MARKOV
+    policies on `models` (table1 drawn among the models), keeping their age,
+    term, amount and premium."""
+    out = pf.subset(np.arange(pf.n))
+    pick = rng.uniform(size=pf.n) < frac
+    out.product = np.where(pick, MARKOV, pf.product).astype(np.int32)
+    out.table1 = np.where(pick, rng.integers(0, models[0].shape[0], pf.n), pf.table1).astype(np.int32)
+    out.age2_m = np.where(pick, 0, pf.age2_m).astype(np.int32)
+    out.markov = models
     return out
 
 

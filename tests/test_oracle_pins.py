@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from synth import (ADVANCE, ARREARS, CF_TABLE, ENDOW, ENDOW_ASSUR, JL_ASSUR1, JL_ASSUR2, JL_ENDOW, JL_ANN, LS_ANN,
+from synth import (ADVANCE, ARREARS, CF_TABLE, ENDOW, ENDOW_ASSUR, JL_ASSUR1, JL_ASSUR2, JL_ENDOW, MARKOV, JL_ANN, LS_ANN,
                    REV_ANN, SL_ANN, TERM, Basis, Portfolio)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -674,3 +674,80 @@ def test_scenario_average_is_the_reserve_on_the_mean_discount_curve():
     avg = ref["r_all"][..., 0].mean(axis=2)
     scale = np.maximum(np.abs(avg), ref["gross"].mean(axis=2))
     assert np.all(np.abs(mean_ref["r_all"][:, :, 0, 0] - avg) <= 1e-12 * scale + 1e-300)
+
+
+# --------------------------------------------------------------------------
+# Uploaded Markov models (Sec. 4.7: reversible, not upper-triangular W)
+# --------------------------------------------------------------------------
+def _mk_pf(models, model, age1, term, amount, premium=0.0):
+    n = np.broadcast(np.asarray(model), np.asarray(age1), np.asarray(term), np.asarray(amount),
+                     np.asarray(premium)).size
+    pf = make_pf([MARKOV] * n, age1, term, amount=amount, premium=premium, table1=model)
+    pf.markov = models
+    return pf
+
+
+def test_two_state_model_reproduces_the_single_life_annuity():
+    q = gm(1.0)
+    w = np.zeros((1, N_AGES, 2, 2))
+    w[0, :, 0, 0], w[0, :, 0, 1], w[0, :, 1, 1] = 1 - q, q, 1.0
+    c = np.array([[1.0 / 12.0, 0.0]])
+    b = basis(q, np.full(600, V_FLAT))
+    mk = _mk_pf((w, c), 0, 700, 360, 1200.0)
+    sl = make_pf([SL_ANN], 700, 360, amount=1200.0, timing=ARREARS)
+    np.testing.assert_allclose(r0(b, mk)[:, 0], r0(b, sl)[:, 0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("S", [1, 12, 240])
+def test_reversible_model_closed_form(S):
+    """Constant non-triangular W: r = amount sum_t v^t e0' W^t c minus the
+    premium annuity sum_t v^t P(state 0 at t), by matrix powers."""
+    W = np.array([[0.95, 0.04, 0.01], [0.10, 0.85, 0.05], [0.0, 0.0, 1.0]])
+    c = np.array([0.0, 1.0 / 12.0, 0.0])
+    w = np.broadcast_to(W, (1, N_AGES, 3, 3)).copy()
+    b = basis(gm(1.0), np.full(600, V_FLAT))
+    pf = _mk_pf((w, c[None]), 0, 500, S, 6000.0, premium=20.0)
+    r = oracle.reserves(b, pf)["r_all"][0, 0, 0]
+    e0 = np.array([1.0, 0.0, 0.0])
+    ben = sum(V_FLAT ** t * e0 @ np.linalg.matrix_power(W, t) @ c for t in range(1, S + 1))
+    prem = sum(V_FLAT ** t * (e0 @ np.linalg.matrix_power(W, t))[0] for t in range(S))
+    np.testing.assert_allclose(r[0], 6000.0 * ben - 20.0 * prem, rtol=1e-12)
+    # the sick state's reserve: the same sums from state 1, without premiums
+    e1 = np.array([0.0, 1.0, 0.0])
+    prem1 = sum(V_FLAT ** t * (e1 @ np.linalg.matrix_power(W, t))[0] for t in range(S))
+    ben1 = sum(V_FLAT ** t * e1 @ np.linalg.matrix_power(W, t) @ c for t in range(1, S + 1))
+    np.testing.assert_allclose(r[1], 6000.0 * ben1 - 20.0 * prem1, rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [8, 9])
+def test_markov_recurrence_equals_summation(seed):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=10, n_steps=40, n_scen=2, n_nodes=2, shock=True)
+    n_ages = w.basis.q.shape[1]
+    raw = rng.uniform(0.0, 1.0, (2, n_ages, 4, 4))
+    raw[:, :, 3, :] = [0, 0, 0, 1]                   # an absorbing state
+    W = raw / raw.sum(axis=3, keepdims=True)
+    c = rng.uniform(-1.0, 2.0, (2, 4))
+    pf = synth.with_markov_policies(rng, w.portfolio, (W, c), frac=1.0)
+    b = w.basis
+    for node in range(2):
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=1, node_step=5)
+        for i in range(pf.n):
+            if int(pf.term_m[i]) - 5 * node <= 0:
+                continue
+            summ = oracle.reserve_path_summation(b, pf, i, node=node, scen=1, node_step=5)
+            scale = np.abs(summ).max() + 1e-300
+            np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=0,
+                                       atol=1e-12 * scale)
+
+
+def test_markov_node_shift_equals_path():
+    w, c = synth.phi_models(N_AGES)
+    b = Basis(q=np.atleast_2d(gm(1.0)), v=np.full((4, 1, 600), V_FLAT))
+    pf = _mk_pf((w, c), [0, 1, 0], [600, 650, 700], [500, 400, 300], [1200.0, 900.0, 600.0],
+                premium=[3.0, 0.0, 1.0])
+    path, off = oracle.reserve_paths(b, pf, node=0)
+    full = oracle.reserves(b, pf, node_step=12)
+    for k in range(4):
+        for i in range(pf.n):
+            assert full["r_all"][k, i, 0, 0] == path[off[i] + 12 * k]
