@@ -84,6 +84,14 @@ typedef struct rr_ctx rr_ctx;
                               RR_OUT_ALL_STATES the 9-state reserves are reported as (both alive,
                               life 1 only, life 2 only, none). */
 
+#define RR_MARKOV      11  /* one life on an uploaded Markov model (rr_markov_upload; table1 =
+                              model, age1_m indexes its tables): starts in state 0, pays
+                              amount x benefit[state] at the end of each month that ends in
+                              that state, premium in advance while in state 0, r_S = 0
+                              (Sec. 4.7: reversible models, W not upper triangular).  The
+                              node shock does not apply to uploaded models.  With
+                              RR_OUT_ALL_STATES slot j is the reserve of state j. */
+
 #define RR_ADVANCE 0       /* annuity paid at the start of each month (f = 0) */
 #define RR_ARREARS 1       /* annuity paid at the end of each month (f = 1) */
 
@@ -266,6 +274,26 @@ int rr_curves_generate_vasicek(rr_ctx *ctx, const rr_vasicek *vs);
  * r[n_nodes][n_scen][n_steps + 1] (r[..][0] = r0). */
 int rr_vasicek_curves(rr_ctx *ctx, const rr_vasicek *vs, int32_t n_nodes, int32_t n_scen,
                       int32_t n_steps, double *v, double *r);
+
+/*
+ * Markov models for RR_MARKOV policies (Sec. 4.7), copied to the device:
+ *   w[n_models][n_ages][n_states][n_states]  one-month transition probabilities
+ *       by attained age in months; row i = state at the start of the month;
+ *       entries in [0, 1], each row summing to 1 within 1e-12;
+ *   benefit[n_models][n_states]  paid per unit amount at the end of a month
+ *       that ends in the state (finite).
+ * 2 <= n_states <= 4, n_ages >= 2, n_models >= 1.  Replaces earlier models;
+ * a loaded portfolio that the new models do not cover is dropped.
+ */
+typedef struct {
+    int32_t n_models;
+    int32_t n_states;
+    int32_t n_ages;
+    const double *w;
+    const double *benefit;
+    int32_t mem_kind;
+} rr_markov;
+int rr_markov_upload(rr_ctx *ctx, const rr_markov *m);
 
 /* Length in doubles of the RR_OUT_PATH buffer for a node. */
 int rr_path_size(rr_ctx *ctx, int32_t node, int32_t node_step_m, int64_t *n_out);

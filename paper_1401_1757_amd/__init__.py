@@ -17,7 +17,13 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ERANGE, RR_ESTATE = 0, -1, -2, -3, -4, -5
 SL_ANN, JL_ANN, REV_ANN, LS_ANN, TERM, ENDOW, ENDOW_ASSUR, CF_TABLE = range(8)
-JL_ENDOW, JL_ASSUR1, JL_ASSUR2 = 8, 9, 10
+JL_ENDOW, JL_ASSUR1, JL_ASSUR2, MARKOV = 8, 9, 10, 11
+
+
+class Markov(ctypes.Structure):
+    _fields_ = [("n_models", ctypes.c_int32), ("n_states", ctypes.c_int32),
+                ("n_ages", ctypes.c_int32), ("w", ctypes.c_void_p), ("benefit", ctypes.c_void_p),
+                ("mem_kind", ctypes.c_int32)]
 
 
 class Vasicek(ctypes.Structure):
@@ -46,7 +52,7 @@ EXPORTS = (
     "rr_surrogate_gradients", "rr_surrogate_adam_step", "rr_surrogate_features",
     "rr_basis_generate_vasicek", "rr_curves_generate_vasicek", "rr_vasicek_curves",
     "rr_node_surrogate_train", "rr_node_surrogate_infer", "rr_node_surrogate_get_weights",
-    "rr_node_surrogate_set_weights", "rr_node_expected_reserves",
+    "rr_node_surrogate_set_weights", "rr_node_expected_reserves", "rr_markov_upload",
 )
 
 # Surrogate dimensions (include/rr.h).
@@ -203,6 +209,7 @@ def load_library(path: str = LIB_PATH):
                                           ctypes.c_int),
         "rr_node_surrogate_set_weights": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "rr_node_expected_reserves": ([vp, ctypes.POINTER(Run), vp, vp], ctypes.c_int),
+        "rr_markov_upload": ([vp, ctypes.POINTER(Markov)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -352,6 +359,13 @@ class Context:
         self._check(self.lib.rr_vasicek_curves(self.h, ctypes.byref(vs), n_nodes, n_scen, n_steps,
                                                v.data_ptr(), None if r is None else r.data_ptr()))
         return v, r
+
+    def markov_upload(self, w, benefit):
+        """Markov models for MARKOV policies: w [models][ages][m][m], benefit [models][m]."""
+        w = _np(w, np.float64)
+        c = _np(benefit, np.float64)
+        st = Markov(w.shape[0], w.shape[2], w.shape[1], w.ctypes.data, c.ctypes.data, HOST)
+        self._check(self.lib.rr_markov_upload(self.h, ctypes.byref(st)))
 
     def portfolio_upload(self, pf):
         keep = []

@@ -135,6 +135,12 @@ struct rr_ctx {
     DevBuf<double> cf_t;                  // [cf_steps][cf_cols] (table tiles)
     int cf_cols = 0;
     bool has_flow = false;                // some tile is not FLOW_LEVEL
+
+    // uploaded Markov models
+    bool has_markov = false;
+    int mk_models = 0, mk_states = 0, mk_ages = 0;
+    std::vector<double> mk_c_host;        // [model][mk_states] benefits
+    DevBuf<double> mk_w;                  // [model][mk_ages][4][4]
     DevBuf<Tile> tiles;
     int gen = 0;                          // bumps on every upload
 

@@ -137,7 +137,8 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
                                           const double *premium, const double *escalation,
                                           const int32_t *anniv, const int32_t *annual,
                                           const int32_t *cf_row, const double *cf, int cf_n_rows,
-                                          int cf_len, int n_steps, int n_ages, int n_tables)
+                                          int cf_len, int n_steps, int n_ages, int n_tables,
+                                          int mk_models = -1, int mk_ages = -1)
 {
     char b[256];
     if (n < 0) return "portfolio: n must be >= 0";
@@ -155,7 +156,7 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
         return "portfolio: product, age1_m, term_m, table1 and amount must not be NULL";
     for (int i = 0; i < n; ++i) {
         int pr = product[i];
-        if (pr < RR_SL_ANN || pr > RR_JL_ASSUR2) {
+        if (pr < RR_SL_ANN || pr > RR_MARKOV) {
             snprintf(b, sizeof b, "portfolio: policy %d has unknown product %d", i, pr);
             return b;
         }
@@ -163,14 +164,27 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
             snprintf(b, sizeof b, "portfolio: policy %d term %d outside [1, n_steps=%d]", i, term[i], n_steps);
             return b;
         }
-        if (age1[i] < 0 || (long long)age1[i] + term[i] > n_ages - 1) {
-            snprintf(b, sizeof b, "portfolio: policy %d age %d + term %d exceeds the tables (n_ages=%d)",
-                     i, age1[i], term[i], n_ages);
-            return b;
-        }
-        if (table1[i] < 0 || table1[i] >= n_tables) {
-            snprintf(b, sizeof b, "portfolio: policy %d table1 %d outside [0, %d)", i, table1[i], n_tables);
-            return b;
+        if (pr == RR_MARKOV) {   // table1 is the model; ages index its tables (-1: not known here)
+            if (mk_models == 0) return "portfolio: RR_MARKOV policies need rr_markov_upload first";
+            if (table1[i] < 0 || (mk_models > 0 && table1[i] >= mk_models)) {
+                snprintf(b, sizeof b, "portfolio: policy %d model %d outside [0, %d)", i, table1[i], mk_models);
+                return b;
+            }
+            if (age1[i] < 0 || (mk_ages > 0 && (long long)age1[i] + term[i] > mk_ages - 1)) {
+                snprintf(b, sizeof b, "portfolio: policy %d age %d + term %d exceeds the Markov tables (%d ages)",
+                         i, age1[i], term[i], mk_ages);
+                return b;
+            }
+        } else {
+            if (age1[i] < 0 || (long long)age1[i] + term[i] > n_ages - 1) {
+                snprintf(b, sizeof b, "portfolio: policy %d age %d + term %d exceeds the tables (n_ages=%d)",
+                         i, age1[i], term[i], n_ages);
+                return b;
+            }
+            if (table1[i] < 0 || table1[i] >= n_tables) {
+                snprintf(b, sizeof b, "portfolio: policy %d table1 %d outside [0, %d)", i, table1[i], n_tables);
+                return b;
+            }
         }
         if (is_two_life(pr)) {
             if (!age2 || !table2) return "portfolio: two-life products need age2_m and table2";
@@ -477,6 +491,10 @@ static int install_basis(rr_ctx *c, const rr_basis *b, std::vector<double> &q,
     bool keep_pf = c->has_pf;
     if (keep_pf) {
         for (int i = 0; i < c->n_user && keep_pf; ++i) {
+            if (c->h_product[i] == RR_MARKOV) {   // uploaded model: only the term matters here
+                if (c->h_term[i] > b->n_steps) keep_pf = false;
+                continue;
+            }
             int two = is_two_life(c->h_product[i]);
             int amax = std::max(c->h_age1[i], two ? c->h_age2[i] : 0) + c->h_term[i];
             int tmax = std::max(c->h_table1[i], two ? c->h_table2[i] : 0);
@@ -641,7 +659,9 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                                            escalation.data(), anniv.data(), annual.data(),
                                            p->cf_row ? cf_row.data() : nullptr,
                                            p->cf ? cf.data() : nullptr, p->cf_n_rows, p->cf_len,
-                                           c->n_steps, c->n_ages, c->n_tables);
+                                           c->n_steps, c->n_ages, c->n_tables,
+                                           c->has_markov ? c->mk_models : 0,
+                                           c->has_markov ? c->mk_ages : 0);
     if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
 
     drop_graphs(c);
@@ -654,9 +674,12 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     std::vector<int32_t> patterned(n, 0), flow(n, FLOW_LEVEL);
     for (size_t i = 0; i < n; ++i) {
         patterned[i] = (escalation[i] > 0.0 || annual[i] == 1) ? 1 : 0;
-        flow[i] = product[i] == RR_CF_TABLE ? FLOW_TABLE : patterned[i] ? FLOW_PATTERN : FLOW_LEVEL;
+        flow[i] = product[i] == RR_CF_TABLE ? FLOW_TABLE
+                  : product[i] == RR_MARKOV ? FLOW_MARKOV
+                  : patterned[i]            ? FLOW_PATTERN
+                                            : FLOW_LEVEL;
     }
-    auto group_of = [&](int u) { return 3 * kind_of(product[u]) + flow[u]; };
+    auto group_of = [&](int u) { return N_FLOWS * kind_of(product[u]) + flow[u]; };
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     // Within a model, remaining terms are bucketed (width term_bucket months,
@@ -685,8 +708,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
         while (i1 < n && group_of(order[i1]) == group) ++i1;
         for (size_t a = i0; a < i1; a += TILE) {
             Tile T;
-            T.kind = group / 3;
-            T.flow = group % 3;
+            T.kind = group / N_FLOWS;
+            T.flow = group % N_FLOWS;
             T.first = (int)s_uidx.size();
             T.smax = 0;
             T.smin = 1 << 30;
@@ -699,11 +722,12 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                     bool two = is_two_life(product[u]);
                     s_age2.push_back(two ? age2[u] : 0);
                     s_term.push_back(term[u]);
-                    s_qoff1.push_back(table1[u]);   // scaled below
+                    const bool mk = product[u] == RR_MARKOV;   // no mortality table
+                    s_qoff1.push_back(mk ? 0 : table1[u]);   // scaled below
                     s_qoff2.push_back(two ? table2[u] : 0);
                     T.smax = std::max(T.smax, term[u]);
                     T.smin = std::min(T.smin, term[u]);
-                    max_age = std::max(max_age, age1[u] + term[u]);
+                    if (!mk) max_age = std::max(max_age, age1[u] + term[u]);
                     if (two) max_age = std::max(max_age, age2[u] + term[u]);
                 } else {
                     s_uidx.push_back(-1);
@@ -784,6 +808,11 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
             C(0, j) = -P;
             C(6, j) = amount[u];
             break;
+        case RR_MARKOV:        // premium in state 0, benefits per state
+            C(0, j) = -P;
+            for (int st = 0; st < c->mk_states; ++st)
+                C(1 + st, j) = amount[u] * c->mk_c_host[(size_t)table1[u] * c->mk_states + st];
+            break;
         case RR_REV_ANN:
             C(0, j) = -P;
             C(4, j) = adv ? pay : 0.0;
@@ -829,6 +858,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                 const int u = s_uidx[j];
                 if (T.flow == FLOW_TABLE) {
                     pc[j] = j - first_tab;   // table tiles are consecutive
+                } else if (T.flow == FLOW_MARKOV) {
+                    pc[j] = u >= 0 ? table1[u] : 0;   // the model
                 } else if (T.flow == FLOW_PATTERN && u >= 0) {
                     pg[j] = 1.0 + escalation[u];
                     pc[j] = anniv[u] | (annual[u] ? PAT_ANNUAL : 0) |
@@ -911,6 +942,57 @@ extern "C" int rr_node_expected_reserves(rr_ctx *c, const rr_run *run, double *n
     c->pad_override = 0;
     c->opt_graph = graph;
     return rc;
+}
+
+extern "C" int rr_markov_upload(rr_ctx *c, const rr_markov *m)
+{
+    if (!c) return RR_EINVAL;
+    if (!m) return fail(c, RR_EINVAL, "markov: models are NULL");
+    if (m->mem_kind != RR_HOST && m->mem_kind != RR_DEVICE) return fail(c, RR_EINVAL, "bad mem_kind");
+    if (m->n_models < 1 || m->n_states < 2 || m->n_states > 4 || m->n_ages < 2)
+        return fail(c, RR_EINVAL, "markov: need n_models >= 1, 2 <= n_states <= 4, n_ages >= 2");
+    if (!m->w || !m->benefit) return fail(c, RR_EINVAL, "markov: w and benefit must not be NULL");
+    const int M = m->n_states;
+    if ((long long)m->n_models * m->n_ages * 16 > (1LL << 31)) return fail(c, RR_EINVAL, "markov: tables too large");
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<double> w, ben;
+    int rc;
+    if ((rc = fetch(c, m->w, (size_t)m->n_models * m->n_ages * M * M, m->mem_kind, w))) return rc;
+    if ((rc = fetch(c, m->benefit, (size_t)m->n_models * M, m->mem_kind, ben))) return rc;
+    for (size_t k = 0; k < ben.size(); ++k)
+        if (!std::isfinite(ben[k])) return fail(c, RR_EINVAL, "markov: benefit[%zu] is not finite", k);
+    std::vector<double> wp((size_t)m->n_models * m->n_ages * 16, 0.0);
+    for (int md = 0; md < m->n_models; ++md)
+        for (int a = 0; a < m->n_ages; ++a)
+            for (int i = 0; i < M; ++i) {
+                double sum = 0.0;
+                for (int j = 0; j < M; ++j) {
+                    const double x = w[(((size_t)md * m->n_ages + a) * M + i) * M + j];
+                    if (!(x >= 0.0 && x <= 1.0))
+                        return fail(c, RR_EINVAL, "markov: model %d age %d w[%d][%d] = %g is not a probability",
+                                    md, a, i, j, x);
+                    sum += x;
+                    wp[(((size_t)md * m->n_ages + a) * 4 + i) * 4 + j] = x;
+                }
+                if (std::fabs(sum - 1.0) > 1e-12)
+                    return fail(c, RR_EINVAL, "markov: model %d age %d row %d sums to %.17g", md, a, i, sum);
+            }
+    HIPCHK(c, c->mk_w.alloc(wp.size()));
+    HIPCHK(c, hipMemcpy(c->mk_w.p, wp.data(), wp.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->mk_c_host.swap(ben);
+    c->mk_models = m->n_models;
+    c->mk_states = M;
+    c->mk_ages = m->n_ages;
+    c->has_markov = true;
+    // A portfolio with RR_MARKOV policies holds the old benefits: drop it.
+    bool has_mk = false;
+    for (int i = 0; i < c->n_user; ++i) has_mk |= c->h_product[i] == RR_MARKOV;
+    if (c->has_pf && has_mk) c->has_pf = false;
+    drop_graphs(c);
+    c->plans.clear();
+    c->tuned.clear();
+    ++c->gen;
+    return RR_OK;
 }
 
 extern "C" int rr_path_size(rr_ctx *c, int32_t node, int32_t node_step_m, int64_t *n_out)
@@ -1021,6 +1103,8 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.pat_code = c->has_flow ? c->pat_code.p : nullptr;
     P.cf_t = (c->has_flow && c->cf_cols > 0) ? c->cf_t.p : nullptr;
     P.cf_cols = c->cf_cols;
+    P.mk_w = c->has_markov ? c->mk_w.p : nullptr;
+    P.mk_ages = c->mk_ages;
     P.n_pad = c->n_pad;
     P.n_user = c->n_user;
     P.tiles = c->tiles.p;

@@ -37,14 +37,17 @@ constexpr int WG_THREADS = RR_WG_THREADS;   // wavefronts per workgroup x 64
 //                             2/3: advance/arrears amount in state 01
 //                             4/5: advance/arrears amount in state 10
 //                             6: KIND_LAST: benefit on the second death (end of its step)
+//  Markov tiles:              0: a0 = - premium (state 0), 1..4: amount x benefit of states 0..3
 
 // How a tile's cash flows vary in time.  Tiles other than level ones run
 // one tile per item.
 enum Flow : int {
     FLOW_LEVEL = 0,     // level amounts (coef rows)
     FLOW_PATTERN = 1,   // annuities in payment with escalation or annual payment
-    FLOW_TABLE = 2      // single life, cash flow of step t from a per-policy table
+    FLOW_TABLE = 2,     // single life, cash flow of step t from a per-policy table
+    FLOW_MARKOV = 3     // one life on an uploaded Markov model (up to 4 states)
 };
+constexpr int N_FLOWS = 4;
 
 struct Tile {
     int kind;
@@ -91,6 +94,8 @@ struct RecParams {
     const int *pat_code;      // [n_pad] anniversary / annual / timing code or table column, or null
     const double *cf_t;       // [cf_steps][cf_cols] amount x table value of the step, or null
     int cf_cols;
+    const double *mk_w;       // [model][mk_ages][4][4] uploaded Markov matrices (zero padded)
+    int mk_ages;
     int n_pad;
     int n_user;
     const Tile *tiles;

@@ -67,7 +67,7 @@ template <int K>
 __device__ __forceinline__ void store_results(const RecParams &P, int node_rel, int tile, int sb,
                                               int lane, int uid, bool live, const double (&r0)[K],
                                               const double (&r1)[K], const double (&r2)[K],
-                                              bool has1, bool has2)
+                                              bool has1, bool has2, const double *r3 = nullptr)
 {
     if (P.r0 != nullptr && uid >= 0) {
         double *o = P.r0 + (((size_t)node_rel * P.n_user + uid) * P.scen_count + sb) * P.r0_states;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void store_results(const RecParams &P, int node_rel, 
                     o[4 * k + 0] = live ? r0[k] : 0.0;
                     o[4 * k + 1] = (live && has1) ? r1[k] : 0.0;
                     o[4 * k + 2] = (live && has2) ? r2[k] : 0.0;
-                    o[4 * k + 3] = 0.0;
+                    o[4 * k + 3] = (live && r3 != nullptr) ? r3[k] : 0.0;
                 }
             }
         }
@@ -597,6 +597,91 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
     store_results<K>(P, node_rel, tile, sb, lane, uid, live, r0, r1, r2, LAST, true);
 }
 
+// One life on an uploaded Markov model (Sec. 4.7; the matrix need not be
+// upper triangular): up to four states, zero padded to four.  With y = c +
+// r' per state (c: the benefits paid at the end of a month ending in the
+// state) and W_t the model's matrix at the attained age:
+//   r_i <- a_i + v * sum_j W_t[i][j] * y_j,  a_0 = - premium, a_i = 0 else.
+// The lane's matrix of the next step is loaded while the current one is used.
+template <int K>
+__device__ __forceinline__ void run_markov(const RecParams &P, const double *__restrict__ vcurves,
+                                           int node_rel, int tile, const Tile &T, int sb, int lane)
+{
+    const int node = P.node_begin + node_rel;
+    const int shift = node * P.node_step;
+    const int slot = T.first + lane;
+    const int S = P.term[slot] - shift;
+    const int uid = P.uidx[slot];
+    const bool live = (uid >= 0) && (S > 0);
+    const int smax = T.smax - shift;
+    const double a0 = P.coef[slot];
+    double c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = P.coef[(1 + j) * P.n_pad + slot];
+    // rows of the model at the policy's attained age at t = 0 (padding lanes: model 0, age 0)
+    const int age0 = uid >= 0 ? P.age1[slot] + shift : 0;
+    const double2 *wb = reinterpret_cast<const double2 *>(
+        P.mk_w + ((size_t)P.pat_code[slot] * P.mk_ages + age0) * 16);
+    const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
+
+    double r[4][K];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < K; ++k) r[i][k] = 0.0;
+    double *path = nullptr;
+    if constexpr (K == 1) {
+        if (P.path != nullptr && uid >= 0) {
+            if (live) {
+                path = P.path + P.path_off[uid];
+                path[S] = 0.0;
+            } else {
+                P.path[P.path_off[uid]] = 0.0;   // expired: its one entry is 0
+            }
+        }
+    }
+    // The lane starts at its own last step (t < S); padding and expired
+    // lanes take no step (S <= 0).
+    int t = min(S, smax) - 1;
+    double2 wn[8];
+    if (t >= 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) wn[e] = wb[(size_t)t * 8 + e];
+    }
+    for (; t >= 0; --t) {
+        double w[16];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            w[2 * e] = wn[e].x;
+            w[2 * e + 1] = wn[e].y;
+        }
+        if (t > 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) wn[e] = wb[(size_t)(t - 1) * 8 + e];
+        }
+        const double *vt = vb + (ptrdiff_t)t * P.scen_pad;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double v = vt[k];
+            double y[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) y[j] = c[j] + r[j][k];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double acc = w[4 * i] * y[0];
+                acc = fma(w[4 * i + 1], y[1], acc);
+                acc = fma(w[4 * i + 2], y[2], acc);
+                acc = fma(w[4 * i + 3], y[3], acc);
+                r[i][k] = fma(v, acc, i == 0 ? a0 : 0.0);
+            }
+        }
+        if constexpr (K == 1) {
+            if (path != nullptr) path[t] = r[0][0];
+        }
+    }
+    store_results<K>(P, node_rel, tile, sb, lane, uid, live, r[0], r[1], r[2], true, true, r[3]);
+}
+
 // Persistent grid: each wavefront takes items from its XCD's queue (the
 // hardware places workgroup b on XCD b mod 8), then steals from the others.
 // The read-only inputs are separate __restrict__ arguments so that the
@@ -647,7 +732,9 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
         }
         if (PAT && T.flow != FLOW_LEVEL) {
             if constexpr (PAT) {
-                if (T.flow == FLOW_TABLE)
+                if (T.flow == FLOW_MARKOV)
+                    run_markov<K>(P, vcurves, node_rel, tile, T, sb, lane);
+                else if (T.flow == FLOW_TABLE)
                     run_scalar<K, 1, LDSQ, false, FLOW_TABLE>(P, s_q, vcurves, node_rel, tile, 1, T,
                                                               T.smax, T.smin, sb, lane);
                 else if (T.kind == KIND_SINGLE)

@@ -576,6 +576,10 @@ def with_markov_policies(rng, pf: Portfolio, models: tuple, frac: float = 0.3) -
     out.product = np.where(pick, MARKOV, pf.product).astype(np.int32)
     out.table1 = np.where(pick, rng.integers(0, models[0].shape[0], pf.n), pf.table1).astype(np.int32)
     out.age2_m = np.where(pick, 0, pf.age2_m).astype(np.int32)
+    if out.escalation is not None:            # payment patterns are for annuities only
+        out.escalation = np.where(pick, 0.0, out.escalation)
+    if out.annual is not None:
+        out.annual = np.where(pick, 0, out.annual).astype(np.int32)
     out.markov = models
     return out
 

@@ -56,7 +56,7 @@ def test_portfolio_checks(rr):
     cases = {
         "term": ("term_m", 7, 601, "policy 7 term 601"),
         "term0": ("term_m", 3, 0, "policy 3 term 0"),
-        "product": ("product", 11, 12, "policy 11 has unknown product 12"),
+        "product": ("product", 11, 13, "policy 11 has unknown product 13"),
         "age": ("age1_m", 5, n_ages, "policy 5 age"),
         "table": ("table1", 2, 3, "policy 2 table1 3"),
         "timing": ("timing", 9, 2, "policy 9 timing 2"),
@@ -178,5 +178,22 @@ def test_cash_flow_table_checks(rr):
     assert "is not finite" in rr.check_portfolio(bad, 120, n_ages, 2)
     bad = ok.subset(np.arange(ok.n)); bad.cf = None
     assert "need cf_row and cf" in rr.check_portfolio(bad, 120, n_ages, 2)
-    bad = ok.subset(np.arange(ok.n)); bad.product[i] = 11
-    assert f"policy {i} has unknown product 11" in rr.check_portfolio(bad, 120, n_ages, 2)
+    bad = ok.subset(np.arange(ok.n)); bad.product[i] = 12
+    assert f"policy {i} has unknown product 12" in rr.check_portfolio(bad, 120, n_ages, 2)
+
+
+def test_markov_policy_checks(rr):
+    """Without a context the model bounds are unknown: the host check takes
+    the model index and age as non-negative; the context's upload checks
+    them against the uploaded models (GPU tests)."""
+    rng = np.random.default_rng(4)
+    w = synth.random_small(rng, n=20, n_steps=60, n_scen=1)
+    n_ages = w.basis.q.shape[1]
+    pf = synth.with_markov_policies(rng, w.portfolio, synth.phi_models(n_ages), frac=0.5)
+    i = int(np.flatnonzero(pf.product == synth.MARKOV)[0])
+    pf.table1[i] = 7                                  # beyond the q tables: fine for a model
+    assert rr.check_portfolio(pf, 60, n_ages, 2) == ""
+    bad = pf.subset(np.arange(pf.n)); bad.table1[i] = -1
+    assert f"policy {i} model -1" in rr.check_portfolio(bad, 60, n_ages, 2)
+    bad = pf.subset(np.arange(pf.n)); bad.age1_m[i] = -3
+    assert f"policy {i} age -3" in rr.check_portfolio(bad, 60, n_ages, 2)

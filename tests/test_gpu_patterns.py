@@ -283,3 +283,90 @@ def test_two_life_insurance_paths(ctx):
         ref = oracle.reserves(b, pf, node, 1, scen, 1, 12)
         gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
         assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
+
+
+# ---------------------------------------------------------------------------
+# Policies on uploaded Markov models (Sec. 4.7)
+# ---------------------------------------------------------------------------
+def markov_workload(seed, n, n_steps, n_scen, n_nodes, models=None, frac=0.4, node_step=7):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=n, n_steps=n_steps, n_scen=n_scen, n_nodes=n_nodes, shock=True,
+                           products=tuple(range(7)) + TWO_LIFE_INS)
+    n_ages = w.basis.q.shape[1]
+    if models is None:
+        models = synth.phi_models(n_ages)
+    pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=0.1, n_rows=3)
+    pf = synth.with_payment_patterns(rng, pf, 0.4, 0.3)
+    pf = synth.with_markov_policies(rng, pf, models, frac=frac)
+    return synth.Workload("markov", w.basis, pf, node_step_m=node_step)
+
+
+@pytest.mark.parametrize("K,J", [(1, 1), (2, 1), (8, 1), (16, 1), (32, 1), (8, 2), (4, 4), (16, 4)])
+def test_markov_policies_with_every_other_kind(ctx, K, J):
+    w = markov_workload(1300 + K + 7 * J, n=500, n_steps=90, n_scen=2 * K + 3, n_nodes=3)
+    assert (w.portfolio.product == synth.MARKOV).sum() > 100
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.markov_upload(*w.portfolio.markov)
+    ctx.portfolio_upload(w.portfolio)
+    ctx.set_option(1, K)
+    ctx.set_option(8, J)
+    _say(f"markov K={K} J={J}")
+    compare(ctx, w)
+
+
+def test_random_four_state_models_all_states(ctx):
+    rng = np.random.default_rng(1400)
+    n_ages = 900 + 120 + 1
+    raw = rng.uniform(0.0, 1.0, (3, n_ages, 4, 4))
+    raw[:, :, 3, :] = [0.0, 0.0, 0.0, 1.0]
+    W = raw / raw.sum(axis=3, keepdims=True)
+    c = rng.uniform(-1.0, 2.0, (3, 4))
+    w = markov_workload(1401, n=200, n_steps=120, n_scen=9, n_nodes=2, models=(W, c), frac=1.0,
+                        node_step=12)
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.markov_upload(W, c)
+    ctx.portfolio_upload(w.portfolio)
+    _say("random 4-state models")
+    compare(ctx, w)
+    # paths at two nodes
+    b, pf = w.basis, w.portfolio
+    for node, scen in ((0, 3), (1, 8)):
+        po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=node, node_step=12)
+        po["path"].fill_(float("nan"))
+        ctx.reserve_recurrence(node, 1, scen, 1, 12, po)
+        torch.cuda.synchronize()
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=scen, node_step=12)
+        ref = oracle.reserves(b, pf, node, 1, scen, 1, 12)
+        gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+        assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
+
+
+def test_markov_invalid_uploads(ctx, rr):
+    w = markov_workload(1500, n=50, n_steps=60, n_scen=2, n_nodes=1)
+    b, pf = w.basis, w.portfolio
+    W, c = pf.markov
+    ctx.basis_upload(b.q, b.v, b.shock)
+    with pytest.raises(rr.RRError, match="need rr_markov_upload"):
+        ctx.portfolio_upload(pf)
+    bad = W.copy(); bad[0, 5, 1, 0] += 0.01
+    with pytest.raises(rr.RRError, match="row 1 sums"):
+        ctx.markov_upload(bad, c)
+    bad = W.copy(); bad[1, 7, 0, 0] = -0.1; bad[1, 7, 0, 1] += 0.1
+    with pytest.raises(rr.RRError, match="not a probability"):
+        ctx.markov_upload(bad, c)
+    cb = c.copy(); cb[0, 1] = np.nan
+    with pytest.raises(rr.RRError, match="benefit"):
+        ctx.markov_upload(W, cb)
+    with pytest.raises(rr.RRError, match="n_states"):
+        ctx.markov_upload(np.zeros((1, 10, 5, 5)), np.zeros((1, 5)))
+    ctx.markov_upload(W, c)
+    pf2 = pf.subset(np.arange(pf.n))
+    i = int(np.flatnonzero(pf2.product == synth.MARKOV)[0])
+    pf2.table1[i] = W.shape[0]
+    with pytest.raises(rr.RRError, match=f"policy {i} model"):
+        ctx.portfolio_upload(pf2)
+    ctx.portfolio_upload(pf)
+    ctx.markov_upload(W, c)                      # new models: the portfolio is dropped
+    out = ctx.alloc_outputs(1, 2)
+    with pytest.raises(rr.RRError):
+        ctx.reserve_recurrence(0, 1, 0, 2, 12, out)
