@@ -39,7 +39,7 @@ class _Basis(ctypes.Structure):
     _fields_ = [("n_ages", ctypes.c_int), ("n_tables", ctypes.c_int),
                 ("q", ctypes.c_void_p), ("n_nodes", ctypes.c_int),
                 ("n_scen", ctypes.c_int), ("n_steps", ctypes.c_int),
-                ("v", ctypes.c_void_p), ("shock", ctypes.c_void_p)]
+                ("v", ctypes.c_void_p), ("shock", ctypes.c_void_p), ("frac", ctypes.c_double)]
 
 
 class _Portfolio(ctypes.Structure):
@@ -94,7 +94,8 @@ class _Args:
         self.v = np.ascontiguousarray(basis.v, np.float64)
         self.shock = None if basis.shock is None else np.ascontiguousarray(basis.shock, np.float64)
         self.b = _Basis(self.q.shape[1], self.q.shape[0], _ptr(self.q), self.v.shape[0],
-                        self.v.shape[1], self.v.shape[2], _ptr(self.v), _ptr(self.shock))
+                        self.v.shape[1], self.v.shape[2], _ptr(self.v), _ptr(self.shock),
+                        float(getattr(basis, "frac", 0.0) or 0.0))
         i32 = lambda x: np.ascontiguousarray(x, np.int32)
         f64 = lambda x: np.ascontiguousarray(x, np.float64)
         opt = lambda x, f: None if x is None else f(x)

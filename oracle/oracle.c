@@ -25,8 +25,8 @@
  *     f = 0 in state 0, annuity payments at f = 0 or 1 (policy timing), death
  *     benefits at f = 1 in the died-in-step state.
  *   - For f in (0, 1) the fractional death probability is f*q (uniform
- *     distribution of deaths) and the discount is v^f; products here use
- *     f in {0, 1} only, where this is exact.
+ *     distribution of deaths) and the discount is v^f; annuities with timing
+ *     2 pay at the basis's fraction f of each month.
  *   - Time t counts months since the node; life l has attained age
  *     age_l + node*node_step + t (equivalent to the paper's age-shift form by
  *     the cash-flow shift identity, Eq. (3.2)).
@@ -69,6 +69,7 @@ typedef struct {
     int n_steps;
     const double *v;        /* [n_nodes][n_scen][n_steps] one-step discount */
     const double *shock;    /* [n_nodes] multiplier on q, or NULL */
+    double frac;            /* payment point of timing-2 annuities within the month, in (0, 1) */
 } orc_basis;
 
 typedef struct {
@@ -203,8 +204,8 @@ int orc_contract_of(int product, int timing, double amount, double premium,
     double prem = gross ? fabs(premium) : -premium;
     double pay = (gross ? fabs(amount) : amount) / 12.0;    /* monthly annuity */
     double sa = gross ? fabs(amount) : amount;
-    if (timing != 0 && timing != 1) return -1;
-    k->f_ann = (double)timing;
+    if (timing < 0 || timing > 2) return -1;
+    k->f_ann = timing == 2 ? 0.5 : (double)timing;   /* 2: the basis's fraction, set by contract_for */
     switch (product) {
     case O_SL_ANN:       /* Sec. 4.1.1: c = (theta, 0) */
         k->n_lives = 1; k->life_model = 2; k->n_states = 2;
@@ -287,10 +288,13 @@ static void step_q(const orc_basis *b, const orc_portfolio *p, int i,
     q[1] = q_at(b, p->table2[i], p->age2[i] + age_shift + t, m);
 }
 
-/* The contract of policy i (an uploaded model: its size and benefits). */
-static void contract_for(const orc_portfolio *p, int i, int gross, orc_contract *k)
+/* The contract of policy i (an uploaded model: its size and benefits; a
+ * fractional timing: the basis's payment point). */
+static void contract_for(const orc_basis *b, const orc_portfolio *p, int i, int gross,
+                         orc_contract *k)
 {
     orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], gross, k);
+    if (p->timing[i] == 2) k->f_ann = b->frac;
     if (p->product[i] == O_MARKOV) {
         int m = p->mk_states;
         const double *c = p->mk_c + (size_t)p->table1[i] * m;
@@ -407,6 +411,8 @@ static int validate(const orc_basis *b, const orc_portfolio *p)
         if (p->product[i] < 0 || p->product[i] >= O_N_PRODUCTS) return -1;
         if (p->term[i] < 1 || p->term[i] > b->n_steps) return -1;
         if (p->anniv && (p->anniv[i] < 1 || p->anniv[i] > 12)) return -1;
+        if (p->timing[i] < 0 || p->timing[i] > 2) return -1;
+        if (p->timing[i] == 2 && !(b->frac > 0.0 && b->frac < 1.0)) return -1;
         if (p->escalation && !(p->escalation[i] >= 0.0)) return -1;
         if (p->product[i] == O_MARKOV) {   /* table1 is the model, ages index its tables */
             if (!p->mk_w || !p->mk_c || p->mk_states < 2 || p->mk_states > 4) return -1;
@@ -457,8 +463,8 @@ int orc_reserves(const orc_basis *b, const orc_portfolio *p, int node0, int nnod
 #pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
     for (int i = 0; i < n; ++i) {
         orc_contract k, kg;
-        contract_for(p, i, 0, &k);
-        contract_for(p, i, 1, &kg);
+        contract_for(b, p, i, 0, &k);
+        contract_for(b, p, i, 1, &kg);
         double r0[ORC_MAX_STATES], g0[ORC_MAX_STATES];
         for (int a = 0; a < nnode; ++a) {
             int node = node0 + a;
@@ -530,7 +536,7 @@ int orc_reserve_paths(const orc_basis *b, const orc_portfolio *p, int node, int 
         if (S <= 0) { path[off[i]] = 0.0; continue; }
         orc_contract k;
         double r0[ORC_MAX_STATES];
-        contract_for(p, i, 0, &k);
+        contract_for(b, p, i, 0, &k);
         const double *vc = b->v + ((size_t)node * b->n_scen + scen) * b->n_steps;
         recurrence_one(b, p, i, &k, node, node * node_step, S, vc, r0, path + off[i]);
     }
@@ -556,7 +562,7 @@ int orc_reserve_path_summation(const orc_basis *b, const orc_portfolio *p, int i
     int S = p->term[i] - shift;
     if (S <= 0) return -1;
     orc_contract k;
-    contract_for(p, i, 0, &k);
+    contract_for(b, p, i, 0, &k);
     int n = k.n_states;
     double m = b->shock ? b->shock[node] : 1.0;
     const double *vc = b->v + ((size_t)node * b->n_scen + scen) * b->n_steps;

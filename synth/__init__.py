@@ -53,6 +53,7 @@ TWO_LIFE = (JL_ANN, REV_ANN, LS_ANN, 8, 9, 10)   # with the two-life endowment a
 
 ADVANCE = 0       # annuity paid at the start of each month (f = 0)
 ARREARS = 1       # annuity paid at the end of each month (f = 1)
+FRACTIONAL = 2    # annuity paid at the basis's fraction f of each month (0 < f < 1)
 
 GM_A, GM_B, GM_C = 5e-4, 7.5e-5, 1.1
 LIMIT_AGE_M = 1440   # 120 years in months
@@ -185,6 +186,7 @@ class Basis:
     q: np.ndarray           # float64 [n_tables, n_ages] monthly q by attained age (months)
     v: np.ndarray           # float64 [n_nodes, n_scen, n_steps] one-step discount factors
     shock: np.ndarray | None = None   # float64 [n_nodes] mortality multiplier or None
+    frac: float = 0.0                 # payment point of FRACTIONAL annuities within the month
 
     @property
     def n_nodes(self) -> int:

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from synth import (ADVANCE, ARREARS, CF_TABLE, ENDOW, ENDOW_ASSUR, JL_ASSUR1, JL_ASSUR2, JL_ENDOW, MARKOV, JL_ANN, LS_ANN,
+from synth import (ADVANCE, ARREARS, CF_TABLE, FRACTIONAL, ENDOW, ENDOW_ASSUR, JL_ASSUR1, JL_ASSUR2, JL_ENDOW, MARKOV, JL_ANN, LS_ANN,
                    REV_ANN, SL_ANN, TERM, Basis, Portfolio)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -751,3 +751,58 @@ def test_markov_node_shift_equals_path():
     for k in range(4):
         for i in range(pf.n):
             assert full["r_all"][k, i, 0, 0] == path[off[i] + 12 * k]
+
+
+# --------------------------------------------------------------------------
+# Fractional payment timing (Sec. 3.1's f in (0, 1); uniform deaths)
+# --------------------------------------------------------------------------
+def _frac_basis(q, v, f):
+    b = basis(q, v)
+    b.frac = f
+    return b
+
+
+@pytest.mark.parametrize("f", [0.25, 0.5, 0.9])
+def test_fractional_annuity_certain(f):
+    b = _frac_basis(np.zeros(N_AGES), np.full(600, V_FLAT), f)
+    S = 240
+    pf = make_pf([SL_ANN], 700, S, amount=1200.0, timing=FRACTIONAL)
+    want = 100.0 * V_FLAT ** f * (1 - V_FLAT ** S) / (1 - V_FLAT)
+    np.testing.assert_allclose(r0(b, pf)[0, 0], want, rtol=1e-13)
+
+
+@pytest.mark.parametrize("f", [0.3, 0.7])
+def test_fractional_timing_interpolates_without_discounting(f):
+    """v = 1: survival to t + f is (1 - f) + f p, so the single-life value is
+    (1 - f) x (advance) + f x (arrears); the joint-life value is the sum of
+    the joint survival to t times (1 - f qx)(1 - f qy)."""
+    q = np.vstack([gm(1.0), gm(1.3)])
+    b = _frac_basis(q, np.ones(600), f)
+    S = 300
+    sl = [make_pf([SL_ANN], 700, S, amount=1200.0, timing=t) for t in (FRACTIONAL, ADVANCE, ARREARS)]
+    r = [r0(b, p)[0, 0] for p in sl]
+    np.testing.assert_allclose(r[0], (1 - f) * r[1] + f * r[2], rtol=1e-13)
+    jl = make_pf([JL_ANN], 700, S, amount=1200.0, timing=FRACTIONAL, age2=650, table1=0, table2=1)
+    qx, qy = q[0, 700:700 + S], q[1, 650:650 + S]
+    surv = np.concatenate([[1.0], np.cumprod((1 - qx) * (1 - qy))[:-1]])
+    want = 100.0 * math.fsum(surv * (1 - f * qx) * (1 - f * qy))
+    np.testing.assert_allclose(r0(b, jl)[0, 0], want, rtol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_fractional_recurrence_equals_summation(seed):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=16, n_steps=50, n_scen=2, n_nodes=2, shock=True,
+                           products=(SL_ANN, JL_ANN, REV_ANN, LS_ANN))
+    b, pf = w.basis, w.portfolio
+    b.frac = 0.4
+    pf.timing[:] = FRACTIONAL
+    for node in range(2):
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=1, node_step=5)
+        for i in range(pf.n):
+            if int(pf.term_m[i]) - 5 * node <= 0:
+                continue
+            summ = oracle.reserve_path_summation(b, pf, i, node=node, scen=1, node_step=5)
+            scale = np.abs(summ).max() + 1e-300
+            np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=0,
+                                       atol=1e-12 * scale)
