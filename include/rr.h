@@ -94,6 +94,10 @@ typedef struct rr_ctx rr_ctx;
 
 #define RR_ADVANCE 0       /* annuity paid at the start of each month (f = 0) */
 #define RR_ARREARS 1       /* annuity paid at the end of each month (f = 1) */
+#define RR_FRACTIONAL 2    /* annuity paid at the basis's fraction frac of each month
+                              (0 < frac < 1): survival to t + frac by frac x the month's death
+                              probability (uniform deaths), discount v^frac (Sec. 3.1's f).
+                              RR_SL_ANN and RR_JL_ANN without payment patterns only. */
 
 #define RR_HOST   0        /* input arrays are in host memory */
 #define RR_DEVICE 1        /* input arrays are in device memory */
@@ -124,6 +128,8 @@ typedef struct {
     const double *v;
     const double *shock;
     int32_t mem_kind;        /* RR_HOST or RR_DEVICE, for all three arrays */
+    double frac;             /* payment point of RR_FRACTIONAL annuities, in (0, 1); 0 = none.
+                                The library keeps v^frac beside v (8 bytes per curve value). */
 } rr_basis;
 
 /*

@@ -36,7 +36,7 @@ def vasicek_struct(a, b, sigma, dt, r0, key, keep):
     keep.append(r0)
     k = (ctypes.c_uint64 * 2)(int(key[0]), int(key[1]))
     return Vasicek(a, b, sigma, dt, r0.ctypes.data, k)
-ADVANCE, ARREARS = 0, 1
+ADVANCE, ARREARS, FRACTIONAL = 0, 1, 2
 HOST, DEVICE = 0, 1
 OUT_R0, OUT_TOTALS, OUT_PATH, OUT_ALL_STATES, OUT_STATS = 1, 2, 4, 8, 16
 OPT_BLOCK_K, OPT_WG_PER_CU, OPT_USE_GRAPH, OPT_KERNEL_TIMING, OPT_XCD_QUEUES = 1, 2, 3, 4, 5
@@ -70,7 +70,7 @@ class Basis(ctypes.Structure):
                 ("q", ctypes.c_void_p), ("n_nodes", ctypes.c_int32),
                 ("n_scen", ctypes.c_int32), ("n_steps", ctypes.c_int32),
                 ("v", ctypes.c_void_p), ("shock", ctypes.c_void_p),
-                ("mem_kind", ctypes.c_int32)]
+                ("mem_kind", ctypes.c_int32), ("frac", ctypes.c_double)]
 
 
 class Portfolio(ctypes.Structure):
@@ -223,7 +223,7 @@ def _np(x, dt):
     return np.ascontiguousarray(x, dtype=dt)
 
 
-def basis_struct(q, v, shock=None, keep=None):
+def basis_struct(q, v, shock=None, keep=None, frac=0.0):
     """Host-memory rr_basis; `keep` collects the arrays that must outlive it."""
     q = _np(q, np.float64)
     v = _np(v, np.float64)
@@ -231,7 +231,7 @@ def basis_struct(q, v, shock=None, keep=None):
     if keep is not None:
         keep.extend([q, v, sh])
     return Basis(q.shape[0], q.shape[1], q.ctypes.data, v.shape[0], v.shape[1], v.shape[2],
-                 v.ctypes.data, None if sh is None else sh.ctypes.data, HOST)
+                 v.ctypes.data, None if sh is None else sh.ctypes.data, HOST, float(frac))
 
 
 def portfolio_struct(pf, keep=None):
@@ -321,13 +321,14 @@ class Context:
         self._check(self.lib.rr_get_option(self.h, opt, ctypes.byref(v)))
         return v.value
 
-    def basis_upload(self, q, v, shock=None):
+    def basis_upload(self, q, v, shock=None, frac=0.0):
         keep = []
-        st = basis_struct(q, v, shock, keep)
+        st = basis_struct(q, v, shock, keep, frac)
         self._check(self.lib.rr_basis_upload(self.h, ctypes.byref(st)))
         self.n_nodes, self.n_scen, self.n_steps = st.n_nodes, st.n_scen, st.n_steps
 
-    def basis_generate_vasicek(self, q, n_scen, n_steps, r0, a, b, sigma, dt, key, shock=None):
+    def basis_generate_vasicek(self, q, n_scen, n_steps, r0, a, b, sigma, dt, key, shock=None,
+                               frac=0.0):
         """Install a basis (q, shock) whose curves are generated on the device:
         len(r0) nodes x n_scen scenarios x n_steps steps."""
         keep = []
@@ -336,7 +337,7 @@ class Context:
         sh = None if shock is None else _np(shock, np.float64)
         keep.extend([q, sh])
         bs = Basis(q.shape[0], q.shape[1], q.ctypes.data, r0.shape[0], n_scen, n_steps, None,
-                   None if sh is None else sh.ctypes.data, HOST)
+                   None if sh is None else sh.ctypes.data, HOST, float(frac))
         vs = vasicek_struct(a, b, sigma, dt, r0, key, keep)
         self._check(self.lib.rr_basis_generate_vasicek(self.h, ctypes.byref(bs), ctypes.byref(vs)))
         self.n_nodes, self.n_scen, self.n_steps = r0.shape[0], n_scen, n_steps

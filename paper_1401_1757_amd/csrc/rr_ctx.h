@@ -108,6 +108,8 @@ struct rr_ctx {
     std::vector<double> q_host;          // [n_tables][n_ages]
     DevBuf<double> v;                    // [n_nodes][n_steps][scen_pad]
     DevBuf<double> shock;                // [n_nodes]
+    double frac = 0.0;                   // payment point of fractional annuities (0: none)
+    DevBuf<double> vf;                   // v^frac, laid out as v
     DevBuf<double> q_stage;              // [n_tables][n_ages_stage]
     DevBuf<double> vas_work;             // normals and short rates of the generator
     DevBuf<double> mean_D, mean_v;       // scenario-mean discount products and curve

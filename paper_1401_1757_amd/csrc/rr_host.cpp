@@ -138,7 +138,7 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
                                           const int32_t *anniv, const int32_t *annual,
                                           const int32_t *cf_row, const double *cf, int cf_n_rows,
                                           int cf_len, int n_steps, int n_ages, int n_tables,
-                                          int mk_models = -1, int mk_ages = -1)
+                                          int mk_models = -1, int mk_ages = -1, double frac = -1.0)
 {
     char b[256];
     if (n < 0) return "portfolio: n must be >= 0";
@@ -210,9 +210,23 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
                 return b;
             }
         }
-        if (timing && timing[i] != RR_ADVANCE && timing[i] != RR_ARREARS) {
-            snprintf(b, sizeof b, "portfolio: policy %d timing %d is not 0 or 1", i, timing[i]);
+        if (timing && timing[i] != RR_ADVANCE && timing[i] != RR_ARREARS && timing[i] != RR_FRACTIONAL) {
+            snprintf(b, sizeof b, "portfolio: policy %d timing %d is not 0, 1 or 2", i, timing[i]);
             return b;
+        }
+        if (timing && timing[i] == RR_FRACTIONAL) {   // -1: the basis is not known here
+            if (pr != RR_SL_ANN && pr != RR_JL_ANN) {
+                snprintf(b, sizeof b, "portfolio: policy %d: fractional timing needs RR_SL_ANN or RR_JL_ANN", i);
+                return b;
+            }
+            if (frac == 0.0) {
+                snprintf(b, sizeof b, "portfolio: policy %d: fractional timing needs a basis with frac > 0", i);
+                return b;
+            }
+            if ((escalation && escalation[i] > 0.0) || (annual && annual[i] == 1)) {
+                snprintf(b, sizeof b, "portfolio: policy %d: fractional timing with a payment pattern", i);
+                return b;
+            }
         }
         if (!std::isfinite(amount[i]) || amount[i] < 0.0) {
             snprintf(b, sizeof b, "portfolio: policy %d amount %g must be finite and >= 0", i, amount[i]);
@@ -477,6 +491,11 @@ static int enqueue_vasicek(rr_ctx *c, const VasParams &P, const std::vector<doub
         c->vas_r0_host = r0;
     }
     HIPCHK(c, launch_vasicek(P, c->vas_r0.p, c->vas_work.p, v, month_major, r_out, c->stream));
+    // Regenerating an installed basis in place: v^frac follows (install_basis
+    // sizes and fills it itself after the first generation).
+    if (c->has_basis && v == c->v.p && c->frac > 0.0 && c->vf.p)
+        HIPCHK(c, launch_pow_curves(c->v.p, c->vf.p, (long long)c->n_nodes * c->n_steps * c->scen_pad,
+                                    c->frac, c->stream));
     return RR_OK;
 }
 
@@ -499,6 +518,7 @@ static int install_basis(rr_ctx *c, const rr_basis *b, std::vector<double> &q,
             int amax = std::max(c->h_age1[i], two ? c->h_age2[i] : 0) + c->h_term[i];
             int tmax = std::max(c->h_table1[i], two ? c->h_table2[i] : 0);
             if (c->h_term[i] > b->n_steps || amax > b->n_ages - 1 || tmax >= b->n_tables) keep_pf = false;
+            if (c->h_timing[i] == RR_FRACTIONAL && !(b->frac > 0.0)) keep_pf = false;
         }
     }
     c->has_pf = keep_pf;
@@ -506,6 +526,7 @@ static int install_basis(rr_ctx *c, const rr_basis *b, std::vector<double> &q,
     c->plans.clear();
     c->tuned.clear();
     c->has_basis = false;
+    c->frac = b->frac;
     c->n_tables = b->n_tables;
     c->n_ages = b->n_ages;
     c->n_nodes = b->n_nodes;
@@ -530,6 +551,11 @@ static int install_basis(rr_ctx *c, const rr_basis *b, std::vector<double> &q,
         P.scen_pad = c->scen_pad;
         if ((rc = enqueue_vasicek(c, P, *gen_r0, c->v.p, 1, nullptr))) return rc;
     }
+    if (c->frac > 0.0) {   // v^frac beside v for fractional annuities
+        const long long nvv = (long long)b->n_nodes * b->n_steps * c->scen_pad;
+        HIPCHK(c, c->vf.alloc((size_t)nvv));
+        HIPCHK(c, launch_pow_curves(c->v.p, c->vf.p, nvv, c->frac, c->stream));
+    }
     HIPCHK(c, c->shock.alloc((size_t)b->n_nodes));
     HIPCHK(c, hipMemcpy(c->shock.p, c->shock_host.data(), sizeof(double) * b->n_nodes,
                         hipMemcpyHostToDevice));
@@ -549,6 +575,7 @@ extern "C" int rr_basis_upload(rr_ctx *c, const rr_basis *b)
     if (b->n_tables < 1 || b->n_ages < 2 || b->n_nodes < 1 || b->n_scen < 1 || b->n_steps < 1)
         return fail(c, RR_EINVAL, "basis: sizes must be positive (n_ages >= 2)");
     if (!b->q || !b->v) return fail(c, RR_EINVAL, "basis: q and v must not be NULL");
+    if (!(b->frac >= 0.0 && b->frac < 1.0)) return fail(c, RR_EINVAL, "basis: frac must be in [0, 1)");
     std::vector<double> q, v, sh;
     int rc;
     size_t nv = (size_t)b->n_nodes * b->n_scen * b->n_steps;
@@ -571,6 +598,7 @@ extern "C" int rr_basis_generate_vasicek(rr_ctx *c, const rr_basis *b, const rr_
         return fail(c, RR_EINVAL, "basis: sizes must be positive (n_ages >= 2)");
     if (!b->q) return fail(c, RR_EINVAL, "basis: q must not be NULL");
     if (b->v) return fail(c, RR_EINVAL, "basis: v must be NULL when the curves are generated");
+    if (!(b->frac >= 0.0 && b->frac < 1.0)) return fail(c, RR_EINVAL, "basis: frac must be in [0, 1)");
     std::vector<double> q, sh, r0;
     int rc;
     if ((rc = fetch(c, b->q, (size_t)b->n_tables * b->n_ages, b->mem_kind, q))) return rc;
@@ -661,7 +689,7 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                                            p->cf ? cf.data() : nullptr, p->cf_n_rows, p->cf_len,
                                            c->n_steps, c->n_ages, c->n_tables,
                                            c->has_markov ? c->mk_models : 0,
-                                           c->has_markov ? c->mk_ages : 0);
+                                           c->has_markov ? c->mk_ages : 0, c->frac);
     if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
 
     drop_graphs(c);
@@ -674,10 +702,11 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     std::vector<int32_t> patterned(n, 0), flow(n, FLOW_LEVEL);
     for (size_t i = 0; i < n; ++i) {
         patterned[i] = (escalation[i] > 0.0 || annual[i] == 1) ? 1 : 0;
-        flow[i] = product[i] == RR_CF_TABLE ? FLOW_TABLE
-                  : product[i] == RR_MARKOV ? FLOW_MARKOV
-                  : patterned[i]            ? FLOW_PATTERN
-                                            : FLOW_LEVEL;
+        flow[i] = product[i] == RR_CF_TABLE      ? FLOW_TABLE
+                  : product[i] == RR_MARKOV      ? FLOW_MARKOV
+                  : timing[i] == RR_FRACTIONAL   ? FLOW_FRAC
+                  : patterned[i]                 ? FLOW_PATTERN
+                                                 : FLOW_LEVEL;
     }
     auto group_of = [&](int u) { return N_FLOWS * kind_of(product[u]) + flow[u]; };
     std::vector<int> order(n);
@@ -916,6 +945,10 @@ extern "C" int rr_node_expected_reserves(rr_ctx *c, const rr_run *run, double *n
         return fail(c, RR_EINVAL, "node range outside the basis");
     if (run->scen_begin < 0 || run->scen_begin + run->scen_count > c->n_scen)
         return fail(c, RR_EINVAL, "scenario range outside the basis");
+    for (int i = 0; i < c->n_user; ++i)
+        if (c->h_timing[i] == RR_FRACTIONAL)
+            return fail(c, RR_EINVAL, "fractional timing: the scenario mean is not the mean-curve reserve "
+                                      "(policy %d)", i);
     if (run->node_count == 0 || (!node_r0 && !node_totals)) return RR_OK;
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, c->mean_D.alloc((size_t)run->node_count * c->n_steps * run->scen_count));
@@ -1105,6 +1138,8 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.cf_cols = c->cf_cols;
     P.mk_w = c->has_markov ? c->mk_w.p : nullptr;
     P.mk_ages = c->mk_ages;
+    P.vf = c->frac > 0.0 ? c->vf.p : nullptr;
+    P.frac = c->frac;
     P.n_pad = c->n_pad;
     P.n_user = c->n_user;
     P.tiles = c->tiles.p;

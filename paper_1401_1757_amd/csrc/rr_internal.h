@@ -45,9 +45,10 @@ enum Flow : int {
     FLOW_LEVEL = 0,     // level amounts (coef rows)
     FLOW_PATTERN = 1,   // annuities in payment with escalation or annual payment
     FLOW_TABLE = 2,     // single life, cash flow of step t from a per-policy table
-    FLOW_MARKOV = 3     // one life on an uploaded Markov model (up to 4 states)
+    FLOW_MARKOV = 3,    // one life on an uploaded Markov model (up to 4 states)
+    FLOW_FRAC = 4       // single- or joint-life annuity paid at a fraction of the month
 };
-constexpr int N_FLOWS = 4;
+constexpr int N_FLOWS = 5;
 
 struct Tile {
     int kind;
@@ -96,6 +97,8 @@ struct RecParams {
     int cf_cols;
     const double *mk_w;       // [model][mk_ages][4][4] uploaded Markov matrices (zero padded)
     int mk_ages;
+    const double *vf;         // v^frac, laid out as v (fractional tiles), or null
+    double frac;
     int n_pad;
     int n_user;
     const Tile *tiles;
@@ -132,6 +135,9 @@ hipError_t launch_fill(double *dst, long long n, double value, hipStream_t strea
 hipError_t launch_fill_int(int *dst, int n, int value, hipStream_t stream);
 hipError_t launch_transpose_curves(const double *src, double *dst, int n_nodes, int n_scen,
                                    int n_steps, int scen_pad, hipStream_t stream);
+// dst[i] = src[i]^f for i < n.
+hipError_t launch_pow_curves(const double *src, double *dst, long long n, double f,
+                             hipStream_t stream);
 // Vasicek scenario generation (rr_scen.hip).  Constants of the exact step
 // (e = exp(-a dt), om = (1 - e)/a, the standard deviations and the
 // correlation part) are computed on the host.

@@ -466,4 +466,20 @@ hipError_t launch_mean_curve(const double *v, int n_steps, int scen_pad, int nod
     return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256) k_pow_curves(const double *__restrict__ src,
+                                                    double *__restrict__ dst, long long n, double f)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = pow(src[i], f);
+}
+
+hipError_t launch_pow_curves(const double *src, double *dst, long long n, double f,
+                             hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pow_curves, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, src,
+                       dst, n, f);
+    return hipGetLastError();
+}
+
 }  // namespace rr

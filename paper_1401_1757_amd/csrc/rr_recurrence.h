@@ -597,6 +597,66 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
     store_results<K>(P, node_rel, tile, sb, lane, uid, live, r0, r1, r2, LAST, true);
 }
 
+// Single- and joint-life annuities paid at the fraction f of each month
+// (Sec. 3.1's f; survival to t + f by f x the month's death probability):
+//   r <- -P + v^f * pf * pay + v * p * r',  pf = prod over lives of (1 - f + f p_l).
+// A lane idles (r stays 0) until its first step; one policy per lane.
+template <int K, bool LDSQ, bool TWO, bool SHOCK>
+__device__ __forceinline__ void run_frac(const RecParams &P, const double *__restrict__ lq,
+                                         const double *__restrict__ vcurves, int node_rel, int tile,
+                                         const Tile &T, int sb, int lane)
+{
+    const int node = P.node_begin + node_rel;
+    const int shift = node * P.node_step;
+    const int slot = T.first + lane;
+    const int S = P.term[slot] - shift;
+    const int uid = P.uidx[slot];
+    const bool live = (uid >= 0) && (S > 0);
+    const int smax = T.smax - shift;
+    const double m = P.shock[node];
+    const double a0 = P.coef[slot];
+    const double pay = P.coef[P.n_pad + slot];
+    const double f = P.frac, g = 1.0 - P.frac;
+    const int qa = P.qoff1[slot] + P.age1[slot] + shift;
+    const int qb = TWO ? P.qoff2[slot] + P.age2[slot] + shift : 0;
+    const size_t off = (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
+    const double *vb = vcurves + off;
+    const double *vfb = P.vf + off;
+    double r[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = 0.0;
+    double *path = nullptr;
+    if constexpr (K == 1) {
+        if (P.path != nullptr && uid >= 0) {
+            if (live) {
+                path = P.path + P.path_off[uid];
+                path[S] = 0.0;
+            } else {
+                P.path[P.path_off[uid]] = 0.0;   // expired: its one entry is 0
+            }
+        }
+    }
+    for (int t = smax - 1; t >= 0; --t) {
+        const double x1 = p_eff<LDSQ, SHOCK>(lq, P.q, qa + t, m);
+        const double x2 = TWO ? p_eff<LDSQ, SHOCK>(lq, P.q, qb + t, m) : 1.0;
+        const double p = TWO ? x1 * x2 : x1;
+        const double pf = TWO ? fma(f, x1, g) * fma(f, x2, g) : fma(f, x1, g);
+        const double c = pf * pay;
+        const bool on = t < S;
+        const double *vt = vb + (ptrdiff_t)t * P.scen_pad;
+        const double *vft = vfb + (ptrdiff_t)t * P.scen_pad;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double nr = fma(vt[k], p * r[k], fma(vft[k], c, a0));
+            r[k] = on ? nr : r[k];
+        }
+        if constexpr (K == 1) {
+            if (path != nullptr && on) path[t] = r[0];
+        }
+    }
+    store_results<K>(P, node_rel, tile, sb, lane, uid, live, r, r, r, false, false);
+}
+
 // One life on an uploaded Markov model (Sec. 4.7; the matrix need not be
 // upper triangular): up to four states, zero padded to four.  With y = c +
 // r' per state (c: the benefits paid at the end of a month ending in the
@@ -732,7 +792,16 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
         }
         if (PAT && T.flow != FLOW_LEVEL) {
             if constexpr (PAT) {
-                if (T.flow == FLOW_MARKOV)
+                if (T.flow == FLOW_FRAC) {
+                    const bool shock = P.shock[P.node_begin + node_rel] != 1.0;
+                    if (T.kind == KIND_JOINT) {
+                        if (shock) run_frac<K, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                        else run_frac<K, LDSQ, true, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                    } else {
+                        if (shock) run_frac<K, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                        else run_frac<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                    }
+                } else if (T.flow == FLOW_MARKOV)
                     run_markov<K>(P, vcurves, node_rel, tile, T, sb, lane);
                 else if (T.flow == FLOW_TABLE)
                     run_scalar<K, 1, LDSQ, false, FLOW_TABLE>(P, s_q, vcurves, node_rel, tile, 1, T,

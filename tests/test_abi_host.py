@@ -59,7 +59,7 @@ def test_portfolio_checks(rr):
         "product": ("product", 11, 13, "policy 11 has unknown product 13"),
         "age": ("age1_m", 5, n_ages, "policy 5 age"),
         "table": ("table1", 2, 3, "policy 2 table1 3"),
-        "timing": ("timing", 9, 2, "policy 9 timing 2"),
+        "timing": ("timing", 9, 3, "policy 9 timing 3"),
         "amount": ("amount", 4, -1.0, "policy 4 amount"),
         "nan": ("premium", 6, float("nan"), "policy 6 premium"),
     }
@@ -197,3 +197,18 @@ def test_markov_policy_checks(rr):
     assert f"policy {i} model -1" in rr.check_portfolio(bad, 60, n_ages, 2)
     bad = pf.subset(np.arange(pf.n)); bad.age1_m[i] = -3
     assert f"policy {i} age -3" in rr.check_portfolio(bad, 60, n_ages, 2)
+
+
+def test_fractional_timing_checks(rr):
+    w = synth.config_c2(n=2000)
+    n_ages = w.basis.q.shape[1]
+    pf = w.portfolio.subset(np.arange(40))
+    sl = np.flatnonzero(pf.product == synth.SL_ANN)
+    term = np.flatnonzero(pf.product == synth.TERM)
+    pf.timing[sl] = synth.FRACTIONAL
+    assert rr.check_portfolio(pf, 600, n_ages, 3) == ""     # the basis's fraction is checked on upload
+    bad = pf.subset(np.arange(pf.n)); bad.timing[term[0]] = synth.FRACTIONAL
+    assert f"policy {term[0]}: fractional timing needs RR_SL_ANN" in rr.check_portfolio(bad, 600, n_ages, 3)
+    bad = pf.subset(np.arange(pf.n))
+    bad.escalation = np.zeros(bad.n); bad.escalation[sl[0]] = 0.03
+    assert f"policy {sl[0]}: fractional timing with a payment pattern" in rr.check_portfolio(bad, 600, n_ages, 3)

@@ -370,3 +370,83 @@ def test_markov_invalid_uploads(ctx, rr):
     out = ctx.alloc_outputs(1, 2)
     with pytest.raises(rr.RRError):
         ctx.reserve_recurrence(0, 1, 0, 2, 12, out)
+
+
+# ---------------------------------------------------------------------------
+# Fractional payment timing (annuities paid at the basis's fraction f)
+# ---------------------------------------------------------------------------
+def frac_workload(seed, n, n_steps, n_scen, n_nodes, f=0.35, node_step=7):
+    rng = np.random.default_rng(seed)
+    w = synth.random_small(rng, n=n, n_steps=n_steps, n_scen=n_scen, n_nodes=n_nodes, shock=True,
+                           products=tuple(range(7)) + TWO_LIFE_INS)
+    pf = w.portfolio
+    ann = np.isin(pf.product, (synth.SL_ANN, synth.JL_ANN))
+    pf.timing = np.where(ann & (rng.uniform(size=pf.n) < 0.6), synth.FRACTIONAL, pf.timing).astype(np.int32)
+    w.basis.frac = f
+    return synth.Workload("fractional", w.basis, pf, node_step_m=node_step)
+
+
+@pytest.mark.parametrize("K,J", [(1, 1), (4, 1), (16, 1), (32, 1), (8, 2), (16, 4)])
+def test_fractional_timing_with_other_products(ctx, K, J):
+    w = frac_workload(1600 + K + 7 * J, n=400, n_steps=100, n_scen=2 * K + 3, n_nodes=3)
+    assert (w.portfolio.timing == synth.FRACTIONAL).sum() > 20
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock, frac=w.basis.frac)
+    ctx.portfolio_upload(w.portfolio)
+    ctx.set_option(1, K)
+    ctx.set_option(8, J)
+    _say(f"fractional K={K} J={J}")
+    compare(ctx, w)
+
+
+def test_fractional_paths_and_regenerated_curves(ctx):
+    w = frac_workload(1700, n=150, n_steps=120, n_scen=2, n_nodes=2, f=0.6, node_step=12)
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock, frac=0.6)
+    ctx.portfolio_upload(pf)
+    _say("fractional paths")
+    for node, scen in ((0, 0), (1, 1)):
+        po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=node, node_step=12)
+        po["path"].fill_(float("nan"))
+        ctx.reserve_recurrence(node, 1, scen, 1, 12, po)
+        torch.cuda.synchronize()
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=scen, node_step=12)
+        ref = oracle.reserves(b, pf, node, 1, scen, 1, 12)
+        gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+        assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
+    # device-generated curves: v^f follows every regeneration
+    A, Bm, Sg, DT = synth.VAS_A, synth.VAS_B, synth.VAS_SIGMA, 1.0 / 12.0
+    ctx.basis_generate_vasicek(b.q, 20, b.n_steps, [0.03, 0.05], A, Bm, Sg, DT, (4, 4),
+                               shock=b.shock, frac=0.6)
+    ctx.portfolio_upload(pf)
+    for key, r0 in (((4, 4), [0.03, 0.05]), ((5, 6), [0.02, 0.04])):
+        ctx.curves_generate_vasicek(r0, A, Bm, Sg, DT, key)
+        ov, _ = oracle.vasicek_curves(A, Bm, Sg, DT, r0, 20, b.n_steps, key)
+        gb = synth.Basis(q=b.q, v=ov, shock=b.shock, frac=0.6)
+        out = ctx.alloc_outputs(2, 20, all_states=False)
+        ctx.reserve_recurrence(0, 2, 0, 20, 12, out)
+        torch.cuda.synchronize()
+        ref = oracle.reserves(gb, pf, 0, 2, 0, 20, 12)
+        assert_reserves_close(to_np(out["r0"]), ref["r_all"][..., 0], ref["gross"])
+
+
+def test_fractional_invalid(ctx, rr):
+    w = frac_workload(1800, n=60, n_steps=60, n_scen=2, n_nodes=1)
+    b, pf = w.basis, w.portfolio
+    with pytest.raises(rr.RRError, match="frac must be"):
+        ctx.basis_upload(b.q, b.v, b.shock, frac=1.0)
+    ctx.basis_upload(b.q, b.v, b.shock)                 # no fraction
+    with pytest.raises(rr.RRError, match="needs a basis with frac"):
+        ctx.portfolio_upload(pf)
+    ctx.basis_upload(b.q, b.v, b.shock, frac=0.35)
+    bad = pf.subset(np.arange(pf.n))
+    i = int(np.flatnonzero(bad.product == synth.TERM)[0])
+    bad.timing[i] = synth.FRACTIONAL
+    with pytest.raises(rr.RRError, match=f"policy {i}: fractional timing needs"):
+        ctx.portfolio_upload(bad)
+    ctx.portfolio_upload(pf)
+    with pytest.raises(rr.RRError, match="fractional timing"):
+        ctx.node_expected_reserves(0, 1, 0, 2, 12)
+    ctx.basis_upload(b.q, b.v, b.shock)                 # a basis without the fraction drops it
+    out = ctx.alloc_outputs(1, 2)
+    with pytest.raises(rr.RRError):
+        ctx.reserve_recurrence(0, 1, 0, 2, 12, out)
