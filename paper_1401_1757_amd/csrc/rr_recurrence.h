@@ -662,44 +662,20 @@ __device__ __forceinline__ void run_frac(const RecParams &P, const double *__res
 // r' per state (c: the benefits paid at the end of a month ending in the
 // state) and W_t the model's matrix at the attained age:
 //   r_i <- a_i + v * sum_j W_t[i][j] * y_j,  a_0 = - premium, a_i = 0 else.
-// The lane's matrix of the next step is loaded while the current one is used.
-template <int K>
-__device__ __forceinline__ void run_markov(const RecParams &P, const double *__restrict__ vcurves,
-                                           int node_rel, int tile, const Tile &T, int sb, int lane)
+// The lane's matrix of the next step is loaded while the current one is
+// used.  The scenarios go through in chunks of KM <= 4 chains (the matrix is
+// read again per chunk, from L2), so this path needs few registers and the
+// kernel's register budget stays that of the level paths.
+template <int KM>
+__device__ __forceinline__ void markov_chunk(const RecParams &P, const double2 *__restrict__ wb,
+                                             const double *__restrict__ vb, int S, int smax,
+                                             double a0, const double (&c)[4], double *path,
+                                             double (&r)[4][KM])
 {
-    const int node = P.node_begin + node_rel;
-    const int shift = node * P.node_step;
-    const int slot = T.first + lane;
-    const int S = P.term[slot] - shift;
-    const int uid = P.uidx[slot];
-    const bool live = (uid >= 0) && (S > 0);
-    const int smax = T.smax - shift;
-    const double a0 = P.coef[slot];
-    double c[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) c[j] = P.coef[(1 + j) * P.n_pad + slot];
-    // rows of the model at the policy's attained age at t = 0 (padding lanes: model 0, age 0)
-    const int age0 = uid >= 0 ? P.age1[slot] + shift : 0;
-    const double2 *wb = reinterpret_cast<const double2 *>(
-        P.mk_w + ((size_t)P.pat_code[slot] * P.mk_ages + age0) * 16);
-    const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
-
-    double r[4][K];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int k = 0; k < K; ++k) r[i][k] = 0.0;
-    double *path = nullptr;
-    if constexpr (K == 1) {
-        if (P.path != nullptr && uid >= 0) {
-            if (live) {
-                path = P.path + P.path_off[uid];
-                path[S] = 0.0;
-            } else {
-                P.path[P.path_off[uid]] = 0.0;   // expired: its one entry is 0
-            }
-        }
-    }
+        for (int k = 0; k < KM; ++k) r[i][k] = 0.0;
     // The lane starts at its own last step (t < S); padding and expired
     // lanes take no step (S <= 0).
     int t = min(S, smax) - 1;
@@ -721,7 +697,7 @@ __device__ __forceinline__ void run_markov(const RecParams &P, const double *__r
         }
         const double *vt = vb + (ptrdiff_t)t * P.scen_pad;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < KM; ++k) {
             const double v = vt[k];
             double y[4];
 #pragma unroll
@@ -735,11 +711,48 @@ __device__ __forceinline__ void run_markov(const RecParams &P, const double *__r
                 r[i][k] = fma(v, acc, i == 0 ? a0 : 0.0);
             }
         }
-        if constexpr (K == 1) {
-            if (path != nullptr) path[t] = r[0][0];
+        if (path != nullptr) path[t] = r[0][0];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void run_markov(const RecParams &P, const double *__restrict__ vcurves,
+                                           int node_rel, int tile, const Tile &T, int sb, int lane)
+{
+    constexpr int KM = K < 4 ? K : 4;
+    const int node = P.node_begin + node_rel;
+    const int shift = node * P.node_step;
+    const int slot = T.first + lane;
+    const int S = P.term[slot] - shift;
+    const int uid = P.uidx[slot];
+    const bool live = (uid >= 0) && (S > 0);
+    const int smax = T.smax - shift;
+    const double a0 = P.coef[slot];
+    double c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = P.coef[(1 + j) * P.n_pad + slot];
+    // rows of the model at the policy's attained age at t = 0 (padding lanes: model 0, age 0)
+    const int age0 = uid >= 0 ? P.age1[slot] + shift : 0;
+    const double2 *wb = reinterpret_cast<const double2 *>(
+        P.mk_w + ((size_t)P.pat_code[slot] * P.mk_ages + age0) * 16);
+    const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
+    double *path = nullptr;
+    if constexpr (K == 1) {
+        if (P.path != nullptr && uid >= 0) {
+            if (live) {
+                path = P.path + P.path_off[uid];
+                path[S] = 0.0;
+            } else {
+                P.path[P.path_off[uid]] = 0.0;   // expired: its one entry is 0
+            }
         }
     }
-    store_results<K>(P, node_rel, tile, sb, lane, uid, live, r[0], r[1], r[2], true, true, r[3]);
+    for (int kc = 0; kc < K; kc += KM) {
+        double r[4][KM];
+        markov_chunk<KM>(P, wb, vb + kc, S, smax, a0, c, path, r);
+        store_results<KM>(P, node_rel, tile, sb + kc, lane, uid, live, r[0], r[1], r[2], true, true,
+                          r[3]);
+    }
 }
 
 // Persistent grid: each wavefront takes items from its XCD's queue (the
