@@ -71,7 +71,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1401_1757_amd", "csrc", f)
                   for f in ("rr_recurrence.h", "rr_internal.h")]
 
 
-def measured_traffic(k, j, wg):
+def measured_traffic(k, j, wg, ring=0):
     """HBM bytes per recurrence launch from the committed FETCH_SIZE / WRITE_SIZE
     counters, if they were taken on this kernel source and launch shape."""
     import hashlib
@@ -85,7 +85,10 @@ def measured_traffic(k, j, wg):
         sha = h.hexdigest()
     except OSError:
         return None
-    if t.get("source_sha256") != sha or t.get("launch") != {"block_k": k, "block_j": j, "wg_per_cu": wg}:
+    launch = dict(t.get("launch", {}))
+    launch.setdefault("curve_ring", 0)
+    if t.get("source_sha256") != sha or launch != {"block_k": k, "block_j": j, "wg_per_cu": wg,
+                                                   "curve_ring": ring}:
         return None
     return float(t["traffic_bytes_per_launch"])
 
@@ -310,7 +313,8 @@ def representative_leg(rr, synth, sync, steps=5):
                 "escalating": int((pf.escalation > 0).sum()), "annual": int(pf.annual.sum()),
                 "launch": {"block_k": ctx.get_option(rr.OPT_LAST_K),
                            "block_j": ctx.get_option(rr.OPT_LAST_J),
-                           "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG)},
+                           "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG),
+                           "curve_ring": ctx.get_option(rr.OPT_LAST_RING)},
                 "first_call_s": first,
                 "paper_context": "the paper estimates 5.7 s wall per scenario for this portfolio "
                                  "on a 2-core laptop CPU (Sec. 5.3); here ms_per_step covers "
@@ -342,6 +346,12 @@ def main():
     ap.add_argument("--block-k", type=int, default=0, help="pin scenarios per lane (0 = autotune)")
     ap.add_argument("--wg", type=int, default=0, help="pin workgroups per CU (0 = autotune)")
     ap.add_argument("--block-j", type=int, default=0, help="pin policies per lane (0 = autotune)")
+    ap.add_argument("--lane-spread", type=int, default=1,
+                    help="1: deal tile lanes over the LDS banks (default), 0: sorted lane order")
+    ap.add_argument("--curve-share", type=int, default=1,
+                    help="1: queue windows whose wavefronts share scenario blocks (default), 0: off")
+    ap.add_argument("--ring", type=int, default=0,
+                    help="curve ring for level portfolios: -1 autotune, 0 off (default), 1 on")
     ap.add_argument("--term-bucket", type=int, default=0, help="months per term bucket (0 = default)")
     ap.add_argument("--surrogate-epochs", type=int, default=0,
                     help="epochs of the surrogate training (0 = the default fit)")
@@ -382,6 +392,8 @@ def main():
     ctx = rr.Context(0)
     if args.term_bucket:
         ctx.set_option(rr.OPT_TERM_BUCKET, args.term_bucket)
+    ctx.set_option(rr.OPT_LANE_SPREAD, args.lane_spread)
+    ctx.set_option(rr.OPT_CURVE_SHARE, args.curve_share)
     t0 = time.perf_counter()
     ctx.basis_upload(b.q, b.v, b.shock)
     ctx.portfolio_upload(pf)
@@ -391,6 +403,7 @@ def main():
     ctx.set_option(rr.OPT_BLOCK_K, args.block_k)
     ctx.set_option(rr.OPT_WG_PER_CU, args.wg)
     ctx.set_option(rr.OPT_BLOCK_J, args.block_j)
+    ctx.set_option(rr.OPT_CURVE_RING, args.ring)
 
     def step():
         ctx.reserve_recurrence(0, 1, 0, b.n_scen, 12, out)
@@ -419,7 +432,8 @@ def main():
         print(json.dumps({"ms_per_step": ms_per_step, "value": value,
                           "block_k": ctx.get_option(rr.OPT_LAST_K),
                           "block_j": ctx.get_option(rr.OPT_LAST_J),
-                          "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG)}))
+                          "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG),
+                          "curve_ring": ctx.get_option(rr.OPT_LAST_RING)}))
         ctx.close()
         return
 
@@ -435,7 +449,8 @@ def main():
     k_opt = ctx.get_option(rr.OPT_LAST_K)
     wg_opt = ctx.get_option(rr.OPT_LAST_WG)
     j_opt = ctx.get_option(rr.OPT_LAST_J)
-    traffic = measured_traffic(k_opt, j_opt, wg_opt)
+    ring_opt = ctx.get_option(rr.OPT_LAST_RING)
+    traffic = measured_traffic(k_opt, j_opt, wg_opt, ring_opt)
 
     result = {
         "metric": "policy x scenario reserve valuations/s (exact FP64 backward recurrence)",
@@ -467,6 +482,7 @@ def main():
         "first_call_s": first_call_s,
         "upload_s": upload_s,
         "launch": {"block_k": k_opt, "block_j": j_opt, "wg_per_cu": wg_opt,
+                   "curve_ring": ctx.get_option(rr.OPT_LAST_RING),
                    "autotuned": args.block_k == 0},
     }
 

@@ -326,6 +326,17 @@ int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out)
 #define RR_OPT_LAST_J       9   /* read-only: policies per lane of the last launch */
 #define RR_OPT_TERM_BUCKET 10   /* months per remaining-term bucket when tiling (default 16);
                                    applies from the next rr_portfolio_upload */
+#define RR_OPT_CURVE_RING  11   /* level single-/joint-life portfolios: stage each wavefront's
+                                   scenario curves in an LDS ring (-1 = autotune, 0 = off
+                                   (default), 1 = on for the shapes that have it: K = 16 with
+                                   J = 1, 2 and K = 8 with J = 2) */
+#define RR_OPT_LAST_RING   12   /* read-only: 1 if the last launch used the curve ring */
+#define RR_OPT_LANE_SPREAD 13   /* 1 = order the lanes of each tile so that their mortality-table
+                                   reads spread over the LDS banks (default), 0 = sorted order;
+                                   applies from the next rr_portfolio_upload */
+#define RR_OPT_CURVE_SHARE 14   /* 1 = order each work queue so that the wavefronts of a workgroup
+                                   take items of one scenario block together (default), 0 = plain
+                                   longest-first order */
 int rr_set_option(rr_ctx *ctx, int32_t option, int64_t value);
 int rr_get_option(rr_ctx *ctx, int32_t option, int64_t *value);
 

@@ -23,7 +23,8 @@ DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++
                 "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
 HOST_FLAGS = ["-x", "c++", "-O2", "-fPIC", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-Wall"]
 
-DEVICE_SOURCES = ["rr_kernels.hip", "rr_kernels_pat.hip", "rr_mlp.hip", "rr_scen.hip"]
+DEVICE_SOURCES = ["rr_kernels.hip", "rr_kernels_pat.hip", "rr_kernels_ring.hip", "rr_mlp.hip",
+                  "rr_scen.hip"]
 HOST_SOURCES = ["rr_host.cpp", "rr_surrogate.cpp"]
 
 

@@ -45,6 +45,7 @@ struct Plan {
     int K = 1;
     int J = 1;
     int wg_per_cu = 2;
+    int ring = 0;       // launch with the curve-ring instances
     int grid = 1;
     int n_items = 0;
     int n_queues = 1;
@@ -53,17 +54,18 @@ struct Plan {
 };
 
 struct PlanKey {
-    int node_begin, node_count, scen_begin, scen_count, node_step, K, J, queues, gen;
+    int node_begin, node_count, scen_begin, scen_count, node_step, K, J, queues, gen, wg;
     bool operator<(const PlanKey &o) const
     {
-        return std::tie(node_begin, node_count, scen_begin, scen_count, node_step, K, J, queues, gen) <
-               std::tie(o.node_begin, o.node_count, o.scen_begin, o.scen_count, o.node_step, o.K,
-                        o.J, o.queues, o.gen);
+        return std::tie(node_begin, node_count, scen_begin, scen_count, node_step, K, J, queues, gen,
+                        wg) < std::tie(o.node_begin, o.node_count, o.scen_begin, o.scen_count,
+                                       o.node_step, o.K, o.J, o.queues, o.gen, o.wg);
     }
 };
 
 struct LaunchCfg {
     int K = 1, J = 1, wg = 2;
+    int ring = 0;       // curve-ring instances (level scalar-reserve portfolios)
 };
 
 struct TuneKey {
@@ -101,6 +103,7 @@ struct rr_ctx {
     std::string err;
     int n_cu = 256;
     size_t lds_per_block = 65536;
+    size_t lds_per_cu = 65536;           // LDS of one CU (resident workgroups x their LDS)
 
     // basis
     bool has_basis = false;
@@ -158,7 +161,10 @@ struct rr_ctx {
     // options
     int opt_k = 0, opt_j = 0, opt_wg = 0, opt_graph = 1, opt_timing = 0, opt_xcd = 1;
     int opt_term_bucket = 16;             // months per remaining-term bucket in the sort
-    int last_k = 0, last_j = 0, last_wg = 0;   // configuration of the last recurrence launch
+    int opt_ring = 0;                     // -1: autotune, 0: off (default), 1: on where supported
+    int opt_lane_spread = 1;              // deal tile lanes over LDS banks (next upload)
+    int opt_curve_share = 1;              // queue windows whose wavefronts share curve blocks
+    int last_k = 0, last_j = 0, last_wg = 0, last_ring = 0;   // configuration of the last recurrence launch
 
     // timing
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;

@@ -306,6 +306,8 @@ extern "C" int rr_create(rr_ctx **out, int device, uint64_t stream)
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RR_EDEVICE;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->lds_per_block = prop.sharedMemPerBlock;
+    c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor > 0 ? prop.maxSharedMemoryPerMultiProcessor
+                                                              : prop.sharedMemPerBlock;
     c->stream = (hipStream_t)(uintptr_t)stream;   // 0 = the null stream
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) return RR_EDEVICE;
     if (c->counters.alloc(MAX_QUEUES + 1) != hipSuccess) return RR_ENOMEM;
@@ -381,6 +383,19 @@ extern "C" int rr_set_option(rr_ctx *c, int32_t option, int64_t value)
             return fail(c, RR_EINVAL, "J must be 0 (auto) or 1, 2, 4");
         c->opt_j = (int)value;
         return RR_OK;
+    case RR_OPT_CURVE_RING:
+        if (value < -1 || value > 1) return fail(c, RR_EINVAL, "curve ring must be -1 (auto), 0 or 1");
+        c->opt_ring = (int)value;
+        return RR_OK;
+    case RR_OPT_LANE_SPREAD: c->opt_lane_spread = value ? 1 : 0; return RR_OK;   // next upload
+    case RR_OPT_CURVE_SHARE:
+        if (c->opt_curve_share != (value ? 1 : 0)) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));   // launches in flight read the old queues
+            drop_graphs(c);
+            c->plans.clear();   // queues are rebuilt on the next call
+        }
+        c->opt_curve_share = value ? 1 : 0;
+        return RR_OK;
     case RR_OPT_USE_GRAPH: c->opt_graph = value ? 1 : 0; return RR_OK;
     case RR_OPT_KERNEL_TIMING: c->opt_timing = value ? 1 : 0; return RR_OK;
     case RR_OPT_XCD_QUEUES:
@@ -404,6 +419,10 @@ extern "C" int rr_get_option(rr_ctx *c, int32_t option, int64_t *value)
     case RR_OPT_LAST_K: *value = c->last_k; return RR_OK;
     case RR_OPT_LAST_J: *value = c->last_j; return RR_OK;
     case RR_OPT_LAST_WG: *value = c->last_wg; return RR_OK;
+    case RR_OPT_CURVE_RING: *value = c->opt_ring; return RR_OK;
+    case RR_OPT_LAST_RING: *value = c->last_ring; return RR_OK;
+    case RR_OPT_LANE_SPREAD: *value = c->opt_lane_spread; return RR_OK;
+    case RR_OPT_CURVE_SHARE: *value = c->opt_curve_share; return RR_OK;
     default: return fail(c, RR_EINVAL, "unknown option %d", option);
     }
 }
@@ -793,6 +812,60 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
         s_qoff1[j] *= c->n_ages_stage;
         s_qoff2[j] *= c->n_ages_stage;
     }
+    // Lane order within each tile.  All lanes of a tile take the same step t
+    // together, so lane l reads the staged table at (qoff + age)_l + shift + t
+    // in one LDS instruction per life: the bank of that read is fixed by
+    // (qoff + age)_l modulo the bank count for the whole recurrence.  Ages
+    // sorted a few months apart put many lanes on few banks; instead the
+    // lanes are dealt so that every group of 16 lanes holds distinct residues
+    // modulo 16 and every half-wavefront distinct residues modulo 32 as far
+    // as the tile's residues allow (each life counted, two-life tiles too).
+    if (c->opt_lane_spread) {
+        std::vector<int> perm(TILE);
+        for (const Tile &T : tiles) {
+            const bool two = T.kind != KIND_SINGLE;
+            int c16[4][16] = {}, c32[2][32] = {}, used[4] = {};
+            int d16[4][16] = {}, d32[2][32] = {};
+            // residues of life 1 and (two lives) life 2 per slot
+            std::vector<int> order(TILE);
+            std::iota(order.begin(), order.end(), 0);
+            int freq[16] = {};
+            for (int l = 0; l < TILE; ++l) ++freq[(s_qoff1[T.first + l] + s_age1[T.first + l]) & 15];
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                const int fa = freq[(s_qoff1[T.first + a] + s_age1[T.first + a]) & 15];
+                const int fb = freq[(s_qoff1[T.first + b] + s_age1[T.first + b]) & 15];
+                return fa > fb;   // most crowded residues first
+            });
+            for (int l : order) {
+                const int j = T.first + l;
+                const int a = (s_qoff1[j] + s_age1[j]) & 31;
+                const int b = two ? (s_qoff2[j] + s_age2[j]) & 31 : 0;
+                int best = -1;
+                long cost_best = 0;
+                for (int g = 0; g < 4; ++g) {
+                    if (used[g] == 16) continue;
+                    long cost = 4L * c16[g][a & 15] + c32[g / 2][a];
+                    if (two) cost += 4L * d16[g][b & 15] + d32[g / 2][b];
+                    if (best < 0 || cost < cost_best) { best = g; cost_best = cost; }
+                }
+                ++c16[best][a & 15];
+                ++c32[best / 2][a];
+                if (two) { ++d16[best][b & 15]; ++d32[best / 2][b]; }
+                perm[best * 16 + used[best]++] = j;
+            }
+            auto apply = [&](std::vector<int> &v) {
+                int tmp[TILE];
+                for (int l = 0; l < TILE; ++l) tmp[l] = v[perm[l]];
+                for (int l = 0; l < TILE; ++l) v[T.first + l] = tmp[l];
+            };
+            apply(s_uidx);
+            apply(s_age1);
+            apply(s_age2);
+            apply(s_term);
+            apply(s_qoff1);
+            apply(s_qoff2);
+        }
+    }
     // Coefficients.
     std::vector<double> coef((size_t)N_COEF * std::max(n_pad, 1), 0.0);
     auto C = [&](int row, int slot) -> double & { return coef[(size_t)row * n_pad + slot]; };
@@ -1046,7 +1119,7 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
     const int queues = c->opt_xcd ? MAX_QUEUES : 1;
     const int K = cfg.K, J = cfg.J;
     PlanKey key{run->node_begin, run->node_count, run->scen_begin, run->scen_count,
-                run->node_step_m, K, J, queues, c->gen};
+                run->node_step_m, K, J, queues, c->gen, cfg.wg};
     auto it = c->plans.find(key);
     Plan *pl;
     if (it == c->plans.end()) {
@@ -1068,16 +1141,18 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
             groups.push_back({t, count});
             t += count;
         }
+        auto item_cost = [&](int first, int count, int shift) -> long long {
+            const Tile &T = c->tiles_host[first];
+            int smax = T.smax;
+            for (int j = 1; j < count; ++j) smax = std::max(smax, c->tiles_host[first + j].smax);
+            const long long steps = std::max(smax - shift, 0);
+            return steps * count * (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind) + (T.flow ? 16 : 0)) +
+                   64;
+        };
         for (int nr = 0; nr < run->node_count; ++nr) {
             const int shift = (run->node_begin + nr) * run->node_step_m;
             for (const auto &g : groups) {
-                const Tile &T = c->tiles_host[g.first];
-                int smax = T.smax;
-                for (int j = 1; j < g.second; ++j) smax = std::max(smax, c->tiles_host[g.first + j].smax);
-                const long long steps = std::max(smax - shift, 0);
-                const long long cost =
-                    steps * g.second *
-                        (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind) + (T.flow ? 16 : 0)) + 64;
+                const long long cost = item_cost(g.first, g.second, shift);
                 for (int b = 0; b < nsb; ++b) {
                     const int qid = queues > 1 ? (int)(((long long)nr * nsb + b) % queues) : 0;
                     qs[qid].push_back({cost, Item{nr, g.first, b * K, g.second}});
@@ -1086,10 +1161,38 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
         }
         std::vector<Item> items;
         std::vector<int> qbeg(queues + 1, 0);
+        const int share = c->opt_curve_share ? WG_THREADS / 64 : 1;
         for (int qi = 0; qi < queues; ++qi) {
-            std::stable_sort(qs[qi].begin(), qs[qi].end(),
-                             [](const W &a, const W &b) { return a.cost > b.cost; });
+            // Longest first.  An item's curves are read with scalar loads
+            // through the scalar cache that neighbouring CUs share, so the
+            // queue is then dealt in windows of `share` tile groups of about
+            // the same length (one per wavefront of a workgroup, taken at
+            // about the same time): within a window the items are ordered by
+            // scenario block, so wavefronts that start together walk the same
+            // curve lines and one cache miss serves them all.
+            std::stable_sort(qs[qi].begin(), qs[qi].end(), [](const W &a, const W &b) {
+                if (a.cost != b.cost) return a.cost > b.cost;
+                return a.item.tile < b.item.tile;
+            });
             qbeg[qi] = (int)items.size();
+            size_t u0 = 0;
+            while (u0 < qs[qi].size()) {
+                // a window: the items of `share` consecutive (node, tile group) units
+                size_t u1 = u0;
+                int units = 0;
+                while (u1 < qs[qi].size() && units < share) {
+                    const Item &h = qs[qi][u1].item;
+                    while (u1 < qs[qi].size() && qs[qi][u1].item.tile == h.tile &&
+                           qs[qi][u1].item.node_rel == h.node_rel)
+                        ++u1;
+                    ++units;
+                }
+                std::stable_sort(qs[qi].begin() + u0, qs[qi].begin() + u1, [](const W &a, const W &b) {
+                    if (a.item.node_rel != b.item.node_rel) return a.item.node_rel < b.item.node_rel;
+                    return a.item.sblock < b.item.sblock;
+                });
+                u0 = u1;
+            }
             for (auto &w : qs[qi]) items.push_back(w.item);
         }
         qbeg[queues] = (int)items.size();
@@ -1107,6 +1210,7 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
     }
     const int waves_per_wg = WG_THREADS / 64;
     pl->wg_per_cu = cfg.wg;
+    pl->ring = cfg.ring;
     pl->grid = std::max(1, std::min(c->n_cu * cfg.wg, (pl->n_items + waves_per_wg - 1) / waves_per_wg));
     *out = pl;
     return RR_OK;
@@ -1121,6 +1225,7 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.n_ages_stage = c->n_ages_stage;
     P.n_q = c->n_tables * c->n_ages_stage;
     P.q_in_lds = (P.n_q <= max_lds_tables_doubles() && (size_t)P.n_q * 8 <= c->lds_per_block) ? 1 : 0;
+    P.ring_off = P.q_in_lds ? (P.n_q + 1) / 2 * 2 : 0;   // 16-byte aligned rings after the tables
     P.v = c->v_override ? c->v_override : c->v.p;
     P.n_steps = c->n_steps;
     P.scen_pad = c->v_override ? c->pad_override : c->scen_pad;
@@ -1163,11 +1268,33 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     return P;
 }
 
+// Dynamic LDS of a recurrence launch: the staged tables, then (curve ring)
+// one ring per wavefront of the workgroup.
+static size_t recurrence_lds_bytes(const RecParams &P, int K, int ring)
+{
+    size_t d = P.q_in_lds ? (size_t)P.n_q : 0;
+    if (ring) d = (size_t)P.ring_off + (size_t)(WG_THREADS / 64) * ring_doubles_per_wave(K);
+    return d * sizeof(double);
+}
+
+// Whether the curve-ring instances can run this portfolio (level single- and
+// joint-life tiles only) with (K, J) and fit their LDS.
+static bool ring_ok(const rr_ctx *c, int K, int J)
+{
+    if (!supported_ring(K, J) || c->has_flow) return false;
+    for (const Tile &T : c->tiles_host)
+        if (T.kind == KIND_REV || T.kind == KIND_LAST) return false;
+    const size_t nq = (size_t)c->n_tables * c->n_ages_stage;
+    const bool q_lds = nq <= (size_t)max_lds_tables_doubles() && nq * 8 <= c->lds_per_block;
+    const size_t d = (q_lds ? (nq + 1) / 2 * 2 : 0) + (size_t)(WG_THREADS / 64) * ring_doubles_per_wave(K);
+    return d * sizeof(double) <= c->lds_per_block;
+}
+
 static int enqueue_run(rr_ctx *c, const rr_run *run, const rr_outputs *out, Plan *pl,
                        double *partial, double *totals, hipStream_t s, bool timed)
 {
     RecParams P = make_params(c, run, out, pl, partial);
-    const size_t lds = P.q_in_lds ? (size_t)P.n_q * sizeof(double) : 0;
+    const size_t lds = recurrence_lds_bytes(P, pl->K, pl->ring);
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (timed) {
         if (!c->ev_free.empty()) {
@@ -1179,7 +1306,11 @@ static int enqueue_run(rr_ctx *c, const rr_run *run, const rr_outputs *out, Plan
         }
         HIPCHK(c, hipEventRecord(ev.first, s));
     }
-    HIPCHK(c, launch_recurrence(pl->K, pl->J, P, pl->grid, lds, s));
+    // Persistent workgroups beyond what the CUs' LDS holds at once would only
+    // start once the queues are drained: leave them out.
+    int grid = pl->grid;
+    if (lds > 0) grid = std::min(grid, c->n_cu * std::max(1, (int)(c->lds_per_cu / lds)));
+    HIPCHK(c, launch_recurrence(pl->K, pl->J, P, grid, lds, s, pl->ring != 0));
     if (timed) {
         HIPCHK(c, hipEventRecord(ev.second, s));
         c->ev_pending.push_back(ev);
@@ -1264,12 +1395,15 @@ static int choose_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, do
     int Kfix = c->opt_k, Jfix = c->opt_j, wgfix = c->opt_wg;
     if (path || run->scen_count == 1) { Kfix = 1; Jfix = 1; }
     if (Kfix && Jfix && !supported_kj(Kfix, Jfix)) Jfix = 1;
-    if (Kfix && Jfix && wgfix) { *cfg_out = LaunchCfg{Kfix, Jfix, wgfix}; return RR_OK; }
+    if (Kfix && Jfix && wgfix && c->opt_ring >= 0) {
+        *cfg_out = LaunchCfg{Kfix, Jfix, wgfix, (c->opt_ring == 1 && ring_ok(c, Kfix, Jfix)) ? 1 : 0};
+        return RR_OK;
+    }
     TuneKey key{run->node_count, run->scen_count, (run->out_mask & RR_OUT_ALL_STATES) ? 4 : 1,
                 path ? 1 : 0, c->gen};
     auto it = c->tuned.find(key);
     if (it != c->tuned.end() && (!Kfix || it->second.K == Kfix) && (!Jfix || it->second.J == Jfix) &&
-        (!wgfix || it->second.wg == wgfix)) {
+        (!wgfix || it->second.wg == wgfix) && (c->opt_ring < 0 || it->second.ring == c->opt_ring)) {
         *cfg_out = it->second;
         return RR_OK;
     }
@@ -1279,9 +1413,13 @@ static int choose_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, do
         if (Kfix && kj[0] != Kfix) continue;
         if (Jfix && kj[1] != Jfix) continue;
         if (kj[0] > std::max(4, run->scen_count)) continue;
-        cands.push_back(LaunchCfg{kj[0], kj[1], wgfix ? wgfix : 2});
+        // scalar-load instances, then (where it runs) the curve-ring instance
+        if (c->opt_ring != 1 || !ring_ok(c, kj[0], kj[1]))
+            cands.push_back(LaunchCfg{kj[0], kj[1], wgfix ? wgfix : 2, 0});
+        if (c->opt_ring != 0 && ring_ok(c, kj[0], kj[1]))
+            cands.push_back(LaunchCfg{kj[0], kj[1], wgfix ? wgfix : 2, 1});
     }
-    if (cands.empty()) cands.push_back(LaunchCfg{Kfix ? Kfix : 8, Jfix ? Jfix : 1, wgfix ? wgfix : 2});
+    if (cands.empty()) cands.push_back(LaunchCfg{Kfix ? Kfix : 8, Jfix ? Jfix : 1, wgfix ? wgfix : 2, 0});
     LaunchCfg best = cands[0];
     float best_ms = 1e30f;
     int rc;
@@ -1386,10 +1524,11 @@ extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outp
     c->last_k = cfg.K;
     c->last_j = cfg.J;
     c->last_wg = cfg.wg;
+    c->last_ring = cfg.ring;
 
     if (c->opt_graph && !c->opt_timing) {
         std::vector<uint64_t> key = {
-            (uint64_t)(uintptr_t)pl, (uint64_t)pl->grid, (uint64_t)run->node_begin,
+            (uint64_t)(uintptr_t)pl, (uint64_t)pl->grid, (uint64_t)pl->ring, (uint64_t)run->node_begin,
             (uint64_t)run->node_count, (uint64_t)run->scen_begin, (uint64_t)run->scen_count,
             (uint64_t)run->node_step_m, (uint64_t)mask, (uint64_t)(uintptr_t)out->r0,
             (uint64_t)(uintptr_t)out->totals, (uint64_t)(uintptr_t)out->path,

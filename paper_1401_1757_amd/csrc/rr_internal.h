@@ -101,6 +101,7 @@ struct RecParams {
     double frac;
     int n_pad;
     int n_user;
+    int ring_off;             // curve-ring launches: first double of the rings in LDS
     const Tile *tiles;
     int n_tiles;
     // work
@@ -121,9 +122,17 @@ struct RecParams {
     const long long *path_off;  // [n_user + 1] (path mode)
 };
 
-// Launchers (rr_kernels.hip).  All are asynchronous on `stream`.
+// Curve ring (level scalar-reserve portfolios): each wavefront stages the
+// discount factors of its K scenarios in LDS, two chunks of RING_C steps.
+constexpr int RING_C = 16;
+constexpr int ring_doubles_per_wave(int K) { return 2 * RING_C * K; }
+
+// Launchers (rr_kernels.hip).  All are asynchronous on `stream`.  ring: the
+// curve-ring instances (supported_ring(K, J); no vector or pattern tiles;
+// lds_bytes then includes the rings after the tables, at p.ring_off).
 hipError_t launch_recurrence(int K, int J, const RecParams &p, int grid, size_t lds_bytes,
-                             hipStream_t stream);
+                             hipStream_t stream, bool ring = false);
+bool supported_ring(int K, int J);
 // scratch: totals_scratch_doubles(node_count, n_tiles, scen_count) doubles
 // (may be null when that is 0).
 hipError_t launch_totals(const double *partial, int node_count, int n_tiles, int scen_count,

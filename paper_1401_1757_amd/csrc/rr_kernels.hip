@@ -20,8 +20,12 @@ bool supported_kj(int K, int J)
 int max_lds_tables_doubles() { return 8192; }   // 64 KiB of tables per workgroup
 
 hipError_t launch_recurrence(int K, int J, const RecParams &p, int grid, size_t lds_bytes,
-                             hipStream_t stream)
+                             hipStream_t stream, bool ring)
 {
+    if (ring) {
+        if (p.has_vector || p.pat_g != nullptr || !supported_ring(K, J)) return hipErrorInvalidValue;
+        return launch_recurrence_ring(K, J, p, grid, lds_bytes, stream);
+    }
     if (p.pat_g != nullptr && p.pat_code != nullptr)
         return launch_recurrence_pat(K, J, p, grid, lds_bytes, stream);
     return launch_switch<false>(K, J, p, grid, lds_bytes, stream);

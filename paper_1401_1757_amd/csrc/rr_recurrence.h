@@ -121,6 +121,49 @@ __device__ __forceinline__ void wait_for(double q, double v)
     asm volatile("" ::"v"(q), "s"(v));
 }
 
+__device__ __forceinline__ void wait_for_v(double q, double v)
+{
+    asm volatile("" ::"v"(q), "v"(v));
+}
+
+// Curve ring of one wavefront (level scalar-reserve items): the discount
+// factors of the item's K scenarios pass through LDS in chunks of RING_C
+// steps, two chunk slots per wavefront.  A chunk is read from the curves with
+// vector loads one chunk ahead (vector loads complete in order, so the wait
+// for a chunk never waits for a later one) and written to its slot when the
+// wavefront enters the chunk before it; every step then reads its K values
+// with wavefront-uniform LDS reads (broadcast, no bank conflicts) one block
+// ahead.  Ring row d (d = steps below the first step of the ring phase) is at
+// (d mod 2 RING_C) * K: the chunk of row d is slot (d / RING_C) mod 2.
+template <int K>
+struct Ring {
+    static constexpr int PL = RING_C * K / 64;   // doubles per lane per chunk
+    static_assert(PL >= 1 && K % PL == 0, "a lane's share of a chunk lies in one step row");
+};
+
+// Lane's share of the chunk whose first row is step tt (rows tt, tt - 1, ...,
+// clamped at step 0): row (lane PL) / K, scenarios (lane PL) mod K onwards.
+template <int K>
+__device__ __forceinline__ void ring_fetch(const double *__restrict__ vb, int stride, int tt,
+                                           int lane, double (&g)[Ring<K>::PL])
+{
+    constexpr int PL = Ring<K>::PL;
+    const int e = lane * PL;
+    const double *src = vb + (ptrdiff_t)max(tt - e / K, 0) * stride + e % K;
+#pragma unroll
+    for (int i = 0; i < PL; ++i) g[i] = src[i];
+}
+
+template <int K>
+__device__ __forceinline__ void ring_store(double *ring, int slot, int lane,
+                                           const double (&g)[Ring<K>::PL])
+{
+    constexpr int PL = Ring<K>::PL;
+    double *dst = ring + slot * RING_C * K + lane * PL;
+#pragma unroll
+    for (int i = 0; i < PL; ++i) dst[i] = g[i];
+}
+
 // Survival probability over one step with the node's mortality shock m
 // applied to the death probability (capped at 1).
 template <bool LDSQ, bool SHOCK>
@@ -205,13 +248,16 @@ __device__ __forceinline__ double pat_factor(PatLane &pl, int t)
 // whose a0 and a1 at step t are the level amounts times F of the payment
 // time.  FLOW_TABLE: one life (J = 1), c at step t = p x the table's cash
 // flow of the step (loaded with the mortality values of the block).
-template <int K, int J, bool LDSQ, bool TWO, bool SHOCK, int FLOW>
+//
+// VR: the all-active phase reads the curves through the wavefront's ring
+// (level flows; `ring` is the wavefront's 2 RING_C K doubles of LDS).
+template <int K, int J, bool LDSQ, bool TWO, bool SHOCK, int FLOW, bool VR = false>
 __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
                                              const double *__restrict__ gq,
                                              const double *__restrict__ vb, int stride,
                                              const ScalarLane (&L)[J], PatLane (&PL)[J], int cfs,
                                              double m, int smax, int smin, double (&r)[J][K],
-                                             double *path)
+                                             double *path, double *ring = nullptr)
 {
     // Cash flow of step t from the table (table tiles only).
     auto cfload = [&](int j, int t) -> double {
@@ -299,7 +345,66 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
             if (path != nullptr && t < L[0].S) path[t] = r[0][0];
         }
     }
-    if constexpr (StepBlock<K, J>::PIPE) {
+    if constexpr (VR) {
+        // Whole chunks of the all-active phase through the ring; the steps
+        // after the last whole chunk take the loops below.
+        constexpr int C = RING_C;
+        static_assert(C % (2 * U) == 0, "a chunk holds whole pairs of blocks");
+        const int lane = threadIdx.x & 63;
+        const int nfull = (t + 1) / C;
+        if (nfull > 0) {
+            const int top0 = t;
+            double g[Ring<K>::PL];
+            ring_fetch<K>(vb, stride, top0, lane, g);
+            ring_store<K>(ring, 0, lane, g);
+            if (nfull > 1) ring_fetch<K>(vb, stride, top0 - C, lane, g);
+            auto load_ring = [&](int tb, double (&vk)[U][K], double (&q1)[U][J], double (&q2)[U][J],
+                                 double (&cv)[U][J]) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double *row = ring + ((top0 - tb + u) & (2 * C - 1)) * K;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) vk[u][k] = row[k];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        q1[u][j] = qload<LDSQ>(lq, gq, L[j].qa + tb - u);
+                        q2[u][j] = TWO ? qload<LDSQ>(lq, gq, L[j].qb + tb - u) : 0.0;
+                        cv[u][j] = 0.0;
+                    }
+            };
+            double av[U][K], aq1[U][J], aq2[U][J], acv[U][J];
+            double bv[U][K], bq1[U][J], bq2[U][J], bcv[U][J];
+            load_ring(t, av, aq1, aq2, acv);
+            for (int ci = 0; ci < nfull; ++ci) {
+                // Entering chunk ci: its successor goes to the slot chunk
+                // ci - 1 used (whose reads are all done), and the chunk after
+                // that is fetched.
+                if (ci + 1 < nfull) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    ring_store<K>(ring, (ci + 1) & 1, lane, g);
+                    if (ci + 2 < nfull) ring_fetch<K>(vb, stride, top0 - (ci + 2) * C, lane, g);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                for (int i = 0; i < C / (2 * U); ++i) {
+                    wait_for_v(aq1[0][0], av[0][0]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_ring(t - U, bv, bq1, bq2, bcv);
+                    __builtin_amdgcn_sched_barrier(0);
+                    run_block(t, av, aq1, aq2, acv);
+                    wait_for_v(bq1[0][0], bv[0][0]);
+                    const int tl = max(t - 2 * U, U - 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_ring(tl, av, aq1, aq2, acv);
+                    __builtin_amdgcn_sched_barrier(0);
+                    run_block(t - U, bv, bq1, bq2, bcv);
+                    t -= 2 * U;
+                }
+            }
+        }
+    } else if constexpr (StepBlock<K, J>::PIPE) {
         // Pairs of blocks through two named buffers (ping-pong): no register
         // copy of a block in flight and no branch between a prefetch and its
         // use, so the compiler keeps every load at its issue point.  The
@@ -350,11 +455,11 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
 
 // An item of `count` (<= J) consecutive tiles of one scalar model and a block
 // of K scenarios: lane l carries slot first + 64 j + l of every tile j.
-template <int K, int J, bool LDSQ, bool TWO, int FLOW>
+template <int K, int J, bool LDSQ, bool TWO, int FLOW, bool VR = false>
 __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__restrict__ lq,
                                            const double *__restrict__ vcurves, int node_rel,
                                            int tile, int count, const Tile &T0, int item_smax,
-                                           int item_smin, int sb, int lane)
+                                           int item_smin, int sb, int lane, double *ring = nullptr)
 {
     const int node = P.node_begin + node_rel;
     const int shift = node * P.node_step;
@@ -409,11 +514,11 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
         }
     }
     if (m == 1.0)
-        scalar_steps<K, J, LDSQ, TWO, false, FLOW>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m, smax,
-                                                   smin, r, path);
+        scalar_steps<K, J, LDSQ, TWO, false, FLOW, VR>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m,
+                                                       smax, smin, r, path, ring);
     else
-        scalar_steps<K, J, LDSQ, TWO, true, FLOW>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m, smax,
-                                                  smin, r, path);
+        scalar_steps<K, J, LDSQ, TWO, true, FLOW, VR>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m,
+                                                      smax, smin, r, path, ring);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         if (j < count) {
@@ -761,28 +866,64 @@ __device__ __forceinline__ void run_markov(const RecParams &P, const double *__r
 // compiler may read the wavefront-uniform curve values with scalar loads.
 // PAT: the portfolio has tiles whose cash flows vary in time (payment
 // patterns or cash-flow tables), run with one policy per lane whatever J.
-template <int K, int J, bool LDSQ, bool VEC, bool PAT>
+// VR: level scalar-reserve portfolios with the curve ring (no vector or
+// pattern tiles); the wavefront's ring follows the tables in LDS.
+template <int K, int J, bool LDSQ, bool VEC, bool PAT, bool VR = false>
 __global__ void __launch_bounds__(WG_THREADS)
 k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__restrict__ items,
              const Tile *__restrict__ tiles, const int *__restrict__ qbeg)
 {
     extern __shared__ double s_q[];
     if constexpr (LDSQ) {
-        for (int i = threadIdx.x; i < P.n_q; i += blockDim.x) s_q[i] = P.q[i];
+        // Stage the tables with 16-byte loads, eight in flight per thread
+        // before their LDS writes (one round trip per batch, not per value).
+        constexpr int B = 8;
+        const int n2 = P.n_q >> 1;
+        const double2 *src = reinterpret_cast<const double2 *>(P.q);
+        double2 *dst = reinterpret_cast<double2 *>(s_q);
+        for (int base = 0; base < n2; base += B * WG_THREADS) {
+            double2 a[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u)   // clamped: every load in bounds, none predicated
+                a[u] = src[min(base + u * WG_THREADS + (int)threadIdx.x, n2 - 1)];
+#pragma unroll
+            for (int u = 0; u < B; ++u)   // all B loads issued before the first write
+                asm volatile("" ::"v"(a[u].x), "v"(a[u].y));
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int i = base + u * WG_THREADS + (int)threadIdx.x;
+                if (i < n2) dst[i] = a[u];
+            }
+        }
+        if ((P.n_q & 1) && threadIdx.x == 0) s_q[P.n_q - 1] = P.q[P.n_q - 1];
         __syncthreads();
     }
+    double *ring = nullptr;
+    if constexpr (VR) ring = s_q + P.ring_off + (threadIdx.x >> 6) * ring_doubles_per_wave(K);
     const int lane = threadIdx.x & 63;
     int qcur = blockIdx.x % P.n_queues;
-    int tried = 0;
-    while (tried < P.n_queues) {
+    while (true) {
         int idx = 0;
         if (lane == 0) idx = atomicAdd(&P.counters[qcur], 1);
         idx = wave_uniform(idx);   // every lane is active here: lane 0's value
         const int beg = wave_uniform(qbeg[qcur]);
         const int end = wave_uniform(qbeg[qcur + 1]);
         if (beg + idx >= end) {
-            qcur = (qcur + 1 == P.n_queues) ? 0 : qcur + 1;
-            ++tried;
+            // This queue is empty: read every queue's head at once (lane i:
+            // queue i) and move to the next one, in queue order after this
+            // one, that still has items; none left: done.  A head read here
+            // may be stale, so a queue can turn out empty at its atomic, and
+            // the scan repeats.
+            bool more = false;
+            if (lane < P.n_queues) {
+                const int h = __hip_atomic_load(&P.counters[lane], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                more = qbeg[lane] + h < qbeg[lane + 1];
+            }
+            const unsigned long long m = __ballot(more);
+            if (m == 0ull) break;
+            const unsigned long long after = m & ~((2ull << qcur) - 1ull);   // queues > qcur
+            qcur = after ? __builtin_ctzll(after) : __builtin_ctzll(m);
             continue;
         }
         const Item it = items[beg + idx];
@@ -831,11 +972,11 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
                     run_vector<K, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
             }
         } else if (T.kind == KIND_SINGLE) {
-            run_scalar<K, J, LDSQ, false, FLOW_LEVEL>(P, s_q, vcurves, node_rel, tile, count, T, smax,
-                                                      smin, sb, lane);
+            run_scalar<K, J, LDSQ, false, FLOW_LEVEL, VR>(P, s_q, vcurves, node_rel, tile, count, T,
+                                                          smax, smin, sb, lane, ring);
         } else if (T.kind == KIND_JOINT) {
-            run_scalar<K, J, LDSQ, true, FLOW_LEVEL>(P, s_q, vcurves, node_rel, tile, count, T, smax,
-                                                     smin, sb, lane);
+            run_scalar<K, J, LDSQ, true, FLOW_LEVEL, VR>(P, s_q, vcurves, node_rel, tile, count, T,
+                                                         smax, smin, sb, lane, ring);
         } else if constexpr (VEC) {
             if (T.kind == KIND_REV)
                 run_vector<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
@@ -893,6 +1034,21 @@ static hipError_t launch_switch(int K, int J, const RecParams &p, int grid, size
     }
     return hipGetLastError();
 }
+
+// Curve-ring instance of (K, J) for level scalar-reserve portfolios.
+template <int K, int J>
+static void launch_kj_ring(const RecParams &p, int grid, size_t lds, hipStream_t s)
+{
+    const dim3 g(grid), b(WG_THREADS);
+    if (p.q_in_lds)
+        hipLaunchKernelGGL((k_recurrence<K, J, true, false, false, true>), g, b, lds, s, p, p.v, p.items, p.tiles, p.qbeg);
+    else
+        hipLaunchKernelGGL((k_recurrence<K, J, false, false, false, true>), g, b, lds, s, p, p.v, p.items, p.tiles, p.qbeg);
+}
+
+// Curve-ring instances (rr_kernels_ring.hip).
+hipError_t launch_recurrence_ring(int K, int J, const RecParams &p, int grid, size_t lds_bytes,
+                                  hipStream_t stream);
 
 // Launch of the kernels with the payment-pattern paths (rr_kernels_pat.hip).
 hipError_t launch_recurrence_pat(int K, int J, const RecParams &p, int grid, size_t lds_bytes,
