@@ -178,6 +178,7 @@ __device__ __forceinline__ double p_eff(const double *__restrict__ lq, const dou
 // Per-lane state of one policy in a scalar-reserve item.
 struct ScalarLane {
     int S;        // remaining term at the node (<= 0: expired or padding)
+    int tmax;     // largest remaining term of the lane's tile (wavefront-uniform)
     int qa, qb;   // LDS indices of the q of life 1 / life 2 at t = 0
     double a0, a1mb1, b1, a1;
     double rS;    // boundary reserve (state 0)
@@ -325,17 +326,26 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
     // (t >= S) takes the step with p = 0, c = 0, a0 = r_S, which leaves its
     // reserve at the boundary value exactly (v * 0 + r_S = r_S), so the loop
     // needs no branches.  Its table reads land in the staged table's padding.
+    // A tile none of whose policies has started yet (t >= its largest term)
+    // skips the step as a whole (a wavefront-uniform branch).
     int t = smax - 1;
     for (; t >= smin; --t) {
         const double *vt = vb + (ptrdiff_t)t * stride;
         double vk[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) vk[k] = vt[k];
+        double x1[J], x2[J], cv[J];   // every table read issued before the first branch
 #pragma unroll
         for (int j = 0; j < J; ++j) {
+            x1[j] = qload<LDSQ>(lq, gq, L[j].qa + t);
+            x2[j] = TWO ? qload<LDSQ>(lq, gq, L[j].qb + t) : 0.0;
+            cv[j] = cfload(j, t);
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (J > 1 && t >= L[j].tmax) continue;
             double p, c, a0;
-            coeffs(j, t, qload<LDSQ>(lq, gq, L[j].qa + t),
-                   TWO ? qload<LDSQ>(lq, gq, L[j].qb + t) : 0.0, cfload(j, t), p, c, a0);
+            coeffs(j, t, x1[j], x2[j], cv[j], p, c, a0);
             const bool on = t < L[j].S;
             p = on ? p : 0.0;
             c = on ? c : 0.0;
@@ -474,6 +484,7 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
     for (int j = 0; j < J; ++j) {
         const int slot = T0.first + j * TILE + lane;   // tiles of an item are consecutive
         if (j < count) {
+            L[j].tmax = wave_uniform(P.tiles[tile + j].smax) - shift;
             L[j].S = P.term[slot] - shift;
             uid[j] = P.uidx[slot];
             L[j].a0 = P.coef[0 * P.n_pad + slot];
@@ -490,6 +501,7 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
 #pragma unroll
             for (int k = 0; k < K; ++k) r[j][k] = L[j].rS;
         } else {   // missing tile of a short item: an always-inactive lane
+            L[j].tmax = -1;
             L[j].S = -1;
             uid[j] = -1;
             L[j].a0 = L[j].a1 = L[j].b1 = L[j].a1mb1 = L[j].rS = 0.0;
