@@ -324,7 +324,7 @@ int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out)
 #define RR_OPT_LAST_WG      7   /* read-only: workgroups per CU of the last launch */
 #define RR_OPT_BLOCK_J      8   /* policies per lane (scalar-reserve models): 0 = autotune, 1, 2, 4 */
 #define RR_OPT_LAST_J       9   /* read-only: policies per lane of the last launch */
-#define RR_OPT_TERM_BUCKET 10   /* months per remaining-term bucket when tiling (default 16);
+#define RR_OPT_TERM_BUCKET 10   /* months per remaining-term bucket when tiling (default 4);
                                    applies from the next rr_portfolio_upload */
 #define RR_OPT_CURVE_RING  11   /* level single-/joint-life portfolios: stage each wavefront's
                                    scenario curves in an LDS ring (-1 = autotune, 0 = off

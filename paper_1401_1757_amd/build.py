@@ -34,19 +34,33 @@ def _sources():
     return dev, host
 
 
+def _includes(path: str, seen: set) -> set:
+    """The project headers a source includes, directly or through other headers."""
+    import re
+    with open(path) as f:
+        names = re.findall(r'^\s*#\s*include\s+"([^"]+)"', f.read(), re.M)
+    for n in names:
+        for d in (os.path.dirname(path), CSRC, INCLUDE):
+            h = os.path.join(d, n)
+            if os.path.exists(h):
+                if h not in seen:
+                    seen.add(h)
+                    _includes(h, seen)
+                break
+    return seen
+
+
 def _stale(obj: str, src: str) -> bool:
-    """The object is missing or older than its source or any header."""
+    """The object is missing or older than its source or a header it includes."""
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    headers = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
-    headers += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE) if h.endswith(".h")]
-    return any(os.path.getmtime(f) > t for f in [src, *headers])
+    return any(os.path.getmtime(f) > t for f in [src, *_includes(src, set())])
 
 
 def build(verbose: bool = False, jobs: int = 4, incremental: bool = False) -> str:
     """Compile every source and link librr.so.  Recompiles everything unless
-    incremental, which keeps objects newer than their source and every header."""
+    incremental, which keeps objects newer than their source and its headers."""
     os.makedirs(OBJDIR, exist_ok=True)
     dev, host = _sources()
     inc = ["-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include"]

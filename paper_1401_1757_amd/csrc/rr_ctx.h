@@ -160,7 +160,7 @@ struct rr_ctx {
 
     // options
     int opt_k = 0, opt_j = 0, opt_wg = 0, opt_graph = 1, opt_timing = 0, opt_xcd = 1;
-    int opt_term_bucket = 16;             // months per remaining-term bucket in the sort
+    int opt_term_bucket = 4;              // months per remaining-term bucket in the sort
     int opt_ring = 0;                     // -1: autotune, 0: off (default), 1: on where supported
     int opt_lane_spread = 1;              // deal tile lanes over LDS banks (next upload)
     int opt_curve_share = 1;              // queue windows whose wavefronts share curve blocks

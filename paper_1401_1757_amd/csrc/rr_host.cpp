@@ -731,9 +731,9 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     // Within a model, remaining terms are bucketed (width term_bucket months,
-    // longest first) and each bucket is ordered by table and age, so that the
-    // 64 lanes of a tile read neighbouring entries of the mortality table (few
-    // LDS bank conflicts) at the price of at most term_bucket ragged steps.
+    // default 4, longest first) and each bucket is ordered by table and age:
+    // tiles of neighbouring table entries at the price of at most term_bucket
+    // ragged steps (the lanes are then dealt over the LDS banks below).
     const int tb = std::max(1, c->opt_term_bucket);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         int ka = group_of(a), kb = group_of(b);
