@@ -348,8 +348,9 @@ def main():
     ap.add_argument("--block-j", type=int, default=0, help="pin policies per lane (0 = autotune)")
     ap.add_argument("--lane-spread", type=int, default=1,
                     help="1: deal tile lanes over the LDS banks (default), 0: sorted lane order")
-    ap.add_argument("--curve-share", type=int, default=1,
-                    help="1: queue windows whose wavefronts share scenario blocks (default), 0: off")
+    ap.add_argument("--curve-share", type=int, default=2,
+                    help="2: workgroups take windows of items of one scenario block together "
+                         "(default), 1: the same order taken item by item, 0: plain queues")
     ap.add_argument("--ring", type=int, default=0,
                     help="curve ring for level portfolios: -1 autotune, 0 off (default), 1 on")
     ap.add_argument("--term-bucket", type=int, default=0, help="months per term bucket (0 = default)")

@@ -334,9 +334,12 @@ int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out)
 #define RR_OPT_LANE_SPREAD 13   /* 1 = order the lanes of each tile so that their mortality-table
                                    reads spread over the LDS banks (default), 0 = sorted order;
                                    applies from the next rr_portfolio_upload */
-#define RR_OPT_CURVE_SHARE 14   /* 1 = order each work queue so that the wavefronts of a workgroup
-                                   take items of one scenario block together (default), 0 = plain
-                                   longest-first order */
+#define RR_OPT_CURVE_SHARE 14   /* 2 = order each work queue in windows of one item per
+                                   wavefront of a workgroup, of one scenario block and about the
+                                   same length, each workgroup taking a window with one atomic and
+                                   running its items together, so that its wavefronts read the same
+                                   curve lines (default); 1 = the same order, items taken one by
+                                   one; 0 = plain longest-first order */
 int rr_set_option(rr_ctx *ctx, int32_t option, int64_t value);
 int rr_get_option(rr_ctx *ctx, int32_t option, int64_t *value);
 

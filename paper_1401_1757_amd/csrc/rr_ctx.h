@@ -163,7 +163,7 @@ struct rr_ctx {
     int opt_term_bucket = 4;              // months per remaining-term bucket in the sort
     int opt_ring = 0;                     // -1: autotune, 0: off (default), 1: on where supported
     int opt_lane_spread = 1;              // deal tile lanes over LDS banks (next upload)
-    int opt_curve_share = 1;              // queue windows whose wavefronts share curve blocks
+    int opt_curve_share = 2;              // 0: plain queues, 1: dealt windows, 2: windows per workgroup
     int last_k = 0, last_j = 0, last_wg = 0, last_ring = 0;   // configuration of the last recurrence launch
 
     // timing

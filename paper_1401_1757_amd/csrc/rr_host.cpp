@@ -389,12 +389,13 @@ extern "C" int rr_set_option(rr_ctx *c, int32_t option, int64_t value)
         return RR_OK;
     case RR_OPT_LANE_SPREAD: c->opt_lane_spread = value ? 1 : 0; return RR_OK;   // next upload
     case RR_OPT_CURVE_SHARE:
-        if (c->opt_curve_share != (value ? 1 : 0)) {
+        if (value < 0 || value > 2) return fail(c, RR_EINVAL, "curve share must be 0, 1 or 2");
+        if (c->opt_curve_share != value) {
             HIPCHK(c, hipStreamSynchronize(c->stream));   // launches in flight read the old queues
-            drop_graphs(c);
-            c->plans.clear();   // queues are rebuilt on the next call
+            drop_graphs(c);                                 // captured kernels carry the mode
+            if ((c->opt_curve_share > 0) != (value > 0)) c->plans.clear();   // queue order changes
         }
-        c->opt_curve_share = value ? 1 : 0;
+        c->opt_curve_share = (int)value;
         return RR_OK;
     case RR_OPT_USE_GRAPH: c->opt_graph = value ? 1 : 0; return RR_OK;
     case RR_OPT_KERNEL_TIMING: c->opt_timing = value ? 1 : 0; return RR_OK;
@@ -1226,6 +1227,7 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.n_q = c->n_tables * c->n_ages_stage;
     P.q_in_lds = (P.n_q <= max_lds_tables_doubles() && (size_t)P.n_q * 8 <= c->lds_per_block) ? 1 : 0;
     P.ring_off = P.q_in_lds ? (P.n_q + 1) / 2 * 2 : 0;   // 16-byte aligned rings after the tables
+    P.win = c->opt_curve_share == 2 ? 1 : 0;
     P.v = c->v_override ? c->v_override : c->v.p;
     P.n_steps = c->n_steps;
     P.scen_pad = c->v_override ? c->pad_override : c->scen_pad;

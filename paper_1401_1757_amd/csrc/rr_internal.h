@@ -109,6 +109,7 @@ struct RecParams {
     const int *qbeg;          // [n_queues + 1]
     int *counters;            // [MAX_QUEUES + 1]: queue heads, then finished-wave count
     int n_queues;
+    int win;                  // 1: workgroups take windows of WG_THREADS/64 items together
     // run
     int node_begin;
     int scen_begin;

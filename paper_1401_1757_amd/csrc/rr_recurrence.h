@@ -914,10 +914,46 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
     if constexpr (VR) ring = s_q + P.ring_off + (threadIdx.x >> 6) * ring_doubles_per_wave(K);
     const int lane = threadIdx.x & 63;
     int qcur = blockIdx.x % P.n_queues;
+    __shared__ int s_win[2];   // window mode: first item of the window, its queue (-1: none left)
     while (true) {
         int idx = 0;
-        if (lane == 0) idx = atomicAdd(&P.counters[qcur], 1);
-        idx = wave_uniform(idx);   // every lane is active here: lane 0's value
+        if (P.win) {
+            // The workgroup takes a window of WG_THREADS/64 consecutive items
+            // with one atomic, one item per wavefront, and starts them
+            // together; the next window waits for all of them.  Thread 0
+            // moves the workgroup to another queue when this one is empty.
+            constexpr int NW = WG_THREADS / 64;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int q = qcur, base = -1;
+                for (int scan = 0; scan <= P.n_queues && base < 0; ++scan) {
+                    const int b = atomicAdd(&P.counters[q], NW);
+                    if (qbeg[q] + b < qbeg[q + 1]) {
+                        base = b;
+                        break;
+                    }
+                    int nq = -1;   // next queue with items left (heads may be stale: rescan)
+                    for (int i = 1; i <= P.n_queues && nq < 0; ++i) {
+                        const int c = (q + i) % P.n_queues;
+                        const int h = __hip_atomic_load(&P.counters[c], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                        if (qbeg[c] + h < qbeg[c + 1]) nq = c;
+                    }
+                    if (nq < 0) break;
+                    q = nq;
+                }
+                s_win[0] = base;
+                s_win[1] = base < 0 ? -1 : q;
+            }
+            __syncthreads();
+            if (s_win[1] < 0) break;
+            qcur = s_win[1];
+            idx = s_win[0] + (int)(threadIdx.x >> 6);
+            if (wave_uniform(qbeg[qcur]) + idx >= wave_uniform(qbeg[qcur + 1])) continue;   // partial window
+        } else {
+            if (lane == 0) idx = atomicAdd(&P.counters[qcur], 1);
+            idx = wave_uniform(idx);   // every lane is active here: lane 0's value
+        }
         const int beg = wave_uniform(qbeg[qcur]);
         const int end = wave_uniform(qbeg[qcur + 1]);
         if (beg + idx >= end) {

@@ -127,3 +127,32 @@ def test_ring_c3_full_size_sampled(ctx):
     idx = rng.choice(pf.n, 40, replace=False)
     ref = oracle.reserves(b, pf.subset(idx), 0, 1, 0, b.n_scen)
     assert_reserves_close(r0[:, idx, :], ref["r_all"][..., 0], ref["gross"])
+
+
+@pytest.mark.parametrize("K,J,wg", [(16, 4, 1), (8, 2, 2), (4, 1, 3)])
+def test_queue_modes_bitwise(ctx, K, J, wg):
+    """Plain longest-first queues, dealt windows, and windows taken by whole
+    workgroups (one atomic per window, partial windows at queue ends, queue
+    switching) give the same results bit for bit, equal to the oracle."""
+    rng = np.random.default_rng(40 + K + J)
+    w = synth.random_small(rng, n=700, n_steps=120, n_scen=53, n_nodes=3, shock=True)
+    b = w.basis
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(w.portfolio)
+    res = []
+    for mode in (0, 1, 2, 2):
+        ctx.set_option(OPT_K, K)
+        ctx.set_option(OPT_J, J)
+        ctx.set_option(OPT_WG, wg)
+        ctx.set_option(14, mode)
+        _say(f"queue mode {mode} K={K} J={J} wg={wg}")
+        out = ctx.alloc_outputs(3, b.n_scen, all_states=True)
+        ctx.reserve_recurrence(0, 3, 0, b.n_scen, 12, out)
+        torch.cuda.synchronize()
+        res.append((to_np(out["r0"]), to_np(out["totals"])))
+    for r, t in res[1:]:
+        assert np.array_equal(r, res[0][0])
+        assert np.array_equal(t, res[0][1])
+    ref = oracle.reserves(b, w.portfolio, 0, 3, 0, b.n_scen, 12)
+    from tests._helpers import assert_states_close
+    assert_states_close(res[0][0], ref["r_all"], ref["gross"])
