@@ -314,7 +314,8 @@ def representative_leg(rr, synth, sync, steps=5):
                 "launch": {"block_k": ctx.get_option(rr.OPT_LAST_K),
                            "block_j": ctx.get_option(rr.OPT_LAST_J),
                            "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG),
-                           "curve_ring": ctx.get_option(rr.OPT_LAST_RING)},
+                           "curve_ring": ctx.get_option(rr.OPT_LAST_RING),
+                           "windows": ctx.get_option(rr.OPT_LAST_WINDOWS)},
                 "first_call_s": first,
                 "paper_context": "the paper estimates 5.7 s wall per scenario for this portfolio "
                                  "on a 2-core laptop CPU (Sec. 5.3); here ms_per_step covers "
@@ -348,9 +349,10 @@ def main():
     ap.add_argument("--block-j", type=int, default=0, help="pin policies per lane (0 = autotune)")
     ap.add_argument("--lane-spread", type=int, default=1,
                     help="1: deal tile lanes over the LDS banks (default), 0: sorted lane order")
-    ap.add_argument("--curve-share", type=int, default=2,
-                    help="2: workgroups take windows of items of one scenario block together "
-                         "(default), 1: the same order taken item by item, 0: plain queues")
+    ap.add_argument("--curve-share", type=int, default=-1,
+                    help="2: workgroups take windows of items of one scenario block together, "
+                         "1: the same order taken item by item, 0: plain queues, "
+                         "-1: 2 or 1 as the autotuner finds (default)")
     ap.add_argument("--ring", type=int, default=0,
                     help="curve ring for level portfolios: -1 autotune, 0 off (default), 1 on")
     ap.add_argument("--term-bucket", type=int, default=0, help="months per term bucket (0 = default)")
@@ -434,7 +436,8 @@ def main():
                           "block_k": ctx.get_option(rr.OPT_LAST_K),
                           "block_j": ctx.get_option(rr.OPT_LAST_J),
                           "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG),
-                          "curve_ring": ctx.get_option(rr.OPT_LAST_RING)}))
+                          "curve_ring": ctx.get_option(rr.OPT_LAST_RING),
+                          "windows": ctx.get_option(rr.OPT_LAST_WINDOWS)}))
         ctx.close()
         return
 
@@ -484,6 +487,7 @@ def main():
         "upload_s": upload_s,
         "launch": {"block_k": k_opt, "block_j": j_opt, "wg_per_cu": wg_opt,
                    "curve_ring": ctx.get_option(rr.OPT_LAST_RING),
+                   "windows": ctx.get_option(rr.OPT_LAST_WINDOWS),
                    "autotuned": args.block_k == 0},
     }
 

@@ -338,8 +338,10 @@ int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out)
                                    wavefront of a workgroup, of one scenario block and about the
                                    same length, each workgroup taking a window with one atomic and
                                    running its items together, so that its wavefronts read the same
-                                   curve lines (default); 1 = the same order, items taken one by
-                                   one; 0 = plain longest-first order */
+                                   curve lines; 1 = the same order, items taken one by one; 0 =
+                                   plain longest-first order; -1 = 2 or 1, whichever the autotuner
+                                   finds faster (default) */
+#define RR_OPT_LAST_WINDOWS 15  /* read-only: 1 if the last launch took windows per workgroup */
 int rr_set_option(rr_ctx *ctx, int32_t option, int64_t value);
 int rr_get_option(rr_ctx *ctx, int32_t option, int64_t *value);
 

@@ -46,6 +46,7 @@ struct Plan {
     int J = 1;
     int wg_per_cu = 2;
     int ring = 0;       // launch with the curve-ring instances
+    int win = 0;        // workgroups take their windows of items together
     int grid = 1;
     int n_items = 0;
     int n_queues = 1;
@@ -66,6 +67,7 @@ struct PlanKey {
 struct LaunchCfg {
     int K = 1, J = 1, wg = 2;
     int ring = 0;       // curve-ring instances (level scalar-reserve portfolios)
+    int win = 0;        // workgroups take windows of items together (one atomic per window)
 };
 
 struct TuneKey {
@@ -163,8 +165,9 @@ struct rr_ctx {
     int opt_term_bucket = 4;              // months per remaining-term bucket in the sort
     int opt_ring = 0;                     // -1: autotune, 0: off (default), 1: on where supported
     int opt_lane_spread = 1;              // deal tile lanes over LDS banks (next upload)
-    int opt_curve_share = 2;              // 0: plain queues, 1: dealt windows, 2: windows per workgroup
-    int last_k = 0, last_j = 0, last_wg = 0, last_ring = 0;   // configuration of the last recurrence launch
+    int opt_curve_share = -1;             // 0: plain queues, 1: dealt windows, 2: windows per
+                                          // workgroup, -1: 1 or 2, whichever the autotuner finds faster
+    int last_k = 0, last_j = 0, last_wg = 0, last_ring = 0, last_win = 0;   // configuration of the last recurrence launch
 
     // timing
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;

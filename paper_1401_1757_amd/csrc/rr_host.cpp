@@ -389,11 +389,12 @@ extern "C" int rr_set_option(rr_ctx *c, int32_t option, int64_t value)
         return RR_OK;
     case RR_OPT_LANE_SPREAD: c->opt_lane_spread = value ? 1 : 0; return RR_OK;   // next upload
     case RR_OPT_CURVE_SHARE:
-        if (value < 0 || value > 2) return fail(c, RR_EINVAL, "curve share must be 0, 1 or 2");
+        if (value < -1 || value > 2) return fail(c, RR_EINVAL, "curve share must be -1, 0, 1 or 2");
         if (c->opt_curve_share != value) {
             HIPCHK(c, hipStreamSynchronize(c->stream));   // launches in flight read the old queues
             drop_graphs(c);                                 // captured kernels carry the mode
-            if ((c->opt_curve_share > 0) != (value > 0)) c->plans.clear();   // queue order changes
+            if ((c->opt_curve_share != 0) != (value != 0)) c->plans.clear();   // queue order changes
+            c->tuned.clear();
         }
         c->opt_curve_share = (int)value;
         return RR_OK;
@@ -424,6 +425,7 @@ extern "C" int rr_get_option(rr_ctx *c, int32_t option, int64_t *value)
     case RR_OPT_LAST_RING: *value = c->last_ring; return RR_OK;
     case RR_OPT_LANE_SPREAD: *value = c->opt_lane_spread; return RR_OK;
     case RR_OPT_CURVE_SHARE: *value = c->opt_curve_share; return RR_OK;
+    case RR_OPT_LAST_WINDOWS: *value = c->last_win; return RR_OK;
     default: return fail(c, RR_EINVAL, "unknown option %d", option);
     }
 }
@@ -1162,7 +1164,7 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
         }
         std::vector<Item> items;
         std::vector<int> qbeg(queues + 1, 0);
-        const int share = c->opt_curve_share ? WG_THREADS / 64 : 1;
+        const int share = c->opt_curve_share != 0 ? WG_THREADS / 64 : 1;
         for (int qi = 0; qi < queues; ++qi) {
             // Longest first.  An item's curves are read with scalar loads
             // through the scalar cache that neighbouring CUs share, so the
@@ -1212,6 +1214,7 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
     const int waves_per_wg = WG_THREADS / 64;
     pl->wg_per_cu = cfg.wg;
     pl->ring = cfg.ring;
+    pl->win = cfg.win;
     pl->grid = std::max(1, std::min(c->n_cu * cfg.wg, (pl->n_items + waves_per_wg - 1) / waves_per_wg));
     *out = pl;
     return RR_OK;
@@ -1227,7 +1230,7 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.n_q = c->n_tables * c->n_ages_stage;
     P.q_in_lds = (P.n_q <= max_lds_tables_doubles() && (size_t)P.n_q * 8 <= c->lds_per_block) ? 1 : 0;
     P.ring_off = P.q_in_lds ? (P.n_q + 1) / 2 * 2 : 0;   // 16-byte aligned rings after the tables
-    P.win = c->opt_curve_share == 2 ? 1 : 0;
+    P.win = pl->win;
     P.v = c->v_override ? c->v_override : c->v.p;
     P.n_steps = c->n_steps;
     P.scen_pad = c->v_override ? c->pad_override : c->scen_pad;
@@ -1349,7 +1352,7 @@ int rr::host::run_items(rr_ctx *c, const rr_run *run, const std::vector<Item> &i
     pl.n_items = (int)items.size();
     pl.n_queues = 1;
     pl.wg_per_cu = 2;
-    pl.grid = std::max(1, std::min(c->n_cu * 2, (pl.n_items + 3) / 4));
+    pl.grid = std::max(1, std::min(c->n_cu * 2, (pl.n_items + WG_THREADS / 64 - 1) / (WG_THREADS / 64)));
     rr_run r = *run;
     r.out_mask = RR_OUT_R0;
     rr_outputs o;
@@ -1397,8 +1400,9 @@ static int choose_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, do
     int Kfix = c->opt_k, Jfix = c->opt_j, wgfix = c->opt_wg;
     if (path || run->scen_count == 1) { Kfix = 1; Jfix = 1; }
     if (Kfix && Jfix && !supported_kj(Kfix, Jfix)) Jfix = 1;
-    if (Kfix && Jfix && wgfix && c->opt_ring >= 0) {
-        *cfg_out = LaunchCfg{Kfix, Jfix, wgfix, (c->opt_ring == 1 && ring_ok(c, Kfix, Jfix)) ? 1 : 0};
+    const int win0 = (c->opt_curve_share == 2 || c->opt_curve_share == -1) ? 1 : 0;
+    if (Kfix && Jfix && wgfix && c->opt_ring >= 0 && c->opt_curve_share >= 0) {
+        *cfg_out = LaunchCfg{Kfix, Jfix, wgfix, (c->opt_ring == 1 && ring_ok(c, Kfix, Jfix)) ? 1 : 0, win0};
         return RR_OK;
     }
     TuneKey key{run->node_count, run->scen_count, (run->out_mask & RR_OUT_ALL_STATES) ? 4 : 1,
@@ -1417,28 +1421,43 @@ static int choose_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, do
         if (kj[0] > std::max(4, run->scen_count)) continue;
         // scalar-load instances, then (where it runs) the curve-ring instance
         if (c->opt_ring != 1 || !ring_ok(c, kj[0], kj[1]))
-            cands.push_back(LaunchCfg{kj[0], kj[1], wgfix ? wgfix : 2, 0});
+            cands.push_back(LaunchCfg{kj[0], kj[1], wgfix ? wgfix : 2, 0, win0});
         if (c->opt_ring != 0 && ring_ok(c, kj[0], kj[1]))
-            cands.push_back(LaunchCfg{kj[0], kj[1], wgfix ? wgfix : 2, 1});
+            cands.push_back(LaunchCfg{kj[0], kj[1], wgfix ? wgfix : 2, 1, win0});
     }
-    if (cands.empty()) cands.push_back(LaunchCfg{Kfix ? Kfix : 8, Jfix ? Jfix : 1, wgfix ? wgfix : 2, 0});
+    if (cands.empty())
+        cands.push_back(LaunchCfg{Kfix ? Kfix : 8, Jfix ? Jfix : 1, wgfix ? wgfix : 2, 0, win0});
     LaunchCfg best = cands[0];
     float best_ms = 1e30f;
     int rc;
-    for (const LaunchCfg &cf : cands) {   // scenarios x policies per lane at the default workgroups
-        if (!supported_kj(cf.K, cf.J)) continue;
-        float ms;
-        if ((rc = time_config(c, run, out, cf, partial, totals, &ms))) return rc;
-        if (ms < best_ms) { best_ms = ms; best = cf; }
+    // Every (K, J) shape at one and two workgroups per CU (registers decide
+    // which fits better), then more workgroups for the best.
+    for (const LaunchCfg &c0 : cands) {
+        if (!supported_kj(c0.K, c0.J)) continue;
+        for (int w : {1, 2}) {
+            if (wgfix && w != wgfix) continue;
+            LaunchCfg cf = c0;
+            cf.wg = wgfix ? wgfix : w;
+            float ms;
+            if ((rc = time_config(c, run, out, cf, partial, totals, &ms))) return rc;
+            if (ms < best_ms) { best_ms = ms; best = cf; }
+        }
     }
     if (!wgfix) {
-        for (int w : {1, 3, 4}) {
+        for (int w : {3, 4}) {
             LaunchCfg cf = best;
             cf.wg = w;
             float ms;
             if ((rc = time_config(c, run, out, cf, partial, totals, &ms))) return rc;
             if (ms < best_ms) { best_ms = ms; best = cf; }
         }
+    }
+    if (c->opt_curve_share == -1) {   // windows taken item by item instead
+        LaunchCfg cf = best;
+        cf.win = 0;
+        float ms;
+        if ((rc = time_config(c, run, out, cf, partial, totals, &ms))) return rc;
+        if (ms < best_ms) { best_ms = ms; best = cf; }
     }
     c->tuned[key] = best;
     *cfg_out = best;
@@ -1527,10 +1546,12 @@ extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outp
     c->last_j = cfg.J;
     c->last_wg = cfg.wg;
     c->last_ring = cfg.ring;
+    c->last_win = cfg.win;
 
     if (c->opt_graph && !c->opt_timing) {
         std::vector<uint64_t> key = {
-            (uint64_t)(uintptr_t)pl, (uint64_t)pl->grid, (uint64_t)pl->ring, (uint64_t)run->node_begin,
+            (uint64_t)(uintptr_t)pl, (uint64_t)pl->grid, (uint64_t)pl->ring, (uint64_t)pl->win,
+            (uint64_t)run->node_begin,
             (uint64_t)run->node_count, (uint64_t)run->scen_begin, (uint64_t)run->scen_count,
             (uint64_t)run->node_step_m, (uint64_t)mask, (uint64_t)(uintptr_t)out->r0,
             (uint64_t)(uintptr_t)out->totals, (uint64_t)(uintptr_t)out->path,

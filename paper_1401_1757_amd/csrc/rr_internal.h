@@ -23,7 +23,7 @@ constexpr int TILE = 64;          // policies per tile = lanes per wavefront
 constexpr int N_COEF = 7;         // per-policy cash-flow coefficients
 constexpr int MAX_QUEUES = 8;     // one work queue per XCD
 #ifndef RR_WG_THREADS
-#define RR_WG_THREADS 256
+#define RR_WG_THREADS 512   // eight wavefronts: two per SIMD, one work window per CU
 #endif
 constexpr int WG_THREADS = RR_WG_THREADS;   // wavefronts per workgroup x 64
 

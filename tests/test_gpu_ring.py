@@ -140,7 +140,7 @@ def test_queue_modes_bitwise(ctx, K, J, wg):
     ctx.basis_upload(b.q, b.v, b.shock)
     ctx.portfolio_upload(w.portfolio)
     res = []
-    for mode in (0, 1, 2, 2):
+    for mode in (0, 1, 2, 2, -1):
         ctx.set_option(OPT_K, K)
         ctx.set_option(OPT_J, J)
         ctx.set_option(OPT_WG, wg)
