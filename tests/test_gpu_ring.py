@@ -156,3 +156,22 @@ def test_queue_modes_bitwise(ctx, K, J, wg):
     ref = oracle.reserves(b, w.portfolio, 0, 3, 0, b.n_scen, 12)
     from tests._helpers import assert_states_close
     assert_states_close(res[0][0], ref["r_all"], ref["gross"])
+
+
+def test_scheduling_options_validated(ctx, rr):
+    """Out-of-range values of the scheduling options are rejected; the
+    read-only options report the last launch."""
+    for opt, bad in ((OPT_RING, 2), (OPT_RING, -2), (14, 3), (14, -2)):
+        with pytest.raises(rr.RRError) as e:
+            ctx.set_option(opt, bad)
+        assert e.value.code == rr.RR_EINVAL
+    assert ctx.get_option(OPT_RING) == 0          # curve ring off by default
+    assert ctx.get_option(14) == -1               # window mode chosen by the autotuner
+    assert ctx.get_option(13) == 1                # lane spread on
+    assert ctx.get_option(10) == 4                # term bucket, months
+    rng = np.random.default_rng(3)
+    w = synth.random_small(rng, n=200, n_steps=60, n_scen=40, n_nodes=1, products=SCALAR_PRODUCTS)
+    _say("scheduling options")
+    run_and_compare(ctx, w)
+    assert ctx.get_option(rr.OPT_LAST_WINDOWS) in (0, 1)
+    assert ctx.get_option(OPT_LAST_RING) == 0
