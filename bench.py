@@ -113,23 +113,73 @@ def timed_steps(fn, steps, sync):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(w, seconds_target=15.0):
-    """The oracle as it stands, on a bounded sample of the workload: the whole
-    portfolio over the first scenarios, sized to about seconds_target."""
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu's "Model name", from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_share() -> int:
+    """Threads for the CPU leg: the CPU share this process is given
+    (OMP_NUM_THREADS, as a GPU machine sets it per GPU), else every core."""
+    val = os.environ.get("OMP_NUM_THREADS", "").strip()
+    if val.isdigit() and int(val) > 0:
+        return int(val)
+    return os.cpu_count() or 1
+
+
+def cpu_baseline(w, reps=7, seconds_per_run=1.2):
+    """The oracle's reduced mode (zero-reserve states removed, the same
+    per-product recurrences the GPU runs; pinned to the dense mode) on a
+    bounded sample of the workload -- the whole portfolio over the first
+    scenarios -- with the process's CPU share and with one core, minimum and
+    median of `reps` runs each; the dense general form once, for
+    information."""
     import oracle
-    threads = int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
     b, pf = w.basis, w.portfolio
+    nproc = os.cpu_count() or 1
+    share = cpu_share()
+
+    def sample(threads):
+        t0 = time.perf_counter()
+        oracle.reserves_reduced(b, pf, 0, 1, 0, 1, n_threads=threads, want_r=False)
+        per_scen = time.perf_counter() - t0
+        n_scen = int(max(1, min(b.n_scen, round(seconds_per_run / max(per_scen, 1e-6)))))
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.reserves_reduced(b, pf, 0, 1, 0, n_scen, n_threads=threads, want_r=False)
+            ts.append(time.perf_counter() - t0)
+        ts = np.array(ts)
+        vals = pf.n * n_scen / ts
+        return {"threads": threads, "scenarios": n_scen, "valuations_per_s_best": float(vals.max()),
+                "valuations_per_s_median": float(np.median(vals)), "seconds_min": float(ts.min()),
+                "seconds_median": float(np.median(ts))}
+
+    multi = sample(share)
+    single = sample(1)
     t0 = time.perf_counter()
-    oracle.reserves(b, pf, 0, 1, 0, 1, want_gross=False, n_threads=threads)
-    per_scen = time.perf_counter() - t0
-    n_scen = int(max(1, min(b.n_scen, round(seconds_target / max(per_scen, 1e-6)))))
-    t0 = time.perf_counter()
-    oracle.reserves(b, pf, 0, 1, 0, n_scen, want_gross=False, n_threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": pf.n * n_scen / dt, "unit": "valuations/s", "cores": threads,
+    n_dense = max(1, min(b.n_scen, multi["scenarios"] // 8))
+    oracle.reserves(b, pf, 0, 1, 0, n_dense, want_gross=False, n_threads=share)
+    dense_val = pf.n * n_dense / (time.perf_counter() - t0)
+    return {"value": multi["valuations_per_s_median"], "unit": "valuations/s", "cores": share,
             "kind": "oracle",
-            "sample": f"all {pf.n} policies x first {n_scen} scenarios of the workload "
-                      f"({dt:.1f} s, dense general-form recurrence, {threads} OpenMP threads)"}
+            "sample": f"all {pf.n} policies x first {multi['scenarios']} scenarios of the workload, "
+                      f"oracle reduced mode (zero-reserve states removed), {share} OpenMP threads, "
+                      f"median of {reps} runs; 1 core: all policies x first {single['scenarios']} "
+                      f"scenarios",
+            "nproc": nproc, "cpu_model": cpu_model(),
+            "threads_note": "the process's CPU share (OMP_NUM_THREADS), not every core nproc shows",
+            "share": multi, "one_core": single,
+            "one_core_valuations_per_s": single["valuations_per_s_median"],
+            "dense_general_form_valuations_per_s": dense_val,
+            "dense_sample_scenarios": n_dense}
 
 
 SURROGATE_TRAIN = dict(seed=1005, n=5000, n_nodes=20, n_scen=100)
@@ -420,6 +470,16 @@ def main():
     sync()
     elapsed = timed_steps(step, args.steps, sync)
     ms_per_step = 1e3 * elapsed / args.steps
+    # The paper's protocol (minimum of 7 runs): seven single steps, each
+    # between HIP events on the stream the library launches on (the null
+    # stream, torch's default stream here).
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(7)]
+    for e0, e1 in evs:
+        e0.record()
+        step()
+        e1.record()
+    sync()
+    step_ms7 = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
     flops, ops, live, vsteps = scenario_step_work(pf)
     n_val = live * b.n_scen
     value = n_val / (elapsed / args.steps)
@@ -483,6 +543,8 @@ def main():
                      "flop_cap": flops / (2 * ops)},
         "valuation_steps_per_s": vsteps * b.n_scen / (elapsed / args.steps),
         "ms_per_step_direct_launch": 1e3 * elapsed_direct / args.steps,
+        "step_ms_min_of_7": float(step_ms7.min()),
+        "step_ms_median_of_7": float(np.median(step_ms7)),
         "first_call_s": first_call_s,
         "upload_s": upload_s,
         "launch": {"block_k": k_opt, "block_j": j_opt, "wg_per_cu": wg_opt,
@@ -523,10 +585,24 @@ def main():
             f4()
         e4 = timed_steps(f4, 10, sync)
         live4 = sum(int((w4.portfolio.term_m - 12 * k > 0).sum()) for k in range(w4.basis.n_nodes))
+        ctx.set_option(rr.OPT_KERNEL_TIMING, 1)
+        ctx.kernel_times()
+        timed_steps(f4, 10, sync)
+        k4 = float(np.mean(ctx.kernel_times()))
+        ctx.set_option(rr.OPT_KERNEL_TIMING, 0)
+        flops4 = sum(scenario_step_work(w4.portfolio, k, 12)[0] for k in range(w4.basis.n_nodes))
+        flops4 *= w4.basis.n_scen
         sec["C4_nested_60_nodes"] = {"valuations_per_s": live4 * w4.basis.n_scen / (e4 / 10),
                                      "ms_per_step": 1e3 * e4 / 10,
                                      "live_valuations": live4 * w4.basis.n_scen,
-                                     "nominal_valuations": w4.portfolio.n * w4.basis.n_nodes * w4.basis.n_scen}
+                                     "nominal_valuations": w4.portfolio.n * w4.basis.n_nodes * w4.basis.n_scen,
+                                     "kernel_ms": k4,
+                                     "algorithmic_flops_per_launch": flops4,
+                                     "kernel_tflops": flops4 / (k4 * 1e-3) / 1e12,
+                                     "kernel_frac_fp64_peak": flops4 / (k4 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                                     "launch": {"block_k": ctx.get_option(rr.OPT_LAST_K),
+                                                "block_j": ctx.get_option(rr.OPT_LAST_J),
+                                                "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG)}}
         sec["representative_500k_annuities"] = representative_leg(rr, synth, sync)
         sec["C3_device_generated_scenarios"] = generated_scenarios_leg(rr, synth, sync)
         sec["C4_node_means"] = node_means_leg(rr, synth, sync)

@@ -342,6 +342,9 @@ int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out)
                                    plain longest-first order; -1 = 2 or 1, whichever the autotuner
                                    finds faster (default) */
 #define RR_OPT_LAST_WINDOWS 15  /* read-only: 1 if the last launch took windows per workgroup */
+#define RR_OPT_LAST_TABLES_LDS 16  /* read-only: 1 if the last launch staged the survival tables in
+                                   LDS, 0 if it read them from device memory (bases whose tables
+                                   exceed 64 KiB) */
 int rr_set_option(rr_ctx *ctx, int32_t option, int64_t value);
 int rr_get_option(rr_ctx *ctx, int32_t option, int64_t *value);
 

@@ -21,15 +21,25 @@ OUT_STATES = 4
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (FP64, no fast-math, no contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile liboracle.so with gcc (FP64, no fast-math, no contraction).
+    sanitize: liboracle_san.so instead, with AddressSanitizer and
+    UndefinedBehaviorSanitizer (CPU only; load it with libasan preloaded)."""
+    lib = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra"]
+        if sanitize:
+            cmd += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined"]
+        cmd += ["-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 MAX_STATES = 9          # largest state model of the oracle
@@ -58,11 +68,15 @@ class _Portfolio(ctypes.Structure):
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("ORACLE_LIB", "")   # e.g. the sanitizer build
+        if not path:
+            path = build()
+        lib = ctypes.CDLL(path)
         vp, ci = ctypes.c_void_p, ctypes.c_int
         lib.orc_reserves.argtypes = [vp, vp, ci, ci, ci, ci, ci, vp, vp, vp, vp, ci]
         lib.orc_reserves.restype = ci
+        lib.orc_reserves_reduced.argtypes = [vp, vp, ci, ci, ci, ci, ci, vp, vp, ci]
+        lib.orc_reserves_reduced.restype = ci
         lib.orc_reserve_paths.argtypes = [vp, vp, ci, ci, ci, vp, ci]
         lib.orc_reserve_paths.restype = ci
         lib.orc_reserve_path_summation.argtypes = [vp, vp, ci, ci, ci, ci, vp]
@@ -122,7 +136,12 @@ class _Args:
 
 
 def default_threads() -> int:
-    return int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    """ORACLE_THREADS, else OMP_NUM_THREADS (a machine's CPU share), else every core."""
+    for var in ("ORACLE_THREADS", "OMP_NUM_THREADS"):
+        val = os.environ.get(var, "").strip()
+        if val.isdigit() and int(val) > 0:
+            return int(val)
+    return os.cpu_count() or 1
 
 
 def reserves(basis, pf, node0=0, nnode=None, scen0=0, nscen=None, node_step=12,
@@ -146,6 +165,24 @@ def reserves(basis, pf, node0=0, nnode=None, scen0=0, nscen=None, node_step=12,
     if rc != 0:
         raise ValueError(f"oracle rejected the input (rc={rc})")
     return {"r_all": r_all, "gross": gross, "totals": totals, "gross_totals": gtot}
+
+
+def reserves_reduced(basis, pf, node0=0, nnode=None, scen0=0, nscen=None, node_step=12,
+                     n_threads=None, want_r=True):
+    """The same reserves by the zero-reserve-state-reduced recurrence of each
+    product (see oracle.c, orc_reserves_reduced): r_all [nnode, n, nscen, 4]
+    (None unless want_r) and totals [nnode, nscen]; no gross values."""
+    lib = _load()
+    a = _Args(basis, pf)
+    nnode = basis.v.shape[0] - node0 if nnode is None else nnode
+    nscen = basis.v.shape[1] - scen0 if nscen is None else nscen
+    r_all = np.zeros((nnode, a.n, nscen, OUT_STATES)) if want_r else None
+    totals = np.zeros((nnode, nscen))
+    rc = lib.orc_reserves_reduced(ctypes.byref(a.b), ctypes.byref(a.p), node0, nnode, scen0, nscen,
+                                  node_step, _ptr(r_all), _ptr(totals), n_threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (rc={rc})")
+    return {"r_all": r_all, "totals": totals}
 
 
 def path_offsets(term_m, node=0, node_step=12):

@@ -325,8 +325,9 @@ def loss(p, z, t, quant=True):
     return float(np.mean((np.asarray(y, np.float64) - t) ** 2))
 
 
-def backward(p, z, t, quant=True):
-    """Gradients of the mean squared error with respect to every parameter."""
+def backward(p, z, t, quant=True, keep=False):
+    """Gradients of the mean squared error with respect to every parameter
+    (and, with keep, the forward and backward intermediates as a third value)."""
     if quant:
         q = bf16
         acc = f32
@@ -348,7 +349,64 @@ def backward(p, z, t, quant=True):
     dz1q = q(dz1)
     g["b1"] = acc(d(dz1q).sum(axis=0))
     g["W1"] = acc(d(s["xq"]).T @ d(dz1q))
+    if keep:
+        s.update(y=y, dy=dy, dz2=dz2, dz2q=dz2q, da1=da1, dz1=dz1, dz1q=dz1q)
+        return g, y, s
     return g, y
+
+
+# ---------------------------------------------------------------------------
+# Rounding-error bookkeeping for parity tests of the bfloat16 kernels
+# ---------------------------------------------------------------------------
+U32 = 2.0 ** -24          # unit roundoff of FP32
+
+
+def gamma(n):
+    """gamma_n = n u / (1 - n u), u the FP32 unit roundoff: an n-term FP32
+    sum in any order differs from the exact sum by at most gamma_{n-1} times
+    the sum of the absolute terms (Higham, Accuracy and Stability of
+    Numerical Algorithms, 2002, Sec. 4.2)."""
+    return n * U32 / (1.0 - n * U32)
+
+
+def abs_sums(p, s, n_rows):
+    """Sums of absolute terms of every FP32 accumulation in forward and
+    backward (s = the intermediates of ``backward(..., keep=True)``):
+    z1, z2, y and da1 per row and unit; and, per gradient element, the sum
+    of the absolute terms it adds up (the scale of its accumulation error)."""
+    d = lambda a: np.abs(np.asarray(a, dtype=np.float64))
+    out = {}
+    out["z1"] = d(s["xq"]) @ d(s["W1"]) + d(p["b1"])
+    out["z2"] = d(s["a1"]) @ d(s["W2"]) + d(p["b2"])
+    out["y"] = d(s["a2"]) @ d(s["W3"]) + abs(float(p["b3"]))
+    out["da1"] = d(s["dz2q"]) @ d(s["W2"]).T
+    g = {}
+    g["b3"] = float(np.sum(d(s["dy"])))
+    g["W3"] = d(s["a2"]).T @ d(s["dy"])
+    g["b2"] = d(s["dz2q"]).sum(axis=0)
+    g["W2"] = d(s["a1"]).T @ d(s["dz2q"])
+    g["b1"] = d(s["dz1q"]).sum(axis=0)
+    g["W1"] = d(s["xq"]).T @ d(s["dz1q"])
+    out["grad"] = g
+    return out
+
+
+def bf16_boundary_distance(x):
+    """Distance of each FP32 value to the nearest point where its bfloat16
+    rounding changes (the midpoint between the two neighbouring bfloat16
+    values), as FP64; zeros and values already in bfloat16 are far from it."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    a = np.abs(x)
+    lo_bits = a.view(np.uint32) & np.uint32(0xFFFF0000)
+    lo = lo_bits.view(np.float32).astype(np.float64)
+    hi = (lo_bits + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+    a64 = a.astype(np.float64)
+    d = np.abs(a64 - 0.5 * (lo + hi))
+    # just above a power of two the boundary below lo is closer (smaller units below)
+    has_prev = lo_bits >= np.uint32(0x10000)
+    prev = np.where(has_prev, lo_bits - np.uint32(0x10000), lo_bits).view(np.float32).astype(np.float64)
+    below = np.where(has_prev, a64 - 0.5 * (prev + lo), np.inf)
+    return np.minimum(d, below)
 
 
 def adam(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -294,7 +294,11 @@ static void contract_for(const orc_basis *b, const orc_portfolio *p, int i, int 
                          orc_contract *k)
 {
     orc_contract_of(p->product[i], p->timing[i], p->amount[i], p->premium[i], gross, k);
-    if (p->timing[i] == 2) k->f_ann = b->frac;
+    /* the annuities' payment point; cash-flow tables and uploaded models pay
+     * at the end of the month whatever their timing field says */
+    const int annuity = p->product[i] == O_SL_ANN || p->product[i] == O_JL_ANN ||
+                        p->product[i] == O_REV_ANN || p->product[i] == O_LS_ANN;
+    if (p->timing[i] == 2 && annuity) k->f_ann = b->frac;
     if (p->product[i] == O_MARKOV) {
         int m = p->mk_states;
         const double *c = p->mk_c + (size_t)p->table1[i] * m;
@@ -598,6 +602,222 @@ int orc_reserve_path_summation(const orc_basis *b, const orc_portfolio *p, int i
         for (int j = 0; j < n; ++j) out[(size_t)t * n + j] = r[j];
     }
     return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reduced mode: the recurrence with the zero-reserve states removed         */
+/* (Sec. 3.6.4), written per product from Eq. (3.7).                         */
+/* ------------------------------------------------------------------------ */
+/*
+ * The same reserves as orc_reserves without forming any W: a state whose
+ * reserve stays 0 for the whole term (no cash flow can be reached from it)
+ * is dropped, and each remaining state's row of Eq. (3.7) is written out
+ * with the per-life survival p_l = 1 - q_l of the step.  With s_l = 1 - f q_l
+ * and d_l = f q_l the survival and death over the fraction f of a step
+ * (uniform deaths; s = 1, d = 0 at f = 0 and s = p, d = q at f = 1), and
+ * a = payment x pattern factor, P the premium (paid at f = 0 in the first
+ * state), B the sum assured and primes the values at t + 1:
+ *   one life, 2 states (annuity, pure endowment, cash-flow table):
+ *       r0 = -P + v^f s a + v p r0'                     (boundary SA or 0)
+ *   one life, 3 states (term / endowment assurance):
+ *       r0 = -P + v (q B + p r0')
+ *   two lives, 4 states (binary labels, life 1 the high digit):
+ *       joint life, two-life endowment: r0 = -P + v^f s1 s2 a + v p1 p2 r0'
+ *       reversionary (paid in state 2):  r2 = v^f s2 a + v p2 r2',
+ *                     r0 = -P + v^f d1 s2 a + v (p1 p2 r0' + q1 p2 r2')
+ *       last survivor (states 0, 1, 2): r1 = v^f s1 a + v p1 r1',
+ *                     r2 = v^f s2 a + v p2 r2',
+ *                     r0 = -P + v^f (s1 s2 + s1 d2 + d1 s2) a
+ *                          + v (p1 p2 r0' + p1 q2 r1' + q1 p2 r2')
+ *   two lives, 9 states (ternary labels: alive, died in the step, dead):
+ *       first death:  r0 = -P + v ((1 - p1 p2) B + p1 p2 r0')
+ *       second death: the died-in-step states of one life carry the
+ *                     reserve of its dead state, so with r2 = (alive, dead)
+ *                     and r6 = (dead, alive):
+ *                     r2 = v (q1 B + p1 r2'),  r6 = v (q2 B + p2 r6'),
+ *                     r0 = -P + v (q1 q2 B + p1 p2 r0' + p1 q2 r2' + q1 p2 r6')
+ *   uploaded Markov models: the full m x m step (nothing to drop).
+ * The boundary is the product's (SA in state 0 for the endowments).
+ * Reported state slots follow orc_reserves.  Only accessors (q lookup,
+ * payment factor, contract amounts, validation) are shared with the dense
+ * mode; no transition matrix is formed for the life models.
+ */
+static void reduced_one(const orc_portfolio *p, int i, const orc_contract *k, int S,
+                        const double *vc, const double *q1s, const double *q2s, const double *as,
+                        double *out4)
+{
+    const int prod = p->product[i];
+    const double P = -k->c_prem[0];             /* premium, positive when paid */
+    const double f = k->f_ann;
+    double r0 = k->boundary[0], r1 = 0.0, r2 = 0.0;
+    double B = 0.0;
+    for (int j = 0; j < k->n_states; ++j)
+        if (k->c_ben[j] != 0.0) B = k->c_ben[j];
+    for (int t = S - 1; t >= 0; --t) {
+        const double v = vc[t];
+        const double q1 = q1s[t], q2 = q2s[t];
+        const double p1 = 1.0 - q1, p2 = 1.0 - q2;
+        const double a = as[t];
+        const double vf = (f == 1.0) ? v : (f == 0.0 ? 1.0 : pow(v, f));
+        const double s1 = 1.0 - f * q1, s2 = 1.0 - f * q2, d1 = f * q1, d2 = f * q2;
+        switch (prod) {
+        case O_SL_ANN:
+        case O_CF_TABLE:
+            r0 = -P + vf * s1 * a + v * p1 * r0;
+            break;
+        case O_ENDOW:
+            r0 = -P + v * p1 * r0;
+            break;
+        case O_TERM:
+        case O_ENDOW_ASSUR:
+            r0 = -P + v * (q1 * B + p1 * r0);
+            break;
+        case O_JL_ANN:
+            r0 = -P + vf * s1 * s2 * a + v * p1 * p2 * r0;
+            break;
+        case O_JL_ENDOW:
+            r0 = -P + v * p1 * p2 * r0;
+            break;
+        case O_REV_ANN: {
+            const double n2 = vf * s2 * a + v * p2 * r2;
+            r0 = -P + vf * d1 * s2 * a + v * (p1 * p2 * r0 + q1 * p2 * r2);
+            r2 = n2;
+            break;
+        }
+        case O_LS_ANN: {
+            const double n1 = vf * s1 * a + v * p1 * r1;
+            const double n2 = vf * s2 * a + v * p2 * r2;
+            r0 = -P + vf * (s1 * s2 + s1 * d2 + d1 * s2) * a + v * (p1 * p2 * r0 + p1 * q2 * r1 + q1 * p2 * r2);
+            r1 = n1;
+            r2 = n2;
+            break;
+        }
+        case O_JL_ASSUR1:
+            r0 = -P + v * ((1.0 - p1 * p2) * B + p1 * p2 * r0);
+            break;
+        case O_JL_ASSUR2: {
+            const double n1 = v * (q1 * B + p1 * r1);   /* (alive, dead) */
+            const double n2 = v * (q2 * B + p2 * r2);   /* (dead, alive) */
+            r0 = -P + v * (q1 * q2 * B + p1 * p2 * r0 + p1 * q2 * r1 + q1 * p2 * r2);
+            r1 = n1;
+            r2 = n2;
+            break;
+        }
+        default:
+            break;
+        }
+    }
+    out4[0] = r0;
+    out4[1] = out4[2] = out4[3] = 0.0;
+    if (prod == O_REV_ANN) out4[2] = r2;
+    if (prod == O_LS_ANN) { out4[1] = r1; out4[2] = r2; }
+    if (prod == O_JL_ASSUR2) { out4[1] = r1; out4[2] = r2; }
+}
+
+/* An uploaded Markov model: every state kept, r_j = -P [j = 0] +
+ * v sum_i w_{j,i} (c_i + r_i'), benefits c at the end of the month. */
+static void markov_one(const orc_portfolio *p, int i, const orc_contract *k, int shift, int S,
+                       const double *vc, double *out4)
+{
+    const int m = p->mk_states;
+    const double P = -k->c_prem[0];
+    double r[ORC_MAX_STATES], rn[ORC_MAX_STATES];
+    for (int j = 0; j < m; ++j) r[j] = 0.0;
+    for (int t = S - 1; t >= 0; --t) {
+        const double v = vc[t];
+        const double *w = p->mk_w + (((size_t)p->table1[i] * p->mk_ages + p->age1[i] + shift + t) * m) * m;
+        for (int j = 0; j < m; ++j) {
+            double acc = 0.0;
+            for (int x = 0; x < m; ++x) acc += w[j * m + x] * (k->c_ann[x] + r[x]);
+            rn[j] = v * acc;
+        }
+        rn[0] -= P;
+        for (int j = 0; j < m; ++j) r[j] = rn[j];
+    }
+    for (int j = 0; j < ORC_OUT_STATES; ++j) out4[j] = j < m ? r[j] : 0.0;
+}
+
+/*
+ * orc_reserves in the reduced mode: r_all [nnode][n][nscen][4] (or NULL) and
+ * totals [nnode][nscen] (or NULL), no gross values.  OpenMP over policies
+ * (dynamic schedule); per policy the death probabilities of each step are
+ * looked up once and shared by the scenarios.  Returns 0, -1 on invalid
+ * input, -2 without memory.
+ */
+int orc_reserves_reduced(const orc_basis *b, const orc_portfolio *p, int node0, int nnode,
+                         int scen0, int nscen, int node_step, double *r_all, double *totals,
+                         int n_threads)
+{
+    if (validate(b, p)) return -1;
+    if (node0 < 0 || nnode < 0 || node0 + nnode > b->n_nodes) return -1;
+    if (scen0 < 0 || nscen < 0 || scen0 + nscen > b->n_scen) return -1;
+    const int n = p->n;
+    double *r0s = (double *)calloc((size_t)nnode * n * nscen + 1, sizeof(double));
+    if (!r0s) return -2;
+    int bad = 0;
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel num_threads(n_threads)
+    {
+        double *q1s = (double *)malloc(sizeof(double) * (size_t)(b->n_steps + 1));
+        double *q2s = (double *)malloc(sizeof(double) * (size_t)(b->n_steps + 1));
+        double *as = (double *)malloc(sizeof(double) * (size_t)(b->n_steps + 1));
+        if (!q1s || !q2s || !as) {
+#pragma omp atomic write
+            bad = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < n; ++i) {
+            if (!q1s || !q2s || !as) continue;
+            orc_contract k;
+            contract_for(b, p, i, 0, &k);
+            double pay = 0.0;   /* the annuity (or table) stream's amount, one state at a time */
+            for (int j = 0; j < k.n_states; ++j)
+                if (k.c_ann[j] != 0.0) pay = k.c_ann[j];
+            for (int a = 0; a < nnode; ++a) {
+                const int node = node0 + a;
+                const int shift = node * node_step;
+                const int S = p->term[i] - shift;
+                const double m = b->shock ? b->shock[node] : 1.0;
+                /* per policy and node, as the paper's forward loop obtains c_t
+                 * and the transition probabilities before the backward loop */
+                if (S > 0 && p->product[i] != O_MARKOV)
+                    for (int t = 0; t < S; ++t) {
+                        double q[2];
+                        step_q(b, p, i, shift, m, t, q);
+                        q1s[t] = q[0];
+                        q2s[t] = q[1];
+                        as[t] = pay != 0.0
+                                    ? pay * payment_factor(p, i, shift + t + (k.f_ann == 1.0 ? 1 : 0), &k)
+                                    : 0.0;
+                    }
+                for (int s = 0; s < nscen; ++s) {
+                    const size_t o = ((size_t)a * n + i) * nscen + s;
+                    double r4[ORC_OUT_STATES] = {0.0, 0.0, 0.0, 0.0};
+                    if (S > 0) {
+                        const double *vc = b->v + ((size_t)node * b->n_scen + (scen0 + s)) * b->n_steps;
+                        if (p->product[i] == O_MARKOV) markov_one(p, i, &k, shift, S, vc, r4);
+                        else reduced_one(p, i, &k, S, vc, q1s, q2s, as, r4);
+                    }
+                    r0s[o] = r4[0];
+                    if (r_all)
+                        for (int j = 0; j < ORC_OUT_STATES; ++j) r_all[o * ORC_OUT_STATES + j] = r4[j];
+                }
+            }
+        }
+        free(q1s);
+        free(q2s);
+        free(as);
+    }
+    if (bad) { free(r0s); return -2; }
+    if (totals)
+        for (int a = 0; a < nnode; ++a)
+            for (int s = 0; s < nscen; ++s) {
+                neumaier tr = {0, 0};
+                for (int i = 0; i < n; ++i) nm_add(&tr, r0s[((size_t)a * n + i) * nscen + s]);
+                totals[(size_t)a * nscen + s] = tr.s + tr.c;
+            }
+    free(r0s);
+    return 0;
 }
 
 /* Number of states of a product's model (for callers sizing buffers). */

@@ -42,6 +42,7 @@ OUT_R0, OUT_TOTALS, OUT_PATH, OUT_ALL_STATES, OUT_STATS = 1, 2, 4, 8, 16
 OPT_BLOCK_K, OPT_WG_PER_CU, OPT_USE_GRAPH, OPT_KERNEL_TIMING, OPT_XCD_QUEUES = 1, 2, 3, 4, 5
 OPT_LAST_K, OPT_LAST_WG, OPT_BLOCK_J, OPT_LAST_J, OPT_TERM_BUCKET = 6, 7, 8, 9, 10
 OPT_CURVE_RING, OPT_LAST_RING, OPT_LANE_SPREAD, OPT_CURVE_SHARE, OPT_LAST_WINDOWS = 11, 12, 13, 14, 15
+OPT_LAST_TABLES_LDS = 16
 
 # Every symbol include/rr.h declares.
 EXPORTS = (

@@ -52,6 +52,11 @@ struct Plan {
     int n_queues = 1;
     DevBuf<Item> items;
     DevBuf<int> qbeg;
+    // Work lists and queue counters in memory the plan does not own; used
+    // instead of items/qbeg and the context's counters when set.
+    const Item *items_ext = nullptr;
+    const int *qbeg_ext = nullptr;
+    int *counters_ext = nullptr;
 };
 
 struct PlanKey {
@@ -150,6 +155,8 @@ struct rr_ctx {
     DevBuf<double> mk_w;                  // [model][mk_ages][4][4]
     DevBuf<Tile> tiles;
     int gen = 0;                          // bumps on every upload
+    long long curve_gen = 0;              // bumps whenever the curve values change (uploads
+                                          // and in-place regeneration)
 
     // run resources
     DevBuf<int> counters;
@@ -167,7 +174,7 @@ struct rr_ctx {
     int opt_lane_spread = 1;              // deal tile lanes over LDS banks (next upload)
     int opt_curve_share = -1;             // 0: plain queues, 1: dealt windows, 2: windows per
                                           // workgroup, -1: 1 or 2, whichever the autotuner finds faster
-    int last_k = 0, last_j = 0, last_wg = 0, last_ring = 0, last_win = 0;   // configuration of the last recurrence launch
+    int last_k = 0, last_j = 0, last_wg = 0, last_ring = 0, last_win = 0, last_qlds = 0;   // configuration of the last recurrence launch
 
     // timing
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;

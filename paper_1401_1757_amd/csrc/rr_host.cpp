@@ -426,6 +426,7 @@ extern "C" int rr_get_option(rr_ctx *c, int32_t option, int64_t *value)
     case RR_OPT_LANE_SPREAD: *value = c->opt_lane_spread; return RR_OK;
     case RR_OPT_CURVE_SHARE: *value = c->opt_curve_share; return RR_OK;
     case RR_OPT_LAST_WINDOWS: *value = c->last_win; return RR_OK;
+    case RR_OPT_LAST_TABLES_LDS: *value = c->last_qlds; return RR_OK;
     default: return fail(c, RR_EINVAL, "unknown option %d", option);
     }
 }
@@ -585,6 +586,7 @@ static int install_basis(rr_ctx *c, const rr_basis *b, std::vector<double> &q,
     if ((rc = stage_tables(c))) return rc;
     c->has_basis = true;
     ++c->gen;
+    ++c->curve_gen;
     return RR_OK;
 }
 
@@ -643,6 +645,7 @@ extern "C" int rr_curves_generate_vasicek(rr_ctx *c, const rr_vasicek *vs)
     std::vector<double> r0;
     int rc;
     if ((rc = vasicek_params(c, vs, c->n_nodes, c->n_scen, c->n_steps, c->scen_pad, &P, &r0))) return rc;
+    ++c->curve_gen;   // cached per-scenario decisions (the surrogate's range flags) are stale
     return enqueue_vasicek(c, P, r0, c->v.p, 1, nullptr);
 }
 
@@ -1117,6 +1120,87 @@ extern "C" int rr_path_size(rr_ctx *c, int32_t node, int32_t node_step_m, int64_
 // ---------------------------------------------------------------------------
 // Planner: work items and per-XCD queues, longest first
 // ---------------------------------------------------------------------------
+// Work items of a run (the host side of a plan): up to J consecutive tiles
+// of one scalar model (one tile for the vector models) x a block of K
+// scenarios x a node, dealt to the work queues, longest first.
+static void plan_lists(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, int queues,
+                       std::vector<Item> &items, std::vector<int> &qbeg)
+{
+    const int K = cfg.K, J = cfg.J;
+    const int nsb = (run->scen_count + K - 1) / K;
+    struct W { long long cost; Item item; };
+    std::vector<std::vector<W>> qs(queues);
+    // Items: up to J consecutive tiles of one scalar model (one tile for the
+    // vector models) x a block of K scenarios x a node.
+    std::vector<std::pair<int, int>> groups;   // (first tile, count)
+    for (int t = 0; t < c->n_tiles;) {
+        const int kind = c->tiles_host[t].kind;
+        const int flow = c->tiles_host[t].flow;
+        const int jmax = ((kind == KIND_SINGLE || kind == KIND_JOINT) && flow == FLOW_LEVEL) ? J : 1;
+        int count = 1;
+        while (count < jmax && t + count < c->n_tiles && c->tiles_host[t + count].kind == kind &&
+               c->tiles_host[t + count].flow == flow)
+            ++count;
+        groups.push_back({t, count});
+        t += count;
+    }
+    auto item_cost = [&](int first, int count, int shift) -> long long {
+        const Tile &T = c->tiles_host[first];
+        int smax = T.smax;
+        for (int j = 1; j < count; ++j) smax = std::max(smax, c->tiles_host[first + j].smax);
+        const long long steps = std::max(smax - shift, 0);
+        return steps * count * (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind) + (T.flow ? 16 : 0)) +
+               64;
+    };
+    for (int nr = 0; nr < run->node_count; ++nr) {
+        const int shift = (run->node_begin + nr) * run->node_step_m;
+        for (const auto &g : groups) {
+            const long long cost = item_cost(g.first, g.second, shift);
+            for (int b = 0; b < nsb; ++b) {
+                const int qid = queues > 1 ? (int)(((long long)nr * nsb + b) % queues) : 0;
+                qs[qid].push_back({cost, Item{nr, g.first, b * K, g.second}});
+            }
+        }
+    }
+    items.clear();
+    qbeg.assign(queues + 1, 0);
+    const int share = c->opt_curve_share != 0 ? WG_THREADS / 64 : 1;
+    for (int qi = 0; qi < queues; ++qi) {
+        // Longest first.  An item's curves are read with scalar loads
+        // through the scalar cache that neighbouring CUs share, so the
+        // queue is then dealt in windows of `share` tile groups of about
+        // the same length (one per wavefront of a workgroup, taken at
+        // about the same time): within a window the items are ordered by
+        // scenario block, so wavefronts that start together walk the same
+        // curve lines and one cache miss serves them all.
+        std::stable_sort(qs[qi].begin(), qs[qi].end(), [](const W &a, const W &b) {
+            if (a.cost != b.cost) return a.cost > b.cost;
+            return a.item.tile < b.item.tile;
+        });
+        qbeg[qi] = (int)items.size();
+        size_t u0 = 0;
+        while (u0 < qs[qi].size()) {
+            // a window: the items of `share` consecutive (node, tile group) units
+            size_t u1 = u0;
+            int units = 0;
+            while (u1 < qs[qi].size() && units < share) {
+                const Item &h = qs[qi][u1].item;
+                while (u1 < qs[qi].size() && qs[qi][u1].item.tile == h.tile &&
+                       qs[qi][u1].item.node_rel == h.node_rel)
+                    ++u1;
+                ++units;
+            }
+            std::stable_sort(qs[qi].begin() + u0, qs[qi].begin() + u1, [](const W &a, const W &b) {
+                if (a.item.node_rel != b.item.node_rel) return a.item.node_rel < b.item.node_rel;
+                return a.item.sblock < b.item.sblock;
+            });
+            u0 = u1;
+        }
+        for (auto &w : qs[qi]) items.push_back(w.item);
+    }
+    qbeg[queues] = (int)items.size();
+}
+
 static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan **out)
 {
     const int queues = c->opt_xcd ? MAX_QUEUES : 1;
@@ -1127,78 +1211,9 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
     Plan *pl;
     if (it == c->plans.end()) {
         std::unique_ptr<Plan> np(new Plan());
-        const int nsb = (run->scen_count + K - 1) / K;
-        struct W { long long cost; Item item; };
-        std::vector<std::vector<W>> qs(queues);
-        // Items: up to J consecutive tiles of one scalar model (one tile for the
-        // vector models) x a block of K scenarios x a node.
-        std::vector<std::pair<int, int>> groups;   // (first tile, count)
-        for (int t = 0; t < c->n_tiles;) {
-            const int kind = c->tiles_host[t].kind;
-            const int flow = c->tiles_host[t].flow;
-            const int jmax = ((kind == KIND_SINGLE || kind == KIND_JOINT) && flow == FLOW_LEVEL) ? J : 1;
-            int count = 1;
-            while (count < jmax && t + count < c->n_tiles && c->tiles_host[t + count].kind == kind &&
-                   c->tiles_host[t + count].flow == flow)
-                ++count;
-            groups.push_back({t, count});
-            t += count;
-        }
-        auto item_cost = [&](int first, int count, int shift) -> long long {
-            const Tile &T = c->tiles_host[first];
-            int smax = T.smax;
-            for (int j = 1; j < count; ++j) smax = std::max(smax, c->tiles_host[first + j].smax);
-            const long long steps = std::max(smax - shift, 0);
-            return steps * count * (ops_of_kind(T.kind) * K + overhead_of_kind(T.kind) + (T.flow ? 16 : 0)) +
-                   64;
-        };
-        for (int nr = 0; nr < run->node_count; ++nr) {
-            const int shift = (run->node_begin + nr) * run->node_step_m;
-            for (const auto &g : groups) {
-                const long long cost = item_cost(g.first, g.second, shift);
-                for (int b = 0; b < nsb; ++b) {
-                    const int qid = queues > 1 ? (int)(((long long)nr * nsb + b) % queues) : 0;
-                    qs[qid].push_back({cost, Item{nr, g.first, b * K, g.second}});
-                }
-            }
-        }
         std::vector<Item> items;
-        std::vector<int> qbeg(queues + 1, 0);
-        const int share = c->opt_curve_share != 0 ? WG_THREADS / 64 : 1;
-        for (int qi = 0; qi < queues; ++qi) {
-            // Longest first.  An item's curves are read with scalar loads
-            // through the scalar cache that neighbouring CUs share, so the
-            // queue is then dealt in windows of `share` tile groups of about
-            // the same length (one per wavefront of a workgroup, taken at
-            // about the same time): within a window the items are ordered by
-            // scenario block, so wavefronts that start together walk the same
-            // curve lines and one cache miss serves them all.
-            std::stable_sort(qs[qi].begin(), qs[qi].end(), [](const W &a, const W &b) {
-                if (a.cost != b.cost) return a.cost > b.cost;
-                return a.item.tile < b.item.tile;
-            });
-            qbeg[qi] = (int)items.size();
-            size_t u0 = 0;
-            while (u0 < qs[qi].size()) {
-                // a window: the items of `share` consecutive (node, tile group) units
-                size_t u1 = u0;
-                int units = 0;
-                while (u1 < qs[qi].size() && units < share) {
-                    const Item &h = qs[qi][u1].item;
-                    while (u1 < qs[qi].size() && qs[qi][u1].item.tile == h.tile &&
-                           qs[qi][u1].item.node_rel == h.node_rel)
-                        ++u1;
-                    ++units;
-                }
-                std::stable_sort(qs[qi].begin() + u0, qs[qi].begin() + u1, [](const W &a, const W &b) {
-                    if (a.item.node_rel != b.item.node_rel) return a.item.node_rel < b.item.node_rel;
-                    return a.item.sblock < b.item.sblock;
-                });
-                u0 = u1;
-            }
-            for (auto &w : qs[qi]) items.push_back(w.item);
-        }
-        qbeg[queues] = (int)items.size();
+        std::vector<int> qbeg;
+        plan_lists(c, run, cfg, queues, items, qbeg);
         np->K = K;
         np->J = J;
         np->n_items = (int)items.size();
@@ -1220,6 +1235,14 @@ static int build_plan(rr_ctx *c, const rr_run *run, const LaunchCfg &cfg, Plan *
     return RR_OK;
 }
 
+// Whether a workgroup stages the survival tables in LDS (else it reads them
+// from device memory).
+static bool tables_in_lds(const rr_ctx *c)
+{
+    const size_t nq = (size_t)c->n_tables * c->n_ages_stage;
+    return nq <= (size_t)max_lds_tables_doubles() && nq * 8 <= c->lds_per_block;
+}
+
 static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out, const Plan *pl,
                              double *partial)
 {
@@ -1228,7 +1251,7 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.q = c->q_stage.p;
     P.n_ages_stage = c->n_ages_stage;
     P.n_q = c->n_tables * c->n_ages_stage;
-    P.q_in_lds = (P.n_q <= max_lds_tables_doubles() && (size_t)P.n_q * 8 <= c->lds_per_block) ? 1 : 0;
+    P.q_in_lds = tables_in_lds(c) ? 1 : 0;
     P.ring_off = P.q_in_lds ? (P.n_q + 1) / 2 * 2 : 0;   // 16-byte aligned rings after the tables
     P.win = pl->win;
     P.v = c->v_override ? c->v_override : c->v.p;
@@ -1256,9 +1279,9 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.n_tiles = c->n_tiles;
     P.has_vector = 0;
     for (const Tile &T : c->tiles_host) P.has_vector |= (T.kind == KIND_REV || T.kind == KIND_LAST);
-    P.items = pl->items.p;
-    P.qbeg = pl->qbeg.p;
-    P.counters = c->counters.p;
+    P.items = pl->items_ext ? pl->items_ext : pl->items.p;
+    P.qbeg = pl->qbeg_ext ? pl->qbeg_ext : pl->qbeg.p;
+    P.counters = pl->counters_ext ? pl->counters_ext : c->counters.p;
     P.n_queues = pl->n_queues;
     P.node_begin = run->node_begin;
     P.scen_begin = run->scen_begin;
@@ -1290,8 +1313,7 @@ static bool ring_ok(const rr_ctx *c, int K, int J)
     for (const Tile &T : c->tiles_host)
         if (T.kind == KIND_REV || T.kind == KIND_LAST) return false;
     const size_t nq = (size_t)c->n_tables * c->n_ages_stage;
-    const bool q_lds = nq <= (size_t)max_lds_tables_doubles() && nq * 8 <= c->lds_per_block;
-    const size_t d = (q_lds ? (nq + 1) / 2 * 2 : 0) + (size_t)(WG_THREADS / 64) * ring_doubles_per_wave(K);
+    const size_t d = (tables_in_lds(c) ? (nq + 1) / 2 * 2 : 0) + (size_t)(WG_THREADS / 64) * ring_doubles_per_wave(K);
     return d * sizeof(double) <= c->lds_per_block;
 }
 
@@ -1464,9 +1486,10 @@ static int choose_config(rr_ctx *c, const rr_run *run, const rr_outputs *out, do
     return RR_OK;
 }
 
-extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outputs *out)
+// Checks shared by the recurrence entry points: state, ranges, output mask
+// and buffers (path capacity included).
+static int check_run_outputs(rr_ctx *c, const rr_run *run, const rr_outputs *out)
 {
-    if (!c) return RR_EINVAL;
     if (!run || !out) return fail(c, RR_EINVAL, "run and outputs must not be NULL");
     if (!c->has_basis || !c->has_pf) return fail(c, RR_ESTATE, "upload a basis and a portfolio first");
     HIPCHK(c, hipSetDevice(c->device));
@@ -1500,6 +1523,17 @@ extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outp
         if (out->path_cap < need)
             return fail(c, RR_ERANGE, "path_cap %lld < %lld doubles needed", (long long)out->path_cap,
                         (long long)need);
+    }
+    return RR_OK;
+}
+
+extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outputs *out)
+{
+    if (!c) return RR_EINVAL;
+    int rc0 = check_run_outputs(c, run, out);
+    if (rc0) return rc0;
+    const uint32_t mask = run->out_mask;
+    if (mask & RR_OUT_PATH) {
         if (c->path_off_node != run->node_begin || c->path_off_step != run->node_step_m ||
             c->path_off_gen != c->gen) {
             std::vector<long long> off((size_t)c->n_user + 1, 0);
@@ -1547,6 +1581,7 @@ extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outp
     c->last_wg = cfg.wg;
     c->last_ring = cfg.ring;
     c->last_win = cfg.win;
+    c->last_qlds = tables_in_lds(c) ? 1 : 0;
 
     if (c->opt_graph && !c->opt_timing) {
         std::vector<uint64_t> key = {

@@ -1016,7 +1016,9 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
     if ((rc = compute_features(c, S, run, true, false, false))) return rc;
 
     // Fallback plan: work items of the exact kernel covering every row outside the box.
-    const std::vector<uint64_t> key = {(uint64_t)c->gen, (uint64_t)S->version,
+    // The scenario flags depend on the curve values, so a regeneration of the
+    // curves in place (same sizes, same gen) invalidates the plan too.
+    const std::vector<uint64_t> key = {(uint64_t)c->gen, (uint64_t)c->curve_gen, (uint64_t)S->version,
                                        (uint64_t)run->node_begin, (uint64_t)run->node_count,
                                        (uint64_t)run->scen_begin, (uint64_t)run->scen_count,
                                        (uint64_t)run->node_step_m};
@@ -1067,6 +1069,9 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
         if ((rc = run_items(c, run, S->fb_tiles, kFbK, exact, 0, fresh))) return rc;
         if ((rc = run_items(c, run, S->fb_scens, 1, exact, 1, fresh))) return rc;
     }
+    if (S->fb_rows > 0 && !exact)   // k_infer would read exact rows nobody computed
+        return fail(c, RR_EDEVICE, "surrogate fallback plan has %lld rows but no work items",
+                    (long long)S->fb_rows);
     const int n_chunks = (n + kChunk - 1) / kChunk;
     HIPCHK(c, S->partial.alloc((size_t)run->node_count * n_chunks * run->scen_count));
     M::Infer f{};

@@ -212,3 +212,60 @@ def test_samples_come_from_exact_reserves():
             assert abs(ts[sel].mean()) < 1e-6 and abs(ts[sel].std() - 1) < 1e-6
     assert mlp.in_range(X, lo, hi).all()
     assert not mlp.in_range(X[:1] + (hi - lo + 1), lo, hi).any()
+
+
+def test_bf16_boundary_distance_by_brute_force():
+    """The distance to the rounding boundary: moving a value by 90 % of it
+    either way keeps its bfloat16 rounding, moving by 101 % towards the
+    boundary changes it; exact midpoints are at distance 0 and bfloat16
+    values at half a unit."""
+    rng = np.random.default_rng(5)
+    x = (rng.normal(0, 1, 2000) * 10.0 ** rng.integers(-8, 8, 2000)).astype(np.float32)
+    d = mlp.bf16_boundary_distance(x)
+    # moves that FP32 represents without landing on a boundary
+    f32_ulp = np.spacing(np.abs(x)).astype(np.float64)
+    far = d > 16 * f32_ulp
+    assert far.mean() > 0.95
+    for sgn in (-1.0, 1.0):
+        moved = (x.astype(np.float64) + sgn * 0.9 * d).astype(np.float32)
+        assert np.array_equal(mlp.bf16(moved)[far], mlp.bf16(x)[far])
+    up = (x.astype(np.float64) + 1.01 * d).astype(np.float32)
+    dn = (x.astype(np.float64) - 1.01 * d).astype(np.float32)
+    changed = (mlp.bf16(up) != mlp.bf16(x)) | (mlp.bf16(dn) != mlp.bf16(x))
+    assert np.all(changed[far])
+    b = mlp.bf16(x)
+    ulp = (np.abs((b.view(np.uint32) + np.uint32(0x10000)).view(np.float32).astype(np.float64))
+           - np.abs(b.astype(np.float64)))
+    # a bfloat16 value is half a unit from the boundary above it, and half
+    # a unit below it from the one below (a quarter at powers of two)
+    db = mlp.bf16_boundary_distance(b)
+    pow2 = (b.view(np.uint32) & np.uint32(0x007F0000)) == 0
+    np.testing.assert_array_equal(db[~pow2], 0.5 * ulp[~pow2])
+    np.testing.assert_array_equal(db[pow2], 0.25 * ulp[pow2])
+    mid = (np.abs(b).astype(np.float64) + 0.5 * ulp).astype(np.float32)
+    assert np.all(mlp.bf16_boundary_distance(mid) == 0.0)
+
+
+def test_abs_sums_equal_the_sums_for_nonnegative_terms():
+    """With non-negative inputs, weights and gradient factors every term is
+    non-negative, so each sum of absolute terms is the sum itself."""
+    rng = np.random.default_rng(6)
+    p = {k: np.abs(v) for k, v in synth.random_mlp_params(rng).items()}
+    p["b3"] = np.float32(abs(p["b3"]))
+    z = np.zeros((40, mlp.K_IN), np.float32)
+    z[:, :mlp.N_FEAT] = np.abs(rng.normal(0, 1, (40, mlp.N_FEAT)))
+    t = np.full(40, -100.0, np.float32)          # y > t: dy > 0
+    g, y, s = mlp.backward(p, z, t, quant=False, keep=True)
+    S = mlp.abs_sums(p, s, 40)
+    np.testing.assert_allclose(S["z1"], s["z1"], rtol=1e-12)
+    np.testing.assert_allclose(S["z2"], s["z2"], rtol=1e-12)
+    np.testing.assert_allclose(S["y"], y, rtol=1e-12)
+    assert np.all(np.asarray(s["dy"]) > 0)
+    for k in ("W3", "b3"):
+        np.testing.assert_allclose(S["grad"][k], g[k], rtol=1e-12)
+    # GELU' is positive for positive pre-activations, so dz2, dz1 and all
+    # remaining gradients are sums of non-negative terms too
+    assert np.all(np.asarray(s["z1"]) > 0) and np.all(np.asarray(s["z2"]) > 0)
+    for k in ("W2", "b2", "W1", "b1"):
+        np.testing.assert_allclose(S["grad"][k], g[k], rtol=1e-12)
+    assert mlp.gamma(1) > mlp.U32 and abs(mlp.gamma(1000) / (1000 * mlp.U32) - 1.0) < 1e-4

@@ -806,3 +806,99 @@ def test_fractional_recurrence_equals_summation(seed):
             scale = np.abs(summ).max() + 1e-300
             np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=0,
                                        atol=1e-12 * scale)
+
+
+# --------------------------------------------------------------------------
+# The gross value G (the scale of every parity tolerance)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("S", [1, 13, 240])
+def test_gross_closed_forms_at_zero_mortality(S):
+    """q = 0: a premium-paying pure endowment or endowment assurance has
+    G = SA v^S + P a-due_S and a term assurance G = P a-due_S, with
+    a-due_S = (1 - v^S) / (1 - v) the annuity-certain due."""
+    v = 0.997
+    SA, P = 1000.0, 3.0
+    pf = make_pf([ENDOW, ENDOW_ASSUR, TERM, JL_ENDOW, JL_ASSUR1, JL_ASSUR2], 300, S,
+                 amount=SA, premium=P, age2=400)
+    b = basis(np.zeros(N_AGES), np.full(S, v))
+    g = oracle.reserves(b, pf)["gross"][0, :, 0]
+    due = (1.0 - v ** S) / (1.0 - v)
+    expect = [SA * v ** S + P * due, SA * v ** S + P * due, P * due, SA * v ** S + P * due,
+              P * due, P * due]
+    np.testing.assert_allclose(g, expect, rtol=1e-13)
+
+
+def test_gross_is_reserve_plus_twice_the_premium_value():
+    """For every product G = PV(benefits) + PV(premiums) while the reserve is
+    PV(benefits) - PV(premiums), and -PV(premiums) is the reserve of the same
+    policy with amount 0: G = r - 2 r(amount 0), random mortality and
+    curves, non-negative cash-flow tables and Markov benefits."""
+    rng = np.random.default_rng(31)
+    w = synth.random_small(rng, n=400, n_steps=60, n_scen=3, n_nodes=2, shock=True,
+                           products=tuple(range(7)) + (JL_ENDOW, JL_ASSUR1, JL_ASSUR2))
+    pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=0.1, n_rows=3)
+    pf.cf = np.abs(pf.cf)
+    W, c = synth.phi_models(w.basis.q.shape[1])
+    pf = synth.with_markov_policies(rng, pf, (W, c), frac=0.1)
+    assert set(np.unique(pf.product)) == set(range(12))
+    full = oracle.reserves(w.basis, pf, node_step=7)
+    zero = pf.subset(np.arange(pf.n))
+    zero.amount = np.zeros(pf.n)
+    prem = oracle.reserves(w.basis, zero, node_step=7, want_gross=False)["r_all"][..., 0]
+    expect = full["r_all"][..., 0] - 2.0 * prem
+    scale = np.maximum(full["gross"], 1e-300)
+    assert np.max(np.abs(full["gross"] - expect) / scale) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# The reduced mode (zero-reserve states removed) against the dense mode
+# --------------------------------------------------------------------------
+def reduced_vs_dense(w, node_step):
+    b, pf = w.basis, w.portfolio
+    dense = oracle.reserves(b, pf, node_step=node_step)
+    red = oracle.reserves_reduced(b, pf, node_step=node_step)
+    scale = np.maximum(np.abs(dense["r_all"]), dense["gross"][..., None])
+    err = np.abs(red["r_all"] - dense["r_all"]) / np.maximum(scale, 1e-300)
+    assert err.max() <= 1e-13, (err.max(), np.unravel_index(np.argmax(err), err.shape))
+    terr = np.abs(red["totals"] - dense["totals"]) / np.maximum(dense["gross_totals"], 1e-300)
+    assert terr.max() <= 1e-13
+
+
+@pytest.mark.parametrize("product", list(range(11)))
+def test_reduced_mode_equals_dense_each_product(product):
+    rng = np.random.default_rng(800 + product)
+    w = synth.random_small(rng, n=80, n_steps=150, n_scen=3, n_nodes=2, shock=True,
+                           products=(product,))
+    if product == CF_TABLE:
+        pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=1.0, n_rows=5)
+        w = synth.Workload("cf", w.basis, pf)
+    reduced_vs_dense(w, 12)
+
+
+def test_reduced_mode_equals_dense_everything_together():
+    """Every product with payment patterns, cash-flow tables, Markov models
+    (permanent health and random 4-state), advance, arrears and fractional
+    timing, three nodes 7 months apart with shocks."""
+    rng = np.random.default_rng(830)
+    w = synth.random_small(rng, n=600, n_steps=90, n_scen=4, n_nodes=3, shock=True,
+                           products=tuple(range(7)) + (JL_ENDOW, JL_ASSUR1, JL_ASSUR2))
+    pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=0.1, n_rows=4)
+    pf = synth.with_payment_patterns(rng, pf, 0.4, 0.3)
+    ann = np.isin(pf.product, (SL_ANN, JL_ANN, REV_ANN, LS_ANN))
+    pf.timing = np.where(ann & (rng.uniform(size=pf.n) < 0.3), FRACTIONAL, pf.timing).astype(np.int32)
+    n_ages = w.basis.q.shape[1]
+    raw = rng.uniform(0.0, 1.0, (2, n_ages, 4, 4))
+    raw[:, :, 3, :] = [0.0, 0.0, 0.0, 1.0]
+    W = raw / raw.sum(axis=3, keepdims=True)
+    pf = synth.with_markov_policies(rng, pf, (W, rng.uniform(-1.0, 2.0, (2, 4))), frac=0.1)
+    w.basis.frac = 0.4
+    w = synth.Workload("all", w.basis, pf)
+    assert set(np.unique(pf.product)) == set(range(12))
+    reduced_vs_dense(w, 7)
+
+
+def test_reduced_mode_on_the_nested_workload_sample():
+    """The benchmark's CPU workload (mixed products, Vasicek curves): a
+    sample of policies and scenarios, reduced = dense."""
+    w = synth.config_c3(n=300, n_scen=6)
+    reduced_vs_dense(w, 12)
