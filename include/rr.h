@@ -73,7 +73,7 @@ typedef struct rr_ctx rr_ctx;
 #define RR_ENDOW_ASSUR  6  /* endowment assurance: term assurance with r_S = (SA, 0, 0) */
 #define RR_CF_TABLE     7  /* one life, 2-state model; pays amount x cf[cf_row][T] at the end of
                               month T (months since node 0) if alive, level premium in advance,
-                              r_S = 0 (Sec. 4.4: c_t holds the nominal amounts) */
+                              r_S = 0 (Sec. 4.6: c_t holds the nominal amounts) */
 #define RR_JL_ENDOW     8  /* two-life pure endowment: SA at the end of the term if both lives are
                               alive, r_S = (SA, 0, 0, 0) (Sec. 4.2.2) */
 #define RR_JL_ASSUR1    9  /* two-life term assurance, SA at the end of the month of the first
@@ -88,9 +88,18 @@ typedef struct rr_ctx rr_ctx;
                               model, age1_m indexes its tables): starts in state 0, pays
                               amount x benefit[state] at the end of each month that ends in
                               that state, premium in advance while in state 0, r_S = 0
-                              (Sec. 4.7: reversible models, W not upper triangular).  The
+                              (Sec. 4.5: reversible models, W not upper triangular).  The
                               node shock does not apply to uploaded models.  With
                               RR_OUT_ALL_STATES slot j is the reserve of state j. */
+
+#define RR_JL3_ANN     12  /* joint-life annuity on three lives, paid while all three are alive:
+                              the 2^3 = 8-state Kronecker model of Sec. 4.3, c = e_0 (binary labels,
+                              life 1 the high digit, 1 = dead); needs age3_m and table3 */
+#define RR_LS3_ANN     13  /* last-survivor annuity on three lives, paid while any is alive,
+                              c = (1,1,1,1,1,1,1,0) (Sec. 4.3).  Three-life annuities are level
+                              (no payment pattern) and paid in advance or in arrears; with
+                              RR_OUT_ALL_STATES slot j is the reserve of state j (0: all alive,
+                              1: life 3 dead, 2: life 2 dead, 3: lives 2 and 3 dead). */
 
 #define RR_ADVANCE 0       /* annuity paid at the start of each month (f = 0) */
 #define RR_ARREARS 1       /* annuity paid at the end of each month (f = 1) */
@@ -180,6 +189,10 @@ typedef struct {
     const double *cf;
     int32_t cf_n_rows;
     int32_t cf_len;
+    /* Life 3 of RR_JL3_ANN / RR_LS3_ANN policies (NULL when there are none):
+     * attained age at node 0 in months and mortality table. */
+    const int32_t *age3_m;
+    const int32_t *table3;
 } rr_portfolio;
 
 /* One valuation run over nodes [node_begin, node_begin + node_count) and
@@ -282,13 +295,14 @@ int rr_vasicek_curves(rr_ctx *ctx, const rr_vasicek *vs, int32_t n_nodes, int32_
                       int32_t n_steps, double *v, double *r);
 
 /*
- * Markov models for RR_MARKOV policies (Sec. 4.7), copied to the device:
+ * Markov models for RR_MARKOV policies (Sec. 4.5), copied to the device:
  *   w[n_models][n_ages][n_states][n_states]  one-month transition probabilities
  *       by attained age in months; row i = state at the start of the month;
  *       entries in [0, 1], each row summing to 1 within 1e-12;
  *   benefit[n_models][n_states]  paid per unit amount at the end of a month
  *       that ends in the state (finite).
- * 2 <= n_states <= 4, n_ages >= 2, n_models >= 1.  Replaces earlier models;
+ * 2 <= n_states <= 9 (e.g. the 9-state two-life model of Sec. 4.2.3 by the
+ * attained age of life 1), n_ages >= 2, n_models >= 1.  Replaces earlier models;
  * a loaded portfolio that the new models do not cover is dropped.
  */
 typedef struct {

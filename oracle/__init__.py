@@ -62,7 +62,8 @@ class _Portfolio(ctypes.Structure):
                 ("annual", ctypes.c_void_p), ("cf_row", ctypes.c_void_p),
                 ("cf", ctypes.c_void_p), ("n_cf_rows", ctypes.c_int), ("cf_len", ctypes.c_int),
                 ("mk_models", ctypes.c_int), ("mk_states", ctypes.c_int), ("mk_ages", ctypes.c_int),
-                ("mk_w", ctypes.c_void_p), ("mk_c", ctypes.c_void_p)]
+                ("mk_w", ctypes.c_void_p), ("mk_c", ctypes.c_void_p),
+                ("age3", ctypes.c_void_p), ("table3", ctypes.c_void_p)]
 
 
 def _load():
@@ -129,9 +130,10 @@ class _Args:
             self.mk_w = np.ascontiguousarray(mk[0], np.float64)
             self.mk_c = np.ascontiguousarray(mk[1], np.float64)
             mk_dims = (self.mk_w.shape[0], self.mk_w.shape[2], self.mk_w.shape[1])
+        self.three = [opt(getattr(pf, "age3_m", None), i32), opt(getattr(pf, "table3", None), i32)]
         self.p = _Portfolio(int(pf.product.shape[0]), *[_ptr(a) for a in self.arrs], _ptr(self.cf),
                             n_rows, cf_len, mk_dims[0], mk_dims[1], mk_dims[2], _ptr(self.mk_w),
-                            _ptr(self.mk_c))
+                            _ptr(self.mk_c), _ptr(self.three[0]), _ptr(self.three[1]))
         self.n = int(pf.product.shape[0])
 
 

@@ -54,7 +54,8 @@
 enum {
     O_SL_ANN = 0, O_JL_ANN = 1, O_REV_ANN = 2, O_LS_ANN = 3,
     O_TERM = 4, O_ENDOW = 5, O_ENDOW_ASSUR = 6, O_CF_TABLE = 7,
-    O_JL_ENDOW = 8, O_JL_ASSUR1 = 9, O_JL_ASSUR2 = 10, O_MARKOV = 11, O_N_PRODUCTS = 12
+    O_JL_ENDOW = 8, O_JL_ASSUR1 = 9, O_JL_ASSUR2 = 10, O_MARKOV = 11,
+    O_JL3_ANN = 12, O_LS3_ANN = 13, O_N_PRODUCTS = 14
 };
 
 #define ORC_MAX_STATES 9
@@ -99,6 +100,9 @@ typedef struct {
     int mk_ages;
     const double *mk_w;
     const double *mk_c;
+    /* Life 3 of the three-life products (NULL when there are none). */
+    const int32_t *age3;
+    const int32_t *table3;
 } orc_portfolio;
 
 /* A contract in the paper's state-space form (Sec. 3.1, Sec. 4). */
@@ -250,13 +254,23 @@ int orc_contract_of(int product, int timing, double amount, double premium,
         k->n_lives = 2; k->life_model = 3; k->n_states = 9;
         k->c_ben[4] = sa; k->c_ben[5] = sa; k->c_ben[7] = sa;
         break;
-    case O_MARKOV:       /* Sec. 4.7: an uploaded state model; the benefit vector
+    case O_JL3_ANN:      /* Sec. 4.3: three lives, 2^3 = 8 states (binary labels, life 1
+                            the high digit); joint life: paid while all three are alive */
+        k->n_lives = 3; k->life_model = 2; k->n_states = 8;
+        k->c_ann[0] = pay;
+        break;
+    case O_LS3_ANN:      /* Sec. 4.3: last survivor of three: paid in every state with a
+                            living life, c = (1, 1, 1, 1, 1, 1, 1, 0) */
+        k->n_lives = 3; k->life_model = 2; k->n_states = 8;
+        for (int j = 0; j < 7; ++j) k->c_ann[j] = pay;
+        break;
+    case O_MARKOV:       /* Sec. 4.5: an uploaded state model; the benefit vector
                             and the size are set by contract_for */
         k->n_lives = 1; k->life_model = 2; k->n_states = 2;
         k->f_ann = 1.0;
         break;
     case O_CF_TABLE:     /* single life, c_t = amount x table value, at f = 1
-                            (Sec. 4.4: c_t holds the nominal amounts) */
+                            (Sec. 4.6: c_t holds the nominal amounts) */
         k->n_lives = 1; k->life_model = 2; k->n_states = 2;
         k->f_ann = 1.0;
         k->c_ann[0] = gross ? fabs(amount) : amount;
@@ -276,16 +290,16 @@ static double q_at(const orc_basis *b, int table, int age, double m)
     return s < 1.0 ? s : 1.0;
 }
 
-/* Per-life death probabilities over step t. */
+/* Per-life death probabilities over step t (q[3]: lives 1-3). */
 static void step_q(const orc_basis *b, const orc_portfolio *p, int i,
                    int age_shift, double m, int t, double *q)
 {
-    if (p->product[i] == O_MARKOV) {   /* an uploaded model carries its own transitions */
-        q[0] = q[1] = 0.0;
-        return;
-    }
+    q[0] = q[1] = q[2] = 0.0;
+    if (p->product[i] == O_MARKOV) return;   /* an uploaded model carries its own transitions */
     q[0] = q_at(b, p->table1[i], p->age1[i] + age_shift + t, m);
     q[1] = q_at(b, p->table2[i], p->age2[i] + age_shift + t, m);
+    if (p->product[i] == O_JL3_ANN || p->product[i] == O_LS3_ANN)
+        q[2] = q_at(b, p->table3[i], p->age3[i] + age_shift + t, m);
 }
 
 /* The contract of policy i (an uploaded model: its size and benefits; a
@@ -297,7 +311,8 @@ static void contract_for(const orc_basis *b, const orc_portfolio *p, int i, int 
     /* the annuities' payment point; cash-flow tables and uploaded models pay
      * at the end of the month whatever their timing field says */
     const int annuity = p->product[i] == O_SL_ANN || p->product[i] == O_JL_ANN ||
-                        p->product[i] == O_REV_ANN || p->product[i] == O_LS_ANN;
+                        p->product[i] == O_REV_ANN || p->product[i] == O_LS_ANN ||
+                        p->product[i] == O_JL3_ANN || p->product[i] == O_LS3_ANN;
     if (p->timing[i] == 2 && annuity) k->f_ann = b->frac;
     if (p->product[i] == O_MARKOV) {
         int m = p->mk_states;
@@ -372,7 +387,7 @@ static void recurrence_one(const orc_basis *b, const orc_portfolio *p, int i,
 {
     int n = k->n_states;
     double m = b->shock ? b->shock[node] : 1.0;
-    double r[ORC_MAX_STATES], rn[ORC_MAX_STATES], q[2];
+    double r[ORC_MAX_STATES], rn[ORC_MAX_STATES], q[3];
     double W1[ORC_MAX_STATES * ORC_MAX_STATES], y[ORC_MAX_STATES];
     for (int j = 0; j < n; ++j) r[j] = k->boundary[j];
     if (path) path[S] = r[0];
@@ -419,7 +434,7 @@ static int validate(const orc_basis *b, const orc_portfolio *p)
         if (p->timing[i] == 2 && !(b->frac > 0.0 && b->frac < 1.0)) return -1;
         if (p->escalation && !(p->escalation[i] >= 0.0)) return -1;
         if (p->product[i] == O_MARKOV) {   /* table1 is the model, ages index its tables */
-            if (!p->mk_w || !p->mk_c || p->mk_states < 2 || p->mk_states > 4) return -1;
+            if (!p->mk_w || !p->mk_c || p->mk_states < 2 || p->mk_states > ORC_MAX_STATES) return -1;
             if (p->table1[i] < 0 || p->table1[i] >= p->mk_models) return -1;
             if (p->age1[i] < 0 || p->age1[i] + p->term[i] > p->mk_ages - 1) return -1;
             continue;
@@ -434,9 +449,15 @@ static int validate(const orc_basis *b, const orc_portfolio *p)
         int two = p->product[i] == O_JL_ANN || p->product[i] == O_REV_ANN ||
                   p->product[i] == O_LS_ANN || p->product[i] == O_JL_ENDOW ||
                   p->product[i] == O_JL_ASSUR1 || p->product[i] == O_JL_ASSUR2;
-        if (two) {
+        int three = p->product[i] == O_JL3_ANN || p->product[i] == O_LS3_ANN;
+        if (two || three) {
             if (p->age2[i] < 0 || p->age2[i] + p->term[i] > b->n_ages - 1) return -1;
             if (p->table2[i] < 0 || p->table2[i] >= b->n_tables) return -1;
+        }
+        if (three) {
+            if (!p->age3 || !p->table3) return -1;
+            if (p->age3[i] < 0 || p->age3[i] + p->term[i] > b->n_ages - 1) return -1;
+            if (p->table3[i] < 0 || p->table3[i] >= b->n_tables) return -1;
         }
     }
     return 0;
@@ -481,7 +502,7 @@ int orc_reserves(const orc_basis *b, const orc_portfolio *p, int node0, int nnod
                 if (S <= 0) { r0s[o] = 0.0; g0s[o] = 0.0; if (gross) gross[o] = 0.0; continue; }
                 const double *vc = b->v + ((size_t)node * b->n_scen + (scen0 + s)) * b->n_steps;
                 recurrence_one(b, p, i, &k, node, shift, S, vc, r0, NULL);
-                if (ro && k.n_states == 9) {
+                if (ro && k.n_lives == 2 && k.life_model == 3) {
                     /* two-life 3-state models in the 4-state labelling (both
                      * alive, x only, y only, none): the dead states 2, 6, 8
                      * (the died-in-step states carry the same reserves) */
@@ -572,7 +593,7 @@ int orc_reserve_path_summation(const orc_basis *b, const orc_portfolio *p, int i
     const double *vc = b->v + ((size_t)node * b->n_scen + scen) * b->n_steps;
     double P[ORC_MAX_STATES * ORC_MAX_STATES], T[ORC_MAX_STATES * ORC_MAX_STATES];
     double Wg[ORC_MAX_STATES * ORC_MAX_STATES], PW[ORC_MAX_STATES * ORC_MAX_STATES];
-    double y[ORC_MAX_STATES], q[2];
+    double y[ORC_MAX_STATES], q[3];
     const double *streams[3] = {k.c_prem, k.c_ann, k.c_ben};
     double gs[3] = {0.0, k.f_ann, 1.0};
     for (int t = 0; t <= S; ++t) {
@@ -714,6 +735,55 @@ static void reduced_one(const orc_portfolio *p, int i, const orc_contract *k, in
     if (prod == O_JL_ASSUR2) { out4[1] = r1; out4[2] = r2; }
 }
 
+/* Three lives (Sec. 4.3), two-state model each.  A state with at least one
+ * life alive is identified by the set A of living lives (bit l-1 of a mask
+ * for life l); the state with none alive has reserve 0 and is dropped.
+ * With d_l = f q_l the death probability of life l over the fraction f of
+ * a step, the last-survivor annuity pays in state A if some life of A is
+ * alive at t + f (probability 1 - prod_{l in A} d_l) and the joint-life
+ * annuity only in A = {1,2,3}, if all are alive at t + f (probability
+ * prod_l (1 - d_l)); its other states never pay again and are dropped too:
+ *   r_A = -P [A = {1,2,3}] + v^f a (payment probability)
+ *         + v sum_{B subset of A, B nonempty} prod_{l in B} p_l prod_{l in A\B} q_l r'_B.  Slots: state j of the binary labels (life 1 the high digit, 1 =
+ * dead), j = 0..3: A = {1,2,3}, {1,2}, {1,3}, {1}. */
+static void three_one(const orc_portfolio *p, int i, const orc_contract *k, int S, const double *vc,
+                      const double *q1s, const double *q2s, const double *q3s, const double *as,
+                      double *out4)
+{
+    const int joint = p->product[i] == O_JL3_ANN;
+    const double P = -k->c_prem[0];
+    const double f = k->f_ann;
+    double r[8] = {0}, rn[8];
+    for (int t = S - 1; t >= 0; --t) {
+        const double v = vc[t];
+        const double vf = (f == 1.0) ? v : (f == 0.0 ? 1.0 : pow(v, f));
+        const double q[3] = {q1s[t], q2s[t], q3s[t]};
+        for (int A = 1; A < 8; ++A) {
+            if (joint && A != 7) { rn[A] = 0.0; continue; }
+            /* the payment's probability: some life of A alive at t + f (last
+             * survivor), every life alive at t + f (joint life) */
+            double pay_prob = 1.0;
+            for (int l = 0; l < 3; ++l)
+                if (A >> l & 1) pay_prob *= joint ? 1.0 - f * q[l] : f * q[l];
+            if (!joint) pay_prob = 1.0 - pay_prob;
+            double acc = 0.0;
+            for (int B = 1; B < 8; ++B) {
+                if ((B & A) != B) continue;
+                double pr = 1.0;
+                for (int l = 0; l < 3; ++l)
+                    if (A >> l & 1) pr *= (B >> l & 1) ? 1.0 - q[l] : q[l];
+                acc += pr * r[B];
+            }
+            rn[A] = vf * as[t] * pay_prob + v * acc - (A == 7 ? P : 0.0);
+        }
+        for (int A = 1; A < 8; ++A) r[A] = rn[A];
+    }
+    out4[0] = r[7];
+    out4[1] = r[3];   /* lives 1, 2 */
+    out4[2] = r[5];   /* lives 1, 3 */
+    out4[3] = r[1];   /* life 1 */
+}
+
 /* An uploaded Markov model: every state kept, r_j = -P [j = 0] +
  * v sum_i w_{j,i} (c_i + r_i'), benefits c at the end of the month. */
 static void markov_one(const orc_portfolio *p, int i, const orc_contract *k, int shift, int S,
@@ -760,14 +830,15 @@ int orc_reserves_reduced(const orc_basis *b, const orc_portfolio *p, int node0, 
     {
         double *q1s = (double *)malloc(sizeof(double) * (size_t)(b->n_steps + 1));
         double *q2s = (double *)malloc(sizeof(double) * (size_t)(b->n_steps + 1));
+        double *q3s = (double *)malloc(sizeof(double) * (size_t)(b->n_steps + 1));
         double *as = (double *)malloc(sizeof(double) * (size_t)(b->n_steps + 1));
-        if (!q1s || !q2s || !as) {
+        if (!q1s || !q2s || !q3s || !as) {
 #pragma omp atomic write
             bad = 1;
         }
 #pragma omp for schedule(dynamic, 1)
         for (int i = 0; i < n; ++i) {
-            if (!q1s || !q2s || !as) continue;
+            if (!q1s || !q2s || !q3s || !as) continue;
             orc_contract k;
             contract_for(b, p, i, 0, &k);
             double pay = 0.0;   /* the annuity (or table) stream's amount, one state at a time */
@@ -782,10 +853,11 @@ int orc_reserves_reduced(const orc_basis *b, const orc_portfolio *p, int node0, 
                  * and the transition probabilities before the backward loop */
                 if (S > 0 && p->product[i] != O_MARKOV)
                     for (int t = 0; t < S; ++t) {
-                        double q[2];
+                        double q[3];
                         step_q(b, p, i, shift, m, t, q);
                         q1s[t] = q[0];
                         q2s[t] = q[1];
+                        q3s[t] = q[2];
                         as[t] = pay != 0.0
                                     ? pay * payment_factor(p, i, shift + t + (k.f_ann == 1.0 ? 1 : 0), &k)
                                     : 0.0;
@@ -796,6 +868,8 @@ int orc_reserves_reduced(const orc_basis *b, const orc_portfolio *p, int node0, 
                     if (S > 0) {
                         const double *vc = b->v + ((size_t)node * b->n_scen + (scen0 + s)) * b->n_steps;
                         if (p->product[i] == O_MARKOV) markov_one(p, i, &k, shift, S, vc, r4);
+                        else if (p->product[i] == O_JL3_ANN || p->product[i] == O_LS3_ANN)
+                            three_one(p, i, &k, S, vc, q1s, q2s, q3s, as, r4);
                         else reduced_one(p, i, &k, S, vc, q1s, q2s, as, r4);
                     }
                     r0s[o] = r4[0];
@@ -806,6 +880,7 @@ int orc_reserves_reduced(const orc_basis *b, const orc_portfolio *p, int node0, 
         }
         free(q1s);
         free(q2s);
+        free(q3s);
         free(as);
     }
     if (bad) { free(r0s); return -2; }

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ERANGE, RR_ESTATE = 0, -1, -2, -3, -4, -5
 SL_ANN, JL_ANN, REV_ANN, LS_ANN, TERM, ENDOW, ENDOW_ASSUR, CF_TABLE = range(8)
 JL_ENDOW, JL_ASSUR1, JL_ASSUR2, MARKOV = 8, 9, 10, 11
+JL3_ANN, LS3_ANN = 12, 13
 
 
 class Markov(ctypes.Structure):
@@ -84,7 +85,8 @@ class Portfolio(ctypes.Structure):
                 ("mem_kind", ctypes.c_int32), ("escalation", ctypes.c_void_p),
                 ("anniv_m", ctypes.c_void_p), ("annual", ctypes.c_void_p),
                 ("cf_row", ctypes.c_void_p), ("cf", ctypes.c_void_p),
-                ("cf_n_rows", ctypes.c_int32), ("cf_len", ctypes.c_int32)]
+                ("cf_n_rows", ctypes.c_int32), ("cf_len", ctypes.c_int32),
+                ("age3_m", ctypes.c_void_p), ("table3", ctypes.c_void_p)]
 
 
 class Run(ctypes.Structure):
@@ -247,13 +249,17 @@ def portfolio_struct(pf, keep=None):
     cf = getattr(pf, "cf", None)
     cf = None if cf is None else np.ascontiguousarray(np.atleast_2d(cf), np.float64)
     n_rows, cf_len = (0, 0) if cf is None else cf.shape
+    three = [None if getattr(pf, name, None) is None else _np(getattr(pf, name), np.int32)
+             for name in ("age3_m", "table3")]
     if keep is not None:
         keep.extend(arrs)
         keep.extend(opt)
         keep.append(cf)
+        keep.extend(three)
     return Portfolio(arrs[0].shape[0], *[a.ctypes.data for a in arrs], HOST,
                      *[None if a is None else a.ctypes.data for a in opt],
-                     None if cf is None else cf.ctypes.data, n_rows, cf_len)
+                     None if cf is None else cf.ctypes.data, n_rows, cf_len,
+                     *[None if a is None else a.ctypes.data for a in three])
 
 
 def check_portfolio(pf, n_steps, n_ages, n_tables):

@@ -136,11 +136,13 @@ struct rr_ctx {
     int max_age_needed = 0;
     int head_pad = 0;                     // largest ragged head of an item (steps)
     std::vector<int32_t> h_product, h_age1, h_age2, h_term, h_table1, h_table2, h_timing;
+    std::vector<int32_t> h_age3, h_table3;   // life 3 (0 for other products)
     std::vector<double> h_amount, h_premium;
     std::vector<int32_t> h_patterned;     // 1: escalating or annual annuity
     std::vector<Tile> tiles_host;
     std::vector<int> slot_of_user;       // user index -> sorted slot
     DevBuf<int> age1, age2, term, qoff1, qoff2, uidx;
+    DevBuf<int> age3, qoff3;              // life 3 of three-life tiles (0 elsewhere)
     DevBuf<double> coef;
     DevBuf<double> pat_g;                 // [n_pad] (with pattern or table tiles)
     DevBuf<int> pat_code;
@@ -152,7 +154,8 @@ struct rr_ctx {
     bool has_markov = false;
     int mk_models = 0, mk_states = 0, mk_ages = 0;
     std::vector<double> mk_c_host;        // [model][mk_states] benefits
-    DevBuf<double> mk_w;                  // [model][mk_ages][4][4]
+    DevBuf<double> mk_w;                  // [model][mk_ages][4][4] ([9][9] above 4 states)
+    DevBuf<double> mk_c;                  // [model][9] benefits per unit amount
     DevBuf<Tile> tiles;
     int gen = 0;                          // bumps on every upload
     long long curve_gen = 0;              // bumps whenever the curve values change (uploads

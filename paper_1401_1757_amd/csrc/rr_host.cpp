@@ -44,10 +44,14 @@ static void set_msg(char *msg, size_t len, const std::string &s)
     }
 }
 
+static bool is_three_life(int product) { return product == RR_JL3_ANN || product == RR_LS3_ANN; }
+
+// Products with a second life (the three-life annuities included).
 static bool is_two_life(int product)
 {
     return product == RR_JL_ANN || product == RR_REV_ANN || product == RR_LS_ANN ||
-           product == RR_JL_ENDOW || product == RR_JL_ASSUR1 || product == RR_JL_ASSUR2;
+           product == RR_JL_ENDOW || product == RR_JL_ASSUR1 || product == RR_JL_ASSUR2 ||
+           is_three_life(product);
 }
 
 // State model after the zero-reserve states are removed (Sec. 3.6.4): the
@@ -58,9 +62,11 @@ static int kind_of(int product)
     switch (product) {
     case RR_JL_ANN:
     case RR_JL_ENDOW:
+    case RR_JL3_ANN:
     case RR_JL_ASSUR1: return KIND_JOINT;
     case RR_REV_ANN: return KIND_REV;
     case RR_LS_ANN:
+    case RR_LS3_ANN:
     case RR_JL_ASSUR2: return KIND_LAST;
     default: return KIND_SINGLE;
     }
@@ -138,7 +144,8 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
                                           const int32_t *anniv, const int32_t *annual,
                                           const int32_t *cf_row, const double *cf, int cf_n_rows,
                                           int cf_len, int n_steps, int n_ages, int n_tables,
-                                          int mk_models = -1, int mk_ages = -1, double frac = -1.0)
+                                          int mk_models = -1, int mk_ages = -1, double frac = -1.0,
+                                          const int32_t *age3 = nullptr, const int32_t *table3 = nullptr)
 {
     char b[256];
     if (n < 0) return "portfolio: n must be >= 0";
@@ -156,7 +163,7 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
         return "portfolio: product, age1_m, term_m, table1 and amount must not be NULL";
     for (int i = 0; i < n; ++i) {
         int pr = product[i];
-        if (pr < RR_SL_ANN || pr > RR_MARKOV) {
+        if (pr < RR_SL_ANN || pr > RR_LS3_ANN) {
             snprintf(b, sizeof b, "portfolio: policy %d has unknown product %d", i, pr);
             return b;
         }
@@ -195,6 +202,18 @@ static std::string check_portfolio_arrays(int n, const int32_t *product, const i
             }
             if (table2[i] < 0 || table2[i] >= n_tables) {
                 snprintf(b, sizeof b, "portfolio: policy %d table2 %d outside [0, %d)", i, table2[i], n_tables);
+                return b;
+            }
+        }
+        if (is_three_life(pr)) {
+            if (!age3 || !table3) return "portfolio: three-life products need age3_m and table3";
+            if (age3[i] < 0 || (long long)age3[i] + term[i] > n_ages - 1) {
+                snprintf(b, sizeof b, "portfolio: policy %d third age %d + term %d exceeds the tables",
+                         i, age3[i], term[i]);
+                return b;
+            }
+            if (table3[i] < 0 || table3[i] >= n_tables) {
+                snprintf(b, sizeof b, "portfolio: policy %d table3 %d outside [0, %d)", i, table3[i], n_tables);
                 return b;
             }
         }
@@ -284,7 +303,8 @@ extern "C" int rr_check_portfolio(const rr_portfolio *p, int32_t n_steps, int32_
                                            p->table1, p->table2, p->timing, p->amount,
                                            p->premium, p->escalation, p->anniv_m, p->annual,
                                            p->cf_row, p->cf, p->cf_n_rows, p->cf_len,
-                                           n_steps, n_ages, n_tables);
+                                           n_steps, n_ages, n_tables, -1, -1, -1.0, p->age3_m,
+                                           p->table3);
     set_msg(msg, msg_len, s);
     return s.empty() ? RR_OK : RR_EINVAL;
 }
@@ -537,9 +557,10 @@ static int install_basis(rr_ctx *c, const rr_basis *b, std::vector<double> &q,
                 if (c->h_term[i] > b->n_steps) keep_pf = false;
                 continue;
             }
-            int two = is_two_life(c->h_product[i]);
-            int amax = std::max(c->h_age1[i], two ? c->h_age2[i] : 0) + c->h_term[i];
-            int tmax = std::max(c->h_table1[i], two ? c->h_table2[i] : 0);
+            int two = is_two_life(c->h_product[i]), three = is_three_life(c->h_product[i]);
+            int amax = std::max({c->h_age1[i], two ? c->h_age2[i] : 0, three ? c->h_age3[i] : 0}) +
+                       c->h_term[i];
+            int tmax = std::max({c->h_table1[i], two ? c->h_table2[i] : 0, three ? c->h_table3[i] : 0});
             if (c->h_term[i] > b->n_steps || amax > b->n_ages - 1 || tmax >= b->n_tables) keep_pf = false;
             if (c->h_timing[i] == RR_FRACTIONAL && !(b->frac > 0.0)) keep_pf = false;
         }
@@ -674,7 +695,7 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     const size_t n = (size_t)p->n;
     std::vector<int32_t> product, age1, age2, term, table1, table2, timing;
     std::vector<double> amount, premium, escalation, cf;
-    std::vector<int32_t> anniv, annual, cf_row;
+    std::vector<int32_t> anniv, annual, cf_row, age3, table3;
     int rc;
     if (n > 0 && (!p->product || !p->age1_m || !p->term_m || !p->table1 || !p->amount))
         return fail(c, RR_EINVAL, "portfolio: product, age1_m, term_m, table1 and amount must not be NULL");
@@ -699,6 +720,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     else annual.assign(n, 0);
     if (p->cf_n_rows < 0 || p->cf_len < 0) return fail(c, RR_EINVAL, "portfolio: cf_n_rows and cf_len must be >= 0");
     if (p->cf_row) { if ((rc = fetch(c, p->cf_row, n, p->mem_kind, cf_row))) return rc; }
+    if (p->age3_m) { if ((rc = fetch(c, p->age3_m, n, p->mem_kind, age3))) return rc; }
+    if (p->table3) { if ((rc = fetch(c, p->table3, n, p->mem_kind, table3))) return rc; }
     if (p->cf) {
         if ((rc = fetch(c, p->cf, (size_t)p->cf_n_rows * p->cf_len, p->mem_kind, cf))) return rc;
     }
@@ -714,8 +737,12 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                                            p->cf ? cf.data() : nullptr, p->cf_n_rows, p->cf_len,
                                            c->n_steps, c->n_ages, c->n_tables,
                                            c->has_markov ? c->mk_models : 0,
-                                           c->has_markov ? c->mk_ages : 0, c->frac);
+                                           c->has_markov ? c->mk_ages : 0, c->frac,
+                                           p->age3_m ? age3.data() : nullptr,
+                                           p->table3 ? table3.data() : nullptr);
     if (!s.empty()) return fail(c, RR_EINVAL, "%s", s.c_str());
+    if (!p->age3_m) age3.assign(n, 0);
+    if (!p->table3) table3.assign(n, 0);
 
     drop_graphs(c);
     c->plans.clear();
@@ -729,6 +756,7 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
         patterned[i] = (escalation[i] > 0.0 || annual[i] == 1) ? 1 : 0;
         flow[i] = product[i] == RR_CF_TABLE      ? FLOW_TABLE
                   : product[i] == RR_MARKOV      ? FLOW_MARKOV
+                  : is_three_life(product[i])    ? FLOW_THREE
                   : timing[i] == RR_FRACTIONAL   ? FLOW_FRAC
                   : patterned[i]                 ? FLOW_PATTERN
                                                  : FLOW_LEVEL;
@@ -751,7 +779,7 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
         return term[a] > term[b];
     });
     // Slots: each model's run padded to whole tiles.
-    std::vector<int> s_age1, s_age2, s_term, s_qoff1, s_qoff2, s_uidx;
+    std::vector<int> s_age1, s_age2, s_age3, s_term, s_qoff1, s_qoff2, s_qoff3, s_uidx;
     std::vector<Tile> tiles;
     std::vector<int> slot_user;
     size_t i0 = 0;
@@ -779,10 +807,14 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                     const bool mk = product[u] == RR_MARKOV;   // no mortality table
                     s_qoff1.push_back(mk ? 0 : table1[u]);   // scaled below
                     s_qoff2.push_back(two ? table2[u] : 0);
+                    const bool three = is_three_life(product[u]);
+                    s_age3.push_back(three ? age3[u] : 0);
+                    s_qoff3.push_back(three ? table3[u] : 0);
                     T.smax = std::max(T.smax, term[u]);
                     T.smin = std::min(T.smin, term[u]);
                     if (!mk) max_age = std::max(max_age, age1[u] + term[u]);
                     if (two) max_age = std::max(max_age, age2[u] + term[u]);
+                    if (three) max_age = std::max(max_age, age3[u] + term[u]);
                 } else {
                     s_uidx.push_back(-1);
                     s_age1.push_back(0);
@@ -790,6 +822,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
                     s_term.push_back(0);
                     s_qoff1.push_back(0);
                     s_qoff2.push_back(0);
+                    s_age3.push_back(0);
+                    s_qoff3.push_back(0);
                 }
             }
             tiles.push_back(T);
@@ -817,6 +851,7 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     for (int j = 0; j < n_pad; ++j) {
         s_qoff1[j] *= c->n_ages_stage;
         s_qoff2[j] *= c->n_ages_stage;
+        s_qoff3[j] *= c->n_ages_stage;
     }
     // Lane order within each tile.  All lanes of a tile take the same step t
     // together, so lane l reads the staged table at (qoff + age)_l + shift + t
@@ -870,6 +905,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
             apply(s_term);
             apply(s_qoff1);
             apply(s_qoff2);
+            apply(s_age3);
+            apply(s_qoff3);
         }
     }
     // Coefficients.
@@ -918,8 +955,21 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
             break;
         case RR_MARKOV:        // premium in state 0, benefits per state
             C(0, j) = -P;
-            for (int st = 0; st < c->mk_states; ++st)
-                C(1 + st, j) = amount[u] * c->mk_c_host[(size_t)table1[u] * c->mk_states + st];
+            if (c->mk_states <= 4) {
+                for (int st = 0; st < c->mk_states; ++st)
+                    C(1 + st, j) = amount[u] * c->mk_c_host[(size_t)table1[u] * c->mk_states + st];
+            } else {
+                C(1, j) = amount[u];   // the kernel scales the model's benefits
+            }
+            break;
+        case RR_JL3_ANN:
+            C(0, j) = (adv ? pay : 0.0) - P;
+            C(1, j) = adv ? 0.0 : pay;
+            break;
+        case RR_LS3_ANN:       // premium while all three are alive
+            C(0, j) = (adv ? pay : 0.0) - P;
+            C(1, j) = adv ? 0.0 : pay;
+            C(2, j) = adv ? pay : 0.0;
             break;
         case RR_REV_ANN:
             C(0, j) = -P;
@@ -941,6 +991,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     if ((rc = upload_vec(c, c->term, s_term))) return rc;
     if ((rc = upload_vec(c, c->qoff1, s_qoff1))) return rc;
     if ((rc = upload_vec(c, c->qoff2, s_qoff2))) return rc;
+    if ((rc = upload_vec(c, c->age3, s_age3))) return rc;
+    if ((rc = upload_vec(c, c->qoff3, s_qoff3))) return rc;
     if ((rc = upload_vec(c, c->uidx, s_uidx))) return rc;
     if ((rc = upload_vec(c, c->coef, coef))) return rc;
     if ((rc = upload_vec(c, c->tiles, tiles))) return rc;
@@ -1002,6 +1054,8 @@ extern "C" int rr_portfolio_upload(rr_ctx *c, const rr_portfolio *p)
     c->h_term.swap(term);
     c->h_table1.swap(table1);
     c->h_table2.swap(table2);
+    c->h_age3.swap(age3);
+    c->h_table3.swap(table3);
     c->h_timing.swap(timing);
     c->h_amount.swap(amount);
     c->h_premium.swap(premium);
@@ -1061,11 +1115,15 @@ extern "C" int rr_markov_upload(rr_ctx *c, const rr_markov *m)
     if (!c) return RR_EINVAL;
     if (!m) return fail(c, RR_EINVAL, "markov: models are NULL");
     if (m->mem_kind != RR_HOST && m->mem_kind != RR_DEVICE) return fail(c, RR_EINVAL, "bad mem_kind");
-    if (m->n_models < 1 || m->n_states < 2 || m->n_states > 4 || m->n_ages < 2)
-        return fail(c, RR_EINVAL, "markov: need n_models >= 1, 2 <= n_states <= 4, n_ages >= 2");
+    if (m->n_models < 1 || m->n_states < 2 || m->n_states > MAX_MK_STATES || m->n_ages < 2)
+        return fail(c, RR_EINVAL, "markov: need n_models >= 1, 2 <= n_states <= 9, n_ages >= 2");
     if (!m->w || !m->benefit) return fail(c, RR_EINVAL, "markov: w and benefit must not be NULL");
     const int M = m->n_states;
-    if ((long long)m->n_models * m->n_ages * 16 > (1LL << 31)) return fail(c, RR_EINVAL, "markov: tables too large");
+    // Device layout: rows padded to 4 states ([4][4], 16-byte row pairs) up
+    // to 4 states, to 9 ([9][9]) above.
+    const int MP = M <= 4 ? 4 : MAX_MK_STATES;
+    if ((long long)m->n_models * m->n_ages * MP * MP > (1LL << 31))
+        return fail(c, RR_EINVAL, "markov: tables too large");
     HIPCHK(c, hipSetDevice(c->device));
     std::vector<double> w, ben;
     int rc;
@@ -1073,7 +1131,7 @@ extern "C" int rr_markov_upload(rr_ctx *c, const rr_markov *m)
     if ((rc = fetch(c, m->benefit, (size_t)m->n_models * M, m->mem_kind, ben))) return rc;
     for (size_t k = 0; k < ben.size(); ++k)
         if (!std::isfinite(ben[k])) return fail(c, RR_EINVAL, "markov: benefit[%zu] is not finite", k);
-    std::vector<double> wp((size_t)m->n_models * m->n_ages * 16, 0.0);
+    std::vector<double> wp((size_t)m->n_models * m->n_ages * MP * MP, 0.0);
     for (int md = 0; md < m->n_models; ++md)
         for (int a = 0; a < m->n_ages; ++a)
             for (int i = 0; i < M; ++i) {
@@ -1084,13 +1142,17 @@ extern "C" int rr_markov_upload(rr_ctx *c, const rr_markov *m)
                         return fail(c, RR_EINVAL, "markov: model %d age %d w[%d][%d] = %g is not a probability",
                                     md, a, i, j, x);
                     sum += x;
-                    wp[(((size_t)md * m->n_ages + a) * 4 + i) * 4 + j] = x;
+                    wp[(((size_t)md * m->n_ages + a) * MP + i) * MP + j] = x;
                 }
                 if (std::fabs(sum - 1.0) > 1e-12)
                     return fail(c, RR_EINVAL, "markov: model %d age %d row %d sums to %.17g", md, a, i, sum);
             }
     HIPCHK(c, c->mk_w.alloc(wp.size()));
     HIPCHK(c, hipMemcpy(c->mk_w.p, wp.data(), wp.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> cpad((size_t)m->n_models * MAX_MK_STATES, 0.0);
+    for (int md = 0; md < m->n_models; ++md)
+        for (int j = 0; j < M; ++j) cpad[(size_t)md * MAX_MK_STATES + j] = ben[(size_t)md * M + j];
+    if ((rc = upload_vec(c, c->mk_c, cpad))) return rc;
     c->mk_c_host.swap(ben);
     c->mk_models = m->n_models;
     c->mk_states = M;
@@ -1271,6 +1333,10 @@ static RecParams make_params(rr_ctx *c, const rr_run *run, const rr_outputs *out
     P.cf_cols = c->cf_cols;
     P.mk_w = c->has_markov ? c->mk_w.p : nullptr;
     P.mk_ages = c->mk_ages;
+    P.mk_states = c->mk_states;
+    P.mk_c = c->has_markov ? c->mk_c.p : nullptr;
+    P.age3 = c->age3.p;
+    P.qoff3 = c->qoff3.p;
     P.vf = c->frac > 0.0 ? c->vf.p : nullptr;
     P.frac = c->frac;
     P.n_pad = c->n_pad;

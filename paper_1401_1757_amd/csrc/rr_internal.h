@@ -38,6 +38,9 @@ constexpr int WG_THREADS = RR_WG_THREADS;   // wavefronts per workgroup x 64
 //                             4/5: advance/arrears amount in state 10
 //                             6: KIND_LAST: benefit on the second death (end of its step)
 //  Markov tiles:              0: a0 = - premium (state 0), 1..4: amount x benefit of states 0..3
+//                             (models of 5-9 states: 1: amount; benefits per model in mk_c)
+//  three-life tiles:          0: advance amount - premium (all alive), 1: arrears amount,
+//                             2: advance amount in the other states (last survivor)
 
 // How a tile's cash flows vary in time.  Tiles other than level ones run
 // one tile per item.
@@ -45,10 +48,12 @@ enum Flow : int {
     FLOW_LEVEL = 0,     // level amounts (coef rows)
     FLOW_PATTERN = 1,   // annuities in payment with escalation or annual payment
     FLOW_TABLE = 2,     // single life, cash flow of step t from a per-policy table
-    FLOW_MARKOV = 3,    // one life on an uploaded Markov model (up to 4 states)
-    FLOW_FRAC = 4       // single- or joint-life annuity paid at a fraction of the month
+    FLOW_MARKOV = 3,    // one life on an uploaded Markov model (up to 9 states)
+    FLOW_FRAC = 4,      // single- or joint-life annuity paid at a fraction of the month
+    FLOW_THREE = 5      // annuity on three lives (KIND_JOINT: joint life, KIND_LAST: last survivor)
 };
-constexpr int N_FLOWS = 5;
+constexpr int N_FLOWS = 6;
+constexpr int MAX_MK_STATES = 9;   // largest uploaded Markov model
 
 struct Tile {
     int kind;
@@ -95,8 +100,13 @@ struct RecParams {
     const int *pat_code;      // [n_pad] anniversary / annual / timing code or table column, or null
     const double *cf_t;       // [cf_steps][cf_cols] amount x table value of the step, or null
     int cf_cols;
-    const double *mk_w;       // [model][mk_ages][4][4] uploaded Markov matrices (zero padded)
+    const double *mk_w;       // [model][mk_ages][4][4] uploaded Markov matrices (zero padded),
+                              // [model][mk_ages][9][9] for models of 5-9 states
     int mk_ages;
+    int mk_states;
+    const double *mk_c;       // [model][9] benefits per unit amount (models of 5-9 states)
+    const int *age3;          // life 3 of three-life tiles (other slots: 0)
+    const int *qoff3;
     const double *vf;         // v^frac, laid out as v (fractional tiles), or null
     double frac;
     int n_pad;

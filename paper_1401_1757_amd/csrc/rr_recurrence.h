@@ -774,7 +774,7 @@ __device__ __forceinline__ void run_frac(const RecParams &P, const double *__res
     store_results<K>(P, node_rel, tile, sb, lane, uid, live, r, r, r, false, false);
 }
 
-// One life on an uploaded Markov model (Sec. 4.7; the matrix need not be
+// One life on an uploaded Markov model (Sec. 4.5; the matrix need not be
 // upper triangular): up to four states, zero padded to four.  With y = c +
 // r' per state (c: the benefits paid at the end of a month ending in the
 // state) and W_t the model's matrix at the attained age:
@@ -832,10 +832,168 @@ __device__ __forceinline__ void markov_chunk(const RecParams &P, const double2 *
     }
 }
 
+// Models of 5 to 9 states: the lane's matrix (rows of 9, zero padded) is
+// read row by row from memory at each step, one scenario chain at a time
+// (these tiles are rare; the point is a small register footprint), and the
+// benefits are the model's times the policy's amount:
+//   r_i <- a_i + v * sum_j W_t[i][j] * (amount c_j + r'_j).
+__device__ __forceinline__ void markov9_chain(const RecParams &P, const double *__restrict__ wb,
+                                              const double *__restrict__ vb, int S, int smax, double a0,
+                                              const double (&c)[MAX_MK_STATES], double *path,
+                                              double (&r)[MAX_MK_STATES])
+{
+    constexpr int M = MAX_MK_STATES;
+#pragma unroll
+    for (int i = 0; i < M; ++i) r[i] = 0.0;
+    for (int t = min(S, smax) - 1; t >= 0; --t) {
+        const double v = vb[(ptrdiff_t)t * P.scen_pad];
+        const double *w = wb + (size_t)t * M * M;
+        double y[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) y[j] = c[j] + r[j];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            double acc = w[i * M] * y[0];
+#pragma unroll
+            for (int j = 1; j < M; ++j) acc = fma(w[i * M + j], y[j], acc);
+            r[i] = fma(v, acc, i == 0 ? a0 : 0.0);
+        }
+        if (path != nullptr) path[t] = r[0];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void run_markov9(const RecParams &P, const double *__restrict__ vcurves,
+                                            int node_rel, int tile, const Tile &T, int sb, int lane)
+{
+    constexpr int M = MAX_MK_STATES;
+    const int node = P.node_begin + node_rel;
+    const int shift = node * P.node_step;
+    const int slot = T.first + lane;
+    const int S = P.term[slot] - shift;
+    const int uid = P.uidx[slot];
+    const bool live = (uid >= 0) && (S > 0);
+    const int smax = T.smax - shift;
+    const double a0 = P.coef[slot];
+    const double amount = P.coef[P.n_pad + slot];
+    const int model = uid >= 0 ? P.pat_code[slot] : 0;
+    double c[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) c[j] = amount * P.mk_c[model * M + j];
+    const int age0 = uid >= 0 ? P.age1[slot] + shift : 0;
+    const double *wb = P.mk_w + ((size_t)model * P.mk_ages + age0) * (M * M);
+    const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
+    double *path = nullptr;
+    if constexpr (K == 1) {
+        if (P.path != nullptr && uid >= 0) {
+            if (live) {
+                path = P.path + P.path_off[uid];
+                path[S] = 0.0;
+            } else {
+                P.path[P.path_off[uid]] = 0.0;   // expired: its one entry is 0
+            }
+        }
+    }
+    for (int k = 0; k < K; ++k) {
+        double r[M];
+        markov9_chain(P, wb, vb + k, S, smax, a0, c, path, r);
+        double x0[1] = {r[0]}, x1[1] = {r[1]}, x2[1] = {r[2]}, x3[1] = {r[3]};
+        store_results<1>(P, node_rel, tile, sb + k, lane, uid, live, x0, x1, x2, true, true, x3);
+    }
+}
+
+// Three lives (Sec. 4.3, two-state model each): a state with some life
+// alive is the set A of living lives (bit l - 1 for life l); the state with
+// none alive has reserve 0 (Sec. 3.6.4).  Per step, with the survival p_l and
+// death probability q_l = 1 - p_l of each life shared by the chains,
+// arrears amount a1, advance amounts a0 (and, all alive, minus the premium)
+// and y_B = a1 + r'_B:
+//   r_A = a0 + v sum_{B subset of A, B nonempty} prod_{l in B} p_l prod_{l in A\B} q_l y_B.
+// The last-survivor annuity pays in every such state; the joint-life annuity
+// only in A = {1,2,3}, whose reserve then needs only its own chain (the
+// other states never pay again).  One scenario chain at a time: rare tiles,
+// small register footprint.  Output slots: state j of the binary labels (life
+// 1 the high digit, 1 = dead): A = {1,2,3}, {1,2}, {1,3}, {1}.
+template <int K, bool LDSQ, bool SHOCK>
+__device__ __forceinline__ void run_three(const RecParams &P, const double *__restrict__ lq,
+                                          const double *__restrict__ vcurves, int node_rel, int tile,
+                                          const Tile &T, int sb, int lane)
+{
+    const int node = P.node_begin + node_rel;
+    const int shift = node * P.node_step;
+    const int slot = T.first + lane;
+    const int S = P.term[slot] - shift;
+    const int uid = P.uidx[slot];
+    const bool live = (uid >= 0) && (S > 0);
+    const int smax = T.smax - shift;
+    const double m = P.shock[node];
+    const bool last = T.kind == KIND_LAST;
+    const double a0all = P.coef[slot];              // advance amount - premium (all alive)
+    const double a1 = P.coef[P.n_pad + slot];       // arrears amount
+    const double a0 = P.coef[2 * P.n_pad + slot];   // advance amount (other states)
+    const int qa = P.qoff1[slot] + P.age1[slot] + shift;
+    const int qb = P.qoff2[slot] + P.age2[slot] + shift;
+    const int qc = P.qoff3[slot] + P.age3[slot] + shift;
+    const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
+    double *path = nullptr;
+    if constexpr (K == 1) {
+        if (P.path != nullptr && uid >= 0) {
+            if (live) {
+                path = P.path + P.path_off[uid];
+                path[S] = 0.0;
+            } else {
+                P.path[P.path_off[uid]] = 0.0;   // expired: its one entry is 0
+            }
+        }
+    }
+    for (int k = 0; k < K; ++k) {
+        double r1 = 0.0, r2 = 0.0, r3 = 0.0, r4 = 0.0, r5 = 0.0, r6 = 0.0, r7 = 0.0;   // r_A, A = mask
+        for (int t = min(S, smax) - 1; t >= 0; --t) {
+            const double p1 = p_eff<LDSQ, SHOCK>(lq, P.q, qa + t, m);
+            const double p2 = p_eff<LDSQ, SHOCK>(lq, P.q, qb + t, m);
+            const double p3 = p_eff<LDSQ, SHOCK>(lq, P.q, qc + t, m);
+            const double q1 = 1.0 - p1, q2 = 1.0 - p2, q3 = 1.0 - p3;
+            const double v = vb[(ptrdiff_t)t * P.scen_pad + k];
+            const double y7 = a1 + r7;
+            if (!last) {
+                r7 = fma(v, p1 * p2 * p3 * y7, a0all);
+            } else {
+                const double y1 = a1 + r1, y2 = a1 + r2, y3 = a1 + r3, y4 = a1 + r4, y5 = a1 + r5,
+                             y6 = a1 + r6;
+                double n7 = p1 * p2 * p3 * y7;
+                n7 = fma(p1 * p2 * q3, y3, n7);
+                n7 = fma(p1 * q2 * p3, y5, n7);
+                n7 = fma(q1 * p2 * p3, y6, n7);
+                n7 = fma(p1 * q2 * q3, y1, n7);
+                n7 = fma(q1 * p2 * q3, y2, n7);
+                n7 = fma(q1 * q2 * p3, y4, n7);
+                const double n3 = fma(p1 * p2, y3, fma(p1 * q2, y1, q1 * p2 * y2));   // {1,2}
+                const double n5 = fma(p1 * p3, y5, fma(p1 * q3, y1, q1 * p3 * y4));   // {1,3}
+                const double n6 = fma(p2 * p3, y6, fma(p2 * q3, y2, q2 * p3 * y4));   // {2,3}
+                r7 = fma(v, n7, a0all);
+                r3 = fma(v, n3, a0);
+                r5 = fma(v, n5, a0);
+                r6 = fma(v, n6, a0);
+                r1 = fma(v, p1 * y1, a0);
+                r2 = fma(v, p2 * y2, a0);
+                r4 = fma(v, p3 * y4, a0);
+            }
+            if (path != nullptr) path[t] = r7;
+        }
+        double x0[1] = {r7}, x1[1] = {r3}, x2[1] = {r5}, x3[1] = {r1};
+        store_results<1>(P, node_rel, tile, sb + k, lane, uid, live, x0, x1, x2, last, last,
+                         last ? x3 : nullptr);
+    }
+}
+
 template <int K>
 __device__ __forceinline__ void run_markov(const RecParams &P, const double *__restrict__ vcurves,
                                            int node_rel, int tile, const Tile &T, int sb, int lane)
 {
+    if (P.mk_states > 4) {
+        run_markov9<K>(P, vcurves, node_rel, tile, T, sb, lane);
+        return;
+    }
     constexpr int KM = K < 4 ? K : 4;
     const int node = P.node_begin + node_rel;
     const int shift = node * P.node_step;
@@ -1003,9 +1161,14 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
                         if (shock) run_frac<K, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
                         else run_frac<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
                     }
-                } else if (T.flow == FLOW_MARKOV)
+                } else if (T.flow == FLOW_MARKOV) {
                     run_markov<K>(P, vcurves, node_rel, tile, T, sb, lane);
-                else if (T.flow == FLOW_TABLE)
+                } else if (T.flow == FLOW_THREE) {
+                    if (P.shock[P.node_begin + node_rel] != 1.0)
+                        run_three<K, LDSQ, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                    else
+                        run_three<K, LDSQ, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                } else if (T.flow == FLOW_TABLE)
                     run_scalar<K, 1, LDSQ, false, FLOW_TABLE>(P, s_q, vcurves, node_rel, tile, 1, T,
                                                               T.smax, T.smin, sb, lane);
                 else if (T.kind == KIND_SINGLE)

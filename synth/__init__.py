@@ -43,13 +43,16 @@ TERM = 4          # term assurance (3-state model, Sec. 4.1.3)
 ENDOW = 5         # pure endowment (Sec. 4.1.2)
 ENDOW_ASSUR = 6   # endowment assurance: term assurance + pure endowment
 N_PRODUCTS = 7    # products with closed-form cash flows (0..6)
-CF_TABLE = 7      # single life, cash flows amount x cf[row][t] from a table (Sec. 4.4)
+CF_TABLE = 7      # single life, cash flows amount x cf[row][t] from a table (Sec. 4.6)
 JL_ENDOW = 8      # two-life pure endowment: SA at maturity if both alive (Sec. 4.2.2)
 JL_ASSUR1 = 9     # two-life term assurance, SA on the first death (9-state model, Sec. 4.2.3)
 JL_ASSUR2 = 10    # two-life term assurance, SA on the second death (Sec. 4.2.3)
 TWO_LIFE_INS = (JL_ENDOW, JL_ASSUR1, JL_ASSUR2)
-MARKOV = 11       # one life on an uploaded Markov model (table1 = model; Sec. 4.7)
+MARKOV = 11       # one life on an uploaded Markov model (table1 = model; Sec. 4.5)
 TWO_LIFE = (JL_ANN, REV_ANN, LS_ANN, 8, 9, 10)   # with the two-life endowment and assurances
+JL3_ANN = 12      # joint-life annuity on three lives (2^3 = 8 states, Sec. 4.3)
+LS3_ANN = 13      # last-survivor annuity on three lives (Sec. 4.3)
+THREE_LIFE = (JL3_ANN, LS3_ANN)
 
 ADVANCE = 0       # annuity paid at the start of each month (f = 0)
 ARREARS = 1       # annuity paid at the end of each month (f = 1)
@@ -160,6 +163,9 @@ class Portfolio:
     # w [models][ages][m][m] monthly one-step matrices (row = state at the
     # start of the month) and c [models][m] benefits per unit amount.
     markov: tuple | None = None
+    # Life 3 of the three-life annuities (None when there are none).
+    age3_m: np.ndarray | None = None       # int32 [n]
+    table3: np.ndarray | None = None       # int32 [n]
 
     @property
     def n(self) -> int:
@@ -288,9 +294,12 @@ def portfolio_mixed(rng, n: int, mix=(0.4, 0.2, 0.2, 0.2),
 
 def max_attained_age(p: Portfolio) -> int:
     a = int((p.age1_m + p.term_m).max(initial=0))
-    two = np.isin(p.product, TWO_LIFE)
+    two = np.isin(p.product, TWO_LIFE + THREE_LIFE)
     if two.any():
         a = max(a, int((p.age2_m[two] + p.term_m[two]).max()))
+    three = np.isin(p.product, THREE_LIFE)
+    if three.any():
+        a = max(a, int((p.age3_m[three] + p.term_m[three]).max()))
     return a
 
 
@@ -456,6 +465,9 @@ def random_small(rng, n: int, n_steps: int, n_scen: int = 1, n_nodes: int = 1,
     pf = Portfolio(product=product, age1_m=age1, age2_m=age2, term_m=term,
                    table1=t1, table2=t2, timing=timing, amount=amount,
                    premium=premium)
+    if any(p in THREE_LIFE for p in products):
+        pf.age3_m = rng.integers(0, age_hi, n).astype(np.int32)
+        pf.table3 = rng.integers(0, n_tables, n).astype(np.int32)
     return Workload("random small", Basis(q=q, v=v, shock=sh), pf)
 
 
@@ -547,7 +559,7 @@ def with_cash_flow_tables(rng, pf: Portfolio, frac: float = 0.3, n_rows: int = 5
 
 def phi_models(n_ages: int, loadings=(1.0, 1.3), recovery: float = 0.08,
                incidence_scale: float = 0.3) -> tuple:
-    """Permanent-health-insurance models (Sec. 4.7: a reversible state model,
+    """Permanent-health-insurance models (Sec. 4.5: a reversible state model,
     not upper triangular): states healthy, sick, dead; monthly sickness
     incidence proportional to the GM death probability, recovery at a fixed
     monthly rate, sick lives dying at twice the healthy rate; benefit

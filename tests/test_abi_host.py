@@ -56,7 +56,8 @@ def test_portfolio_checks(rr):
     cases = {
         "term": ("term_m", 7, 601, "policy 7 term 601"),
         "term0": ("term_m", 3, 0, "policy 3 term 0"),
-        "product": ("product", 11, 13, "policy 11 has unknown product 13"),
+        "product": ("product", 11, 14, "policy 11 has unknown product 14"),
+        "three": ("product", 12, synth.LS3_ANN, "three-life products need age3_m and table3"),
         "age": ("age1_m", 5, n_ages, "policy 5 age"),
         "table": ("table1", 2, 3, "policy 2 table1 3"),
         "timing": ("timing", 9, 3, "policy 9 timing 3"),
@@ -72,6 +73,16 @@ def test_portfolio_checks(rr):
     two.product[1] = synth.LS_ANN
     two.age2_m[1] = n_ages - 5
     assert "second age" in rr.check_portfolio(two, 600, n_ages, 3)
+    three = w.portfolio.subset(np.arange(20))
+    three.product[2] = synth.JL3_ANN
+    three.age3_m = np.zeros(20, np.int32)
+    three.table3 = np.zeros(20, np.int32)
+    assert rr.check_portfolio(three, 600, n_ages, 3) == ""
+    three.age3_m[2] = n_ages - 5
+    assert "policy 2 third age" in rr.check_portfolio(three, 600, n_ages, 3)
+    three.age3_m[2] = 0
+    three.table3[2] = 3
+    assert "policy 2 table3 3" in rr.check_portfolio(three, 600, n_ages, 3)
 
 
 def test_basis_checks(rr):
@@ -178,8 +189,8 @@ def test_cash_flow_table_checks(rr):
     assert "is not finite" in rr.check_portfolio(bad, 120, n_ages, 2)
     bad = ok.subset(np.arange(ok.n)); bad.cf = None
     assert "need cf_row and cf" in rr.check_portfolio(bad, 120, n_ages, 2)
-    bad = ok.subset(np.arange(ok.n)); bad.product[i] = 12
-    assert f"policy {i} has unknown product 12" in rr.check_portfolio(bad, 120, n_ages, 2)
+    bad = ok.subset(np.arange(ok.n)); bad.product[i] = 14
+    assert f"policy {i} has unknown product 14" in rr.check_portfolio(bad, 120, n_ages, 2)
 
 
 def test_markov_policy_checks(rr):

@@ -67,12 +67,12 @@ def compare(ctx, w, all_states=True):
 
 
 def wide_basis_workload(seed, n, n_steps, n_scen, n_nodes, n_tables=10, node_step=7,
-                        markov=True, frac=0.0):
+                        markov=True, frac=0.0, products=ALL_LIFE_PRODUCTS):
     """Every product on n_tables random tables (more than LDS holds), with
     cash-flow tables, payment patterns and permanent-health Markov policies."""
     rng = np.random.default_rng(seed)
     w = synth.random_small(rng, n=n, n_steps=n_steps, n_scen=n_scen, n_nodes=n_nodes, shock=True,
-                           products=ALL_LIFE_PRODUCTS, n_tables=n_tables)
+                           products=products, n_tables=n_tables)
     assert w.basis.q.size > LDS_TABLE_DOUBLES
     pf = synth.with_cash_flow_tables(rng, w.portfolio, frac=0.1, n_rows=4)
     pf = synth.with_payment_patterns(rng, pf, 0.4, 0.3)
@@ -126,7 +126,8 @@ def test_tables_in_device_memory_gm_long_terms(ctx, rr):
 
 
 def test_tables_in_device_memory_fractional(ctx, rr):
-    w = wide_basis_workload(2200, n=400, n_steps=100, n_scen=19, n_nodes=2, frac=0.37, markov=False)
+    w = wide_basis_workload(2200, n=600, n_steps=100, n_scen=19, n_nodes=2, frac=0.37, markov=False,
+                            products=tuple(range(7)))
     assert (w.portfolio.timing == synth.FRACTIONAL).sum() > 20
     upload(ctx, w)
     ctx.set_option(rr.OPT_BLOCK_K, 8)

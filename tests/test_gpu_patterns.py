@@ -286,7 +286,7 @@ def test_two_life_insurance_paths(ctx):
 
 
 # ---------------------------------------------------------------------------
-# Policies on uploaded Markov models (Sec. 4.7)
+# Policies on uploaded Markov models (Sec. 4.5)
 # ---------------------------------------------------------------------------
 def markov_workload(seed, n, n_steps, n_scen, n_nodes, models=None, frac=0.4, node_step=7):
     rng = np.random.default_rng(seed)

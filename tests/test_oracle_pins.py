@@ -498,7 +498,7 @@ def test_payment_patterns_node_shift_equals_path(step):
 
 
 # --------------------------------------------------------------------------
-# Cash-flow tables (one life, c_t = amount x cf[row][t], Sec. 4.4)
+# Cash-flow tables (one life, c_t = amount x cf[row][t], Sec. 4.6)
 # --------------------------------------------------------------------------
 def _cf_pf(rows, row_of, age1, term, amount, premium=0.0, table1=0):
     n = np.broadcast(np.asarray(row_of), np.asarray(age1), np.asarray(term), np.asarray(amount),
@@ -677,7 +677,7 @@ def test_scenario_average_is_the_reserve_on_the_mean_discount_curve():
 
 
 # --------------------------------------------------------------------------
-# Uploaded Markov models (Sec. 4.7: reversible, not upper-triangular W)
+# Uploaded Markov models (Sec. 4.5: reversible, not upper-triangular W)
 # --------------------------------------------------------------------------
 def _mk_pf(models, model, age1, term, amount, premium=0.0):
     n = np.broadcast(np.asarray(model), np.asarray(age1), np.asarray(term), np.asarray(amount),
@@ -902,3 +902,170 @@ def test_reduced_mode_on_the_nested_workload_sample():
     sample of policies and scenarios, reduced = dense."""
     w = synth.config_c3(n=300, n_scen=6)
     reduced_vs_dense(w, 12)
+
+
+# --------------------------------------------------------------------------
+# Three lives (Sec. 4.3: Kronecker W of 2^3 states)
+# --------------------------------------------------------------------------
+from synth import JL3_ANN, LS3_ANN  # noqa: E402
+
+
+def make_pf3(product, ages, term, amount=12.0, premium=0.0, timing=ARREARS, tables=(0, 0, 0)):
+    pf = make_pf(product, ages[0], term, amount=amount, premium=premium, timing=timing,
+                 age2=ages[1], table1=tables[0], table2=tables[1])
+    n = pf.n
+    pf.age3_m = np.full(n, ages[2], np.int32)
+    pf.table3 = np.full(n, tables[2], np.int32)
+    return pf
+
+
+@pytest.mark.parametrize("timing", [ADVANCE, ARREARS])
+def test_three_lives_reduce_to_two_when_life_three_never_dies(timing):
+    """q3 = 0: the three-life joint-life annuity is the two-life one exactly,
+    and the last-survivor annuity the annuity certain (1 - v^n)/i."""
+    q = np.stack([gm(), gm(1.3), np.zeros(N_AGES)])
+    S = 240
+    b = basis(q, np.full(S, V_FLAT))
+    j3 = make_pf3([JL3_ANN, LS3_ANN], (700, 760, 500), S, timing=timing, tables=(0, 1, 2))
+    j2 = make_pf([JL_ANN], 700, S, timing=timing, age2=760, table1=0, table2=1)
+    r3 = r0(b, j3)
+    assert r3[0, 0] == pytest.approx(r0(b, j2)[0, 0], rel=1e-14)
+    i = 1.0 / V_FLAT - 1.0
+    cert = (1.0 - V_FLAT ** S) / i * (1.0 / V_FLAT if timing == ADVANCE else 1.0)
+    assert r3[1, 0] == pytest.approx(cert, rel=1e-13)
+
+
+def test_three_lives_with_life_three_dead_at_once():
+    """q3 = 1: an arrears joint-life annuity on three lives pays nothing and
+    the last-survivor annuity is the two-life last-survivor annuity."""
+    q = np.stack([gm(), gm(0.8), np.ones(N_AGES)])
+    S = 180
+    b = basis(q, np.full(S, V_FLAT))
+    r3 = r0(b, make_pf3([JL3_ANN, LS3_ANN], (650, 700, 400), S, tables=(0, 1, 2)))
+    ls2 = r0(b, make_pf([LS_ANN], 650, S, age2=700, table1=0, table2=1))
+    assert r3[0, 0] == 0.0
+    assert r3[1, 0] == pytest.approx(ls2[0, 0], rel=1e-13)
+
+
+def test_three_lives_inclusion_exclusion():
+    """Last survivor of three = sum of single-life annuities - sum of the
+    pairs' joint-life annuities + the three-life joint-life annuity (the
+    indicator that some life is alive, expanded); random mortality, random
+    curve, both timings."""
+    rng = np.random.default_rng(41)
+    q = rng.uniform(0.0, 0.05, (3, 1200))
+    S = 150
+    v = rng.uniform(0.99, 1.0, S)
+    b = basis(q, v)
+    ages = (300, 420, 555)
+    for timing in (ADVANCE, ARREARS):
+        ls3 = r0(b, make_pf3([LS3_ANN], ages, S, timing=timing, tables=(0, 1, 2)))[0, 0]
+        jl3 = r0(b, make_pf3([JL3_ANN], ages, S, timing=timing, tables=(0, 1, 2)))[0, 0]
+        single = sum(r0(b, make_pf([SL_ANN], ages[l], S, timing=timing, table1=l))[0, 0] for l in range(3))
+        pairs = sum(r0(b, make_pf([JL_ANN], ages[a], S, timing=timing, age2=ages[c], table1=a,
+                                   table2=c))[0, 0] for a, c in ((0, 1), (0, 2), (1, 2)))
+        assert ls3 == pytest.approx(single - pairs + jl3, rel=1e-12)
+
+
+def test_three_lives_symmetric_and_states():
+    """The reserves in the all-alive state do not depend on how the lives are
+    numbered; the last-survivor reserve with life 3 dead (slot 1) is the
+    two-life last-survivor reserve of lives 1 and 2 and with only life 1
+    alive (slot 3) the single-life annuity."""
+    q = np.stack([gm(), gm(0.7), gm(1.2)])
+    S = 200
+    b = basis(q, np.full(S, V_FLAT))
+    base = r0(b, make_pf3([JL3_ANN, LS3_ANN], (600, 680, 720), S, premium=1.5, tables=(0, 1, 2)))
+    perm = r0(b, make_pf3([JL3_ANN, LS3_ANN], (720, 600, 680), S, premium=1.5, tables=(2, 0, 1)))
+    np.testing.assert_allclose(perm[:, 0], base[:, 0], rtol=1e-13)
+    ls2 = r0(b, make_pf([LS_ANN], 600, S, age2=680, table1=0, table2=1))[0, 0]
+    sl1 = r0(b, make_pf([SL_ANN], 600, S, table1=0))[0, 0]
+    assert base[1, 1] == pytest.approx(ls2, rel=1e-13)
+    assert base[1, 3] == pytest.approx(sl1, rel=1e-13)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_three_lives_recurrence_equals_summation(seed):
+    rng = np.random.default_rng(60 + seed)
+    w = synth.random_small(rng, n=12, n_steps=40, n_scen=2, n_nodes=2, shock=True,
+                           products=(JL3_ANN, LS3_ANN))
+    w.basis.frac = 0.3
+    w.portfolio.timing = rng.integers(0, 3, w.portfolio.n).astype(np.int32)
+    b, pf = w.basis, w.portfolio
+    for i in range(pf.n):
+        for node in (0, 1):
+            if pf.term_m[i] - 12 * node <= 0:
+                continue
+            summ = oracle.reserve_path_summation(b, pf, i, node=node, scen=1)
+            path, off = oracle.reserve_paths(b, pf, node=node, scen=1)
+            np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=1e-12, atol=1e-12)
+
+
+def test_reduced_mode_three_lives():
+    rng = np.random.default_rng(870)
+    w = synth.random_small(rng, n=200, n_steps=120, n_scen=3, n_nodes=2, shock=True,
+                           products=(JL3_ANN, LS3_ANN, SL_ANN, LS_ANN))
+    w.basis.frac = 0.45
+    pf = w.portfolio
+    pf.timing = rng.integers(0, 3, pf.n).astype(np.int32)
+    pf.premium = np.where(rng.uniform(size=pf.n) < 0.5, pf.premium, 0.0)
+    reduced_vs_dense(synth.Workload("three", w.basis, pf), 12)
+
+
+# --------------------------------------------------------------------------
+# Uploaded models of up to nine states
+# --------------------------------------------------------------------------
+def two_life_assurance_tables(q, gap, model):
+    """The 9-state two-life assurance model of Sec. 4.2.3 as an uploaded
+    table by the attained age x of life 1, life 2 being x + gap."""
+    n_ages = q.shape[1] - gap
+    W = np.zeros((1, n_ages, 9, 9))
+    for x in range(n_ages):
+        W[0, x] = oracle.build_w(2, 3, [q[0, x], q[1, x + gap]])
+    c = {JL_ASSUR1: [0, 1, 0, 1, 1, 0, 0, 0, 0], JL_ASSUR2: [0, 0, 0, 0, 1, 1, 0, 1, 0]}[model]
+    return W, np.asarray([c], np.float64)
+
+
+@pytest.mark.parametrize("model", [JL_ASSUR1, JL_ASSUR2])
+def test_nine_state_upload_reproduces_two_life_assurances(model):
+    """The paper's 9-state matrix uploaded as a table (life 2 a fixed 60
+    months older) gives the built-in first- and second-death assurances."""
+    rng = np.random.default_rng(880 + model)
+    q = np.stack([gm(), gm(1.4)])
+    S, gap = 300, 60
+    W, c = two_life_assurance_tables(q, gap, model)
+    b = basis(q, rng.uniform(0.995, 1.0, S))
+    ages = rng.integers(300, 1000, 20)
+    prem = rng.uniform(0.0, 40.0, 20)
+    built = make_pf([model] * 20, ages, S, amount=1e4, premium=prem, age2=ages + gap, table1=0, table2=1)
+    up = make_pf([MARKOV] * 20, ages, S, amount=1e4, premium=prem, table1=0)
+    up.markov = (W, c)
+    rb = oracle.reserves(b, built)
+    ru = oracle.reserves(b, up)
+    np.testing.assert_allclose(ru["r_all"][..., 0], rb["r_all"][..., 0], rtol=1e-13,
+                               atol=1e-13 * float(rb["gross"].max()))
+    red = oracle.reserves_reduced(b, up)
+    np.testing.assert_allclose(red["r_all"][..., 0], ru["r_all"][..., 0], rtol=1e-13,
+                               atol=1e-13 * float(rb["gross"].max()))
+
+
+@pytest.mark.parametrize("m", [5, 9])
+def test_large_markov_recurrence_equals_summation(m):
+    rng = np.random.default_rng(890 + m)
+    n_ages = 400
+    raw = rng.uniform(0.0, 1.0, (2, n_ages, m, m))
+    raw[:, :, m - 1, :] = 0.0
+    raw[:, :, m - 1, m - 1] = 1.0
+    W = raw / raw.sum(axis=3, keepdims=True)
+    c = rng.uniform(-1.0, 2.0, (2, m))
+    pf = make_pf([MARKOV] * 6, rng.integers(0, 300, 6), rng.integers(20, 90, 6), amount=100.0,
+                 premium=rng.uniform(0, 2, 6), table1=rng.integers(0, 2, 6))
+    pf.markov = (W, c)
+    b = basis(np.zeros((1, n_ages)), rng.uniform(0.99, 1.0, (1, 2, 90)))
+    for i in range(pf.n):
+        summ = oracle.reserve_path_summation(b, pf, i, scen=1)
+        path, off = oracle.reserve_paths(b, pf, scen=1)
+        np.testing.assert_allclose(path[off[i]:off[i + 1]], summ[:, 0], rtol=1e-12, atol=1e-12)
+    dense = oracle.reserves(b, pf)
+    red = oracle.reserves_reduced(b, pf)
+    np.testing.assert_allclose(red["r_all"], dense["r_all"], rtol=1e-13, atol=1e-11)
