@@ -327,6 +327,30 @@ int rr_path_size(rr_ctx *ctx, int32_t node, int32_t node_step_m, int64_t *n_out)
  */
 int rr_reserve_recurrence(rr_ctx *ctx, const rr_run *run, const rr_outputs *out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): rr_reserve_recurrence with the same run, outputs and results, except
+ * that it allocates nothing.  Its work lists, queue counters and partial
+ * totals live in one static device array of 64 MiB per GPU, which every call
+ * on that GPU shares (from any context) and which is held until the process
+ * ends.  Consequences:
+ *   - a run whose scratch exceeds 64 MiB is RR_ERANGE (the partial totals take
+ *     8 bytes x nodes x tiles of 64 policies x scenarios when totals or
+ *     statistics are requested: e.g. 10,000 policies x 60 nodes x 500
+ *     scenarios fits, 500,000 policies x 1,000 scenarios does not);
+ *   - calls that overlap on one GPU (two streams, or two host threads) race on
+ *     the array: the caller serialises them;
+ *   - RR_OUT_PATH is RR_EINVAL (its offsets need an upload);
+ *   - no autotuning (it builds and uploads candidate plans): the launch shape
+ *     is the pinned options, else the shape an earlier rr_reserve_recurrence
+ *     call chose for this run shape, else K = 16, J = 2, one workgroup per CU;
+ *   - no graph replay and no kernel timing; the work lists are copied from
+ *     host memory the context keeps on every call (a few tens of KB).
+ * The basis and portfolio uploads still allocate: call them beforehand.
+ */
+int rr_reserve_recurrence_noalloc(rr_ctx *ctx, const rr_run *run, const rr_outputs *out);
+
 /* Options (rr_set_option). */
 #define RR_OPT_BLOCK_K      1   /* scenarios per lane: 0 = autotune, or 1,2,4,8,16,32 */
 #define RR_OPT_WG_PER_CU    2   /* persistent workgroups per CU: 0 = autotune, 1..8 */

@@ -56,6 +56,7 @@ EXPORTS = (
     "rr_basis_generate_vasicek", "rr_curves_generate_vasicek", "rr_vasicek_curves",
     "rr_node_surrogate_train", "rr_node_surrogate_infer", "rr_node_surrogate_get_weights",
     "rr_node_surrogate_set_weights", "rr_node_expected_reserves", "rr_markov_upload",
+    "rr_reserve_recurrence_noalloc",
 )
 
 # Surrogate dimensions (include/rr.h).
@@ -214,6 +215,8 @@ def load_library(path: str = LIB_PATH):
         "rr_node_surrogate_set_weights": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "rr_node_expected_reserves": ([vp, ctypes.POINTER(Run), vp, vp], ctypes.c_int),
         "rr_markov_upload": ([vp, ctypes.POINTER(Markov)], ctypes.c_int),
+        "rr_reserve_recurrence_noalloc": ([vp, ctypes.POINTER(Run), ctypes.POINTER(Outputs)],
+                                          ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -428,6 +431,33 @@ class Context:
         o = Outputs(_ptr(outputs.get("r0")), _ptr(outputs.get("totals")), _ptr(path),
                     0 if path is None else path.numel(), _ptr(outputs.get("stats")))
         self._check(self.lib.rr_reserve_recurrence(self.h, ctypes.byref(run), ctypes.byref(o)))
+        return outputs
+
+    def reserve_recurrence_noalloc(self, node_begin=0, node_count=None, scen_begin=0,
+                                   scen_count=None, node_step=12, outputs=None, tail=0.005):
+        """rr_reserve_recurrence_noalloc: the same valuation with the library's
+        static scratch (no device allocation); outputs as for reserve_recurrence
+        (a path is RR_EINVAL)."""
+        node_count = self.n_nodes - node_begin if node_count is None else node_count
+        scen_count = self.n_scen - scen_begin if scen_count is None else scen_count
+        if outputs is None:
+            outputs = self.alloc_outputs(node_count, scen_count)
+        mask = 0
+        if outputs.get("r0") is not None:
+            mask |= OUT_R0
+            if outputs["r0"].dim() == 4:
+                mask |= OUT_ALL_STATES
+        if outputs.get("totals") is not None:
+            mask |= OUT_TOTALS
+        if outputs.get("stats") is not None:
+            mask |= OUT_STATS
+        if outputs.get("path") is not None:     # the library rejects it
+            mask |= OUT_PATH
+        run = Run(node_begin, node_count, scen_begin, scen_count, node_step, mask, tail)
+        path = outputs.get("path")
+        o = Outputs(_ptr(outputs.get("r0")), _ptr(outputs.get("totals")), _ptr(path),
+                    0 if path is None else path.numel(), _ptr(outputs.get("stats")))
+        self._check(self.lib.rr_reserve_recurrence_noalloc(self.h, ctypes.byref(run), ctypes.byref(o)))
         return outputs
 
     def sync(self):

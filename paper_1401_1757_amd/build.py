@@ -24,7 +24,7 @@ DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++
 HOST_FLAGS = ["-x", "c++", "-O2", "-fPIC", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-Wall"]
 
 DEVICE_SOURCES = ["rr_kernels.hip", "rr_kernels_pat.hip", "rr_kernels_ring.hip", "rr_mlp.hip",
-                  "rr_scen.hip"]
+                  "rr_scen.hip", "rr_noalloc.hip"]
 HOST_SOURCES = ["rr_host.cpp", "rr_surrogate.cpp"]
 
 

@@ -52,11 +52,19 @@ struct Plan {
     int n_queues = 1;
     DevBuf<Item> items;
     DevBuf<int> qbeg;
-    // Work lists and queue counters in memory the plan does not own; used
-    // instead of items/qbeg and the context's counters when set.
+    // Work lists and queue counters in memory the plan does not own (the
+    // static scratch of the allocation-free entry point); used instead of
+    // items/qbeg and the context's counters when set.
     const Item *items_ext = nullptr;
     const int *qbeg_ext = nullptr;
     int *counters_ext = nullptr;
+};
+
+// A plan's work lists on the host (the allocation-free entry point copies
+// them into its static scratch on every call).
+struct HostPlan {
+    std::vector<Item> items;
+    std::vector<int> qbeg;
 };
 
 struct PlanKey {
@@ -162,6 +170,9 @@ struct rr_ctx {
                                           // and in-place regeneration)
 
     // run resources
+    double *scratch = nullptr;            // static device scratch of rr_reserve_recurrence_noalloc
+                                          // on this device (shared by every context on it)
+    std::map<rr::host::PlanKey, rr::host::HostPlan> host_plans;
     DevBuf<int> counters;
     DevBuf<double> partial;
     DevBuf<double> totals_tmp;

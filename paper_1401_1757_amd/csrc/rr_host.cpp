@@ -330,6 +330,9 @@ extern "C" int rr_create(rr_ctx **out, int device, uint64_t stream)
                                                               : prop.sharedMemPerBlock;
     c->stream = (hipStream_t)(uintptr_t)stream;   // 0 = the null stream
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) return RR_EDEVICE;
+    void *scratch = nullptr;   // static scratch of rr_reserve_recurrence_noalloc on this device
+    if (noalloc_scratch(device, &scratch) != hipSuccess) return RR_EDEVICE;
+    c->scratch = static_cast<double *>(scratch);
     if (c->counters.alloc(MAX_QUEUES + 1) != hipSuccess) return RR_ENOMEM;
     if (hipMemset(c->counters.p, 0, sizeof(int) * (MAX_QUEUES + 1)) != hipSuccess) return RR_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return RR_EDEVICE;
@@ -1683,6 +1686,119 @@ extern "C" int rr_reserve_recurrence(rr_ctx *c, const rr_run *run, const rr_outp
         return RR_OK;
     }
     return enqueue_run(c, run, out, pl, partial, totals, c->stream, c->opt_timing != 0);
+}
+
+// Launch shape of the allocation-free entry point, which cannot autotune
+// (the autotuner builds and uploads candidate plans): pinned options, else
+// the shape the autotuner chose for this run shape on an earlier
+// rr_reserve_recurrence call, else 16 scenarios x 2 tiles per wavefront at
+// one workgroup per CU (fewer scenarios: the largest K that fits).
+static LaunchCfg noalloc_config(rr_ctx *c, const rr_run *run)
+{
+    const int win = (c->opt_curve_share == 2 || c->opt_curve_share == -1) ? 1 : 0;
+    int K = c->opt_k, J = c->opt_j, wg = c->opt_wg;
+    if (run->scen_count == 1) { K = 1; J = 1; }
+    if (K && J && !supported_kj(K, J)) J = 1;
+    if (K && J && wg)
+        return LaunchCfg{K, J, wg, (c->opt_ring == 1 && ring_ok(c, K, J)) ? 1 : 0, win};
+    TuneKey key{run->node_count, run->scen_count, (run->out_mask & RR_OUT_ALL_STATES) ? 4 : 1, 0, c->gen};
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end() && (!K || it->second.K == K) && (!J || it->second.J == J) &&
+        (!wg || it->second.wg == wg))
+        return it->second;
+    if (!K) {
+        K = 16;
+        while (K > 1 && K > run->scen_count) K /= 2;
+    }
+    if (!J) J = supported_kj(K, 2) ? 2 : 1;
+    return LaunchCfg{K, J, wg ? wg : 1, 0, win};
+}
+
+extern "C" int rr_reserve_recurrence_noalloc(rr_ctx *c, const rr_run *run, const rr_outputs *out)
+{
+    if (!c) return RR_EINVAL;
+    if (run && (run->out_mask & RR_OUT_PATH))
+        return fail(c, RR_EINVAL, "rr_reserve_recurrence_noalloc does not write paths (RR_OUT_PATH)");
+    int rc = check_run_outputs(c, run, out);
+    if (rc) return rc;
+    if (!c->scratch) return fail(c, RR_EDEVICE, "no static scratch on device %d", c->device);
+    if (run->node_count == 0 || run->scen_count == 0) return RR_OK;
+    const uint32_t mask = run->out_mask;
+    const long long ns = (long long)run->node_count * run->scen_count;
+    const bool need_tot = (mask & (RR_OUT_TOTALS | RR_OUT_STATS)) != 0;
+    const LaunchCfg cfg = noalloc_config(c, run);
+    const int queues = c->opt_xcd ? MAX_QUEUES : 1;
+    PlanKey key{run->node_begin, run->node_count, run->scen_begin, run->scen_count,
+                run->node_step_m, cfg.K, cfg.J, queues, c->gen, cfg.wg};
+    auto it = c->host_plans.find(key);
+    if (it == c->host_plans.end()) {
+        HostPlan hp;
+        plan_lists(c, run, cfg, queues, hp.items, hp.qbeg);
+        it = c->host_plans.emplace(key, std::move(hp)).first;
+    }
+    const HostPlan &hp = it->second;
+    // Layout of the scratch, in doubles, each part 256-byte aligned:
+    // counters, queue offsets, work items, totals (statistics without
+    // RR_OUT_TOTALS), per-tile partial totals and the chunked-totals scratch.
+    long long off = 0;
+    auto take = [&](long long doubles) {
+        const long long o = off;
+        off += (doubles + 31) / 32 * 32;
+        return o;
+    };
+    const long long o_cnt = take((MAX_QUEUES + 2) / 2);
+    const long long o_qbeg = take(((long long)hp.qbeg.size() + 1) / 2);
+    static_assert(sizeof(Item) % sizeof(double) == 0, "work items are whole doubles");
+    const long long o_items = take((long long)hp.items.size() * (long long)(sizeof(Item) / sizeof(double)));
+    const bool own_tot = need_tot && !(mask & RR_OUT_TOTALS);
+    const long long o_tot = own_tot ? take(ns) : -1;
+    const long long np = need_tot ? ns * c->n_tiles + totals_scratch_doubles(run->node_count, c->n_tiles,
+                                                                               run->scen_count)
+                                  : 0;
+    const long long o_part = need_tot ? take(np) : -1;
+    const long long cap = (long long)(NOALLOC_SCRATCH_BYTES / sizeof(double));
+    if (off > cap)
+        return fail(c, RR_ERANGE,
+                    "this run needs %.1f MiB of scratch; rr_reserve_recurrence_noalloc has %lld MiB "
+                    "(split the run into fewer nodes or scenarios, or use rr_reserve_recurrence)",
+                    off * 8.0 / (1 << 20), (long long)(NOALLOC_SCRATCH_BYTES >> 20));
+    double *S = c->scratch;
+    double *totals = need_tot ? ((mask & RR_OUT_TOTALS) ? out->totals : S + o_tot) : nullptr;
+    const hipStream_t st = c->stream;
+    if (c->n_user == 0) {
+        if (totals) HIPCHK(c, launch_fill(totals, ns, 0.0, st));
+        if (mask & RR_OUT_STATS) HIPCHK(c, launch_fill(out->stats, 2LL * run->node_count, 0.0, st));
+        return RR_OK;
+    }
+    // The array keeps the contents of the last call on this device: the queue
+    // counters must start at zero (a kernel, not a memset node).
+    int *counters = reinterpret_cast<int *>(S + o_cnt);
+    HIPCHK(c, launch_fill_int(counters, MAX_QUEUES + 1, 0, st));
+    HIPCHK(c, hipMemcpyAsync(S + o_qbeg, hp.qbeg.data(), hp.qbeg.size() * sizeof(int),
+                             hipMemcpyHostToDevice, st));
+    if (!hp.items.empty())
+        HIPCHK(c, hipMemcpyAsync(S + o_items, hp.items.data(), hp.items.size() * sizeof(Item),
+                                 hipMemcpyHostToDevice, st));
+    Plan pl;
+    pl.K = cfg.K;
+    pl.J = cfg.J;
+    pl.n_items = (int)hp.items.size();
+    pl.n_queues = queues;
+    pl.items_ext = reinterpret_cast<const Item *>(S + o_items);
+    pl.qbeg_ext = reinterpret_cast<const int *>(S + o_qbeg);
+    pl.counters_ext = counters;
+    pl.wg_per_cu = cfg.wg;
+    pl.ring = cfg.ring;
+    pl.win = cfg.win;
+    const int waves_per_wg = WG_THREADS / 64;
+    pl.grid = std::max(1, std::min(c->n_cu * cfg.wg, (pl.n_items + waves_per_wg - 1) / waves_per_wg));
+    c->last_k = cfg.K;
+    c->last_j = cfg.J;
+    c->last_wg = cfg.wg;
+    c->last_ring = cfg.ring;
+    c->last_win = cfg.win;
+    c->last_qlds = tables_in_lds(c) ? 1 : 0;
+    return enqueue_run(c, run, out, &pl, need_tot ? S + o_part : nullptr, totals, st, false);
 }
 
 extern "C" int rr_kernel_times(rr_ctx *c, double *ms, int32_t cap, int32_t *count)

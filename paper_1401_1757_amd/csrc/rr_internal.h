@@ -180,6 +180,11 @@ hipError_t launch_mean_curve(const double *v, int n_steps, int scen_pad, int nod
                              int node_count, int scen_begin, int scen_count, double *D,
                              double *vbar, hipStream_t stream);
 int max_lds_tables_doubles();
+// Static device scratch of rr_reserve_recurrence_noalloc (rr_noalloc.hip):
+// its device address on `device`, the current device (looked up once per
+// device); NOALLOC_SCRATCH_BYTES is its size.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+hipError_t noalloc_scratch(int device, void **ptr);
 bool supported_k(int K);
 bool supported_kj(int K, int J);   // (scenarios, policies) per lane
 
