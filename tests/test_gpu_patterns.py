@@ -358,7 +358,7 @@ def test_markov_invalid_uploads(ctx, rr):
     with pytest.raises(rr.RRError, match="benefit"):
         ctx.markov_upload(W, cb)
     with pytest.raises(rr.RRError, match="n_states"):
-        ctx.markov_upload(np.zeros((1, 10, 5, 5)), np.zeros((1, 5)))
+        ctx.markov_upload(np.zeros((1, 10, 10, 10)), np.zeros((1, 10)))
     ctx.markov_upload(W, c)
     pf2 = pf.subset(np.arange(pf.n))
     i = int(np.flatnonzero(pf2.product == synth.MARKOV)[0])
@@ -450,3 +450,157 @@ def test_fractional_invalid(ctx, rr):
     out = ctx.alloc_outputs(1, 2)
     with pytest.raises(rr.RRError):
         ctx.reserve_recurrence(0, 1, 0, 2, 12, out)
+
+
+# ---------------------------------------------------------------------------
+# Uploaded models of five to nine states (Sec. 4.5; the 9-state two-life
+# model of Sec. 4.2.3 as a table)
+# ---------------------------------------------------------------------------
+def nine_state_tables(q, gap, benefit):
+    """The 9-state two-life assurance model by the attained age x of life 1,
+    life 2 being x + gap (Kronecker product of the 3-state life models)."""
+    n_ages = q.shape[1] - gap
+    W = np.zeros((1, n_ages, 9, 9))
+    for x in range(n_ages):
+        W[0, x] = oracle.build_w(2, 3, [q[0, x], q[1, x + gap]])
+    return W, np.asarray([benefit], np.float64)
+
+
+@pytest.mark.parametrize("model", [synth.JL_ASSUR1, synth.JL_ASSUR2])
+def test_nine_state_upload_equals_two_life_assurance(ctx, model):
+    """The same policies as built-in first- or second-death assurances and as
+    MARKOV policies on the uploaded 9-state table: equal state-0 reserves
+    (1e-13), both against the oracle."""
+    rng = np.random.default_rng(1700 + model)
+    gap, S, n = 60, 240, 150
+    q = synth.mortality_tables(1500, [1.0, 1.3])
+    benefit = {synth.JL_ASSUR1: [0, 1, 0, 1, 1, 0, 0, 0, 0],
+               synth.JL_ASSUR2: [0, 0, 0, 0, 1, 1, 0, 1, 0]}[model]
+    W, c = nine_state_tables(q, gap, benefit)
+    ages = rng.integers(300, 1100, n).astype(np.int32)
+    common = dict(age1_m=np.concatenate([ages, ages]), age2_m=np.concatenate([ages + gap, ages]),
+                  term_m=np.full(2 * n, S, np.int32), table1=np.concatenate([np.zeros(n, np.int32),
+                                                                             np.zeros(n, np.int32)]),
+                  table2=np.ones(2 * n, np.int32), timing=np.ones(2 * n, np.int32),
+                  amount=np.tile(rng.uniform(1e3, 1e5, n), 2), premium=np.tile(rng.uniform(0, 50, n), 2))
+    pf = synth.Portfolio(product=np.array([model] * n + [synth.MARKOV] * n, np.int32), **common)
+    pf.markov = (W, c)
+    v = rng.uniform(0.995, 1.0, (2, 9, S))
+    w = synth.Workload("nine states", synth.Basis(q=q, v=v, shock=np.array([1.0, 1.04])), pf)
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.markov_upload(W, c)
+    ctx.portfolio_upload(pf)
+    _say(f"nine-state table vs built-in {model}")
+    out = ctx.alloc_outputs(1, 9, all_states=True)
+    ctx.reserve_recurrence(0, 1, 0, 9, 12, out)
+    torch.cuda.synchronize()
+    got = to_np(out["r0"])
+    ref = oracle.reserves(w.basis, pf, 0, 1, 0, 9, 12)
+    assert_states_close(got, ref["r_all"], ref["gross"])
+    built, up = got[0, :n, :, 0], got[0, n:, :, 0]
+    scale = np.maximum(np.abs(built), ref["gross"][0, :n])
+    assert np.all(np.abs(up - built) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("m,K", [(5, 8), (9, 1), (9, 4), (9, 16), (7, 32)])
+def test_large_random_markov_models(ctx, rr, m, K):
+    """Random reversible models of m states beside every other kind of
+    tile, every state slot, two nodes; paths for K = 1."""
+    rng = np.random.default_rng(1800 + m + K)
+    n_ages = 900 + 90 + 1
+    raw = rng.uniform(0.0, 1.0, (2, n_ages, m, m))
+    raw[:, :, m - 1, :] = 0.0
+    raw[:, :, m - 1, m - 1] = 1.0
+    W = raw / raw.sum(axis=3, keepdims=True)
+    c = rng.uniform(-1.0, 2.0, (2, m))
+    w = markov_workload(1801 + m, n=400, n_steps=90, n_scen=2 * K + 3, n_nodes=2, models=(W, c),
+                        frac=0.3, node_step=12)
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.markov_upload(W, c)
+    ctx.portfolio_upload(pf)
+    ctx.set_option(rr.OPT_BLOCK_K, K)
+    _say(f"random {m}-state models K={K}")
+    compare(ctx, w)
+    if K == 1:
+        for node, scen in ((0, 2), (1, 4)):
+            po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=node, node_step=12)
+            po["path"].fill_(float("nan"))
+            ctx.reserve_recurrence(node, 1, scen, 1, 12, po)
+            torch.cuda.synchronize()
+            path, off = oracle.reserve_paths(b, pf, node=node, scen=scen, node_step=12)
+            ref = oracle.reserves(b, pf, node, 1, scen, 1, 12)
+            gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+            assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
+
+
+# ---------------------------------------------------------------------------
+# Three lives (Sec. 4.3)
+# ---------------------------------------------------------------------------
+THREE = (synth.JL3_ANN, synth.LS3_ANN)
+
+
+def three_life_workload(seed, n, n_steps, n_scen, n_nodes, node_step=7, products=None):
+    rng = np.random.default_rng(seed)
+    products = products or THREE + (synth.SL_ANN, synth.JL_ANN, synth.LS_ANN, synth.TERM,
+                                     synth.JL_ASSUR2)
+    w = synth.random_small(rng, n=n, n_steps=n_steps, n_scen=n_scen, n_nodes=n_nodes, shock=True,
+                           products=products, n_tables=3)
+    pf = synth.with_payment_patterns(rng, w.portfolio, 0.3, 0.2)
+    three = np.isin(pf.product, THREE)
+    pf.premium = np.where(three & (rng.uniform(size=pf.n) < 0.5), 0.0, pf.premium)
+    return synth.Workload("three lives", w.basis, pf, node_step_m=node_step)
+
+
+@pytest.mark.parametrize("K,J", [(1, 1), (2, 1), (4, 1), (8, 2), (16, 1), (16, 4), (32, 1)])
+def test_three_life_annuities_with_other_kinds(ctx, rr, K, J):
+    """Joint-life and last-survivor annuities on three lives (advance and
+    arrears, with and without premiums) beside level, patterned and
+    two-life tiles; three nodes with shocks, every state slot."""
+    w = three_life_workload(1900 + K + 7 * J, n=400, n_steps=90, n_scen=2 * K + 3, n_nodes=3)
+    assert np.isin(w.portfolio.product, THREE).sum() > 60
+    ctx.basis_upload(w.basis.q, w.basis.v, w.basis.shock)
+    ctx.portfolio_upload(w.portfolio)
+    ctx.set_option(rr.OPT_BLOCK_K, K)
+    ctx.set_option(rr.OPT_BLOCK_J, J)
+    _say(f"three lives K={K} J={J}")
+    compare(ctx, w)
+
+
+def test_three_life_paths_and_long_terms(ctx):
+    w = three_life_workload(1990, n=120, n_steps=300, n_scen=3, n_nodes=2, node_step=12,
+                            products=THREE)
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("three-life paths")
+    compare(ctx, w)
+    for node, scen in ((0, 0), (1, 2)):
+        po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=node, node_step=12)
+        po["path"].fill_(float("nan"))
+        ctx.reserve_recurrence(node, 1, scen, 1, 12, po)
+        torch.cuda.synchronize()
+        path, off = oracle.reserve_paths(b, pf, node=node, scen=scen, node_step=12)
+        ref = oracle.reserves(b, pf, node, 1, scen, 1, 12)
+        gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+        assert_reserves_close(to_np(po["path"]), path, np.maximum(gross, 0), what="path")
+
+
+def test_three_life_invalid(ctx, rr):
+    rng = np.random.default_rng(1995)
+    w = synth.random_small(rng, n=20, n_steps=50, n_scen=2, products=THREE)
+    ctx.basis_upload(w.basis.q, w.basis.v)
+    bad = w.portfolio.subset(np.arange(20))
+    bad.age3_m = None
+    with pytest.raises(rr.RRError, match="age3_m"):
+        ctx.portfolio_upload(bad)
+    bad = w.portfolio.subset(np.arange(20))
+    bad.timing[3] = synth.FRACTIONAL
+    with pytest.raises(rr.RRError):
+        ctx.portfolio_upload(bad)
+    bad = w.portfolio.subset(np.arange(20))
+    bad.escalation = np.zeros(20)
+    bad.escalation[4] = 0.03
+    bad.premium[4] = 0.0
+    with pytest.raises(rr.RRError, match="policy 4"):
+        ctx.portfolio_upload(bad)
