@@ -10,6 +10,8 @@
   inner scenarios) in the launch configuration the benchmark times: every
   valuation and every total of three whole nodes against the oracle, and
   those nodes' mean and 1-in-200 statistic against the oracle's own totals.
+* The headline workload (10,000 policies x 1,000 scenarios) in full: all
+  10^7 valuations, the totals and the statistics against the oracle.
 
 Bar: FP64 reserves within 1e-10 of max(|r|, gross PV) per valuation, totals
 within 1e-10 of the summed gross PV."""
@@ -198,3 +200,24 @@ def test_c4_full_size_three_nodes_every_valuation(ctx, rr):
         assert abs(stats[node, 0] - mean[0]) <= RTOL * gsum, (stats[node, 0], mean[0])
         assert abs(stats[node, 1] - q[0]) <= RTOL * float(ref["gross_totals"].max()), (stats[node, 1], q[0])
         assert live > 0
+
+
+def test_c3_full_size_every_valuation(ctx, rr):
+    """The headline workload in the benchmark's launch configuration
+    (autotuned, r0 + totals + statistics): all 10,000 x 1,000 valuations,
+    every total and the 1-in-200 total against the oracle."""
+    w = synth.config_c3()
+    b, pf = w.basis, w.portfolio
+    upload(ctx, w)
+    out = ctx.alloc_outputs(1, b.n_scen, stats=True)
+    _say("C3 full size, every valuation")
+    ctx.reserve_recurrence(0, 1, 0, b.n_scen, 12, out)
+    torch.cuda.synchronize()
+    ref = oracle.reserves(b, pf, 0, 1, 0, b.n_scen, 12)
+    assert_reserves_close(to_np(out["r0"]), ref["r_all"][..., 0], ref["gross"])
+    err = np.abs(to_np(out["totals"]) - ref["totals"])
+    assert np.all(err <= RTOL * ref["gross_totals"]), err.max()
+    mean, q = oracle.node_stats(ref["totals"])
+    st = to_np(out["stats"])[0]
+    gsum = float(ref["gross_totals"].max())
+    assert abs(st[0] - mean[0]) <= RTOL * gsum and abs(st[1] - q[0]) <= RTOL * gsum
