@@ -603,6 +603,17 @@ def main():
                                      "launch": {"block_k": ctx.get_option(rr.OPT_LAST_K),
                                                 "block_j": ctx.get_option(rr.OPT_LAST_J),
                                                 "wg_per_cu": ctx.get_option(rr.OPT_LAST_WG)}}
+        if not args.no_cpu:
+            # The nested valuation on the host once, in full (reduced mode,
+            # the process's CPU share): the CPU side of this secondary line.
+            import oracle
+            t0 = time.perf_counter()
+            oracle.reserves_reduced(w4.basis, w4.portfolio, 0, w4.basis.n_nodes, 0, w4.basis.n_scen,
+                                    12, n_threads=cpu_share(), want_r=False)
+            c4s = time.perf_counter() - t0
+            sec["C4_nested_60_nodes"]["cpu_reduced_mode"] = {
+                "seconds": c4s, "valuations_per_s": live4 * w4.basis.n_scen / c4s,
+                "threads": cpu_share(), "sample": "the whole workload, once"}
         sec["representative_500k_annuities"] = representative_leg(rr, synth, sync)
         sec["C3_device_generated_scenarios"] = generated_scenarios_leg(rr, synth, sync)
         sec["C4_node_means"] = node_means_leg(rr, synth, sync)

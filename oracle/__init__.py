@@ -76,7 +76,7 @@ def _load():
         vp, ci = ctypes.c_void_p, ctypes.c_int
         lib.orc_reserves.argtypes = [vp, vp, ci, ci, ci, ci, ci, vp, vp, vp, vp, ci]
         lib.orc_reserves.restype = ci
-        lib.orc_reserves_reduced.argtypes = [vp, vp, ci, ci, ci, ci, ci, vp, vp, ci]
+        lib.orc_reserves_reduced.argtypes = [vp, vp, ci, ci, ci, ci, ci, vp, vp, vp, ci]
         lib.orc_reserves_reduced.restype = ci
         lib.orc_reserve_paths.argtypes = [vp, vp, ci, ci, ci, vp, ci]
         lib.orc_reserve_paths.restype = ci
@@ -173,18 +173,21 @@ def reserves_reduced(basis, pf, node0=0, nnode=None, scen0=0, nscen=None, node_s
                      n_threads=None, want_r=True):
     """The same reserves by the zero-reserve-state-reduced recurrence of each
     product (see oracle.c, orc_reserves_reduced): r_all [nnode, n, nscen, 4]
-    (None unless want_r) and totals [nnode, nscen]; no gross values."""
+    (None unless want_r), totals [nnode, nscen] and abs_totals (the sums of
+    |r_0|); no gross values."""
     lib = _load()
     a = _Args(basis, pf)
     nnode = basis.v.shape[0] - node0 if nnode is None else nnode
     nscen = basis.v.shape[1] - scen0 if nscen is None else nscen
     r_all = np.zeros((nnode, a.n, nscen, OUT_STATES)) if want_r else None
     totals = np.zeros((nnode, nscen))
+    abs_totals = np.zeros((nnode, nscen))
     rc = lib.orc_reserves_reduced(ctypes.byref(a.b), ctypes.byref(a.p), node0, nnode, scen0, nscen,
-                                  node_step, _ptr(r_all), _ptr(totals), n_threads or default_threads())
+                                  node_step, _ptr(r_all), _ptr(totals), _ptr(abs_totals),
+                                  n_threads or default_threads())
     if rc != 0:
         raise ValueError(f"oracle rejected the input (rc={rc})")
-    return {"r_all": r_all, "totals": totals}
+    return {"r_all": r_all, "totals": totals, "abs_totals": abs_totals}
 
 
 def path_offsets(term_m, node=0, node_step=12):

@@ -808,15 +808,17 @@ static void markov_one(const orc_portfolio *p, int i, const orc_contract *k, int
 }
 
 /*
- * orc_reserves in the reduced mode: r_all [nnode][n][nscen][4] (or NULL) and
- * totals [nnode][nscen] (or NULL), no gross values.  OpenMP over policies
+ * orc_reserves in the reduced mode: r_all [nnode][n][nscen][4] (or NULL),
+ * totals [nnode][nscen] (or NULL) and abs_totals [nnode][nscen] (or NULL),
+ * the sums of |r_0| over the same policies (a scale for the rounding of a
+ * total that needs no per-policy output), no gross values.  OpenMP over policies
  * (dynamic schedule); per policy the death probabilities of each step are
  * looked up once and shared by the scenarios.  Returns 0, -1 on invalid
  * input, -2 without memory.
  */
 int orc_reserves_reduced(const orc_basis *b, const orc_portfolio *p, int node0, int nnode,
                          int scen0, int nscen, int node_step, double *r_all, double *totals,
-                         int n_threads)
+                         double *abs_totals, int n_threads)
 {
     if (validate(b, p)) return -1;
     if (node0 < 0 || nnode < 0 || node0 + nnode > b->n_nodes) return -1;
@@ -884,12 +886,17 @@ int orc_reserves_reduced(const orc_basis *b, const orc_portfolio *p, int node0, 
         free(as);
     }
     if (bad) { free(r0s); return -2; }
-    if (totals)
+    if (totals || abs_totals)
         for (int a = 0; a < nnode; ++a)
             for (int s = 0; s < nscen; ++s) {
-                neumaier tr = {0, 0};
-                for (int i = 0; i < n; ++i) nm_add(&tr, r0s[((size_t)a * n + i) * nscen + s]);
-                totals[(size_t)a * nscen + s] = tr.s + tr.c;
+                neumaier tr = {0, 0}, ta = {0, 0};
+                for (int i = 0; i < n; ++i) {
+                    const double x = r0s[((size_t)a * n + i) * nscen + s];
+                    nm_add(&tr, x);
+                    nm_add(&ta, fabs(x));
+                }
+                if (totals) totals[(size_t)a * nscen + s] = tr.s + tr.c;
+                if (abs_totals) abs_totals[(size_t)a * nscen + s] = ta.s + ta.c;
             }
     free(r0s);
     return 0;

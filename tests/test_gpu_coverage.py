@@ -12,6 +12,9 @@
   those nodes' mean and 1-in-200 statistic against the oracle's own totals.
 * The headline workload (10,000 policies x 1,000 scenarios) in full: all
   10^7 valuations, the totals and the statistics against the oracle.
+* Every one of the 30,000 totals of the full nested valuation, and every
+  node's mean and 1-in-200 total, against the oracle's reduced mode (pinned
+  to its dense mode at 1e-13), within 1e-10 of the sum of |r| per total.
 
 Bar: FP64 reserves within 1e-10 of max(|r|, gross PV) per valuation, totals
 within 1e-10 of the summed gross PV."""
@@ -221,3 +224,25 @@ def test_c3_full_size_every_valuation(ctx, rr):
     st = to_np(out["stats"])[0]
     gsum = float(ref["gross_totals"].max())
     assert abs(st[0] - mean[0]) <= RTOL * gsum and abs(st[1] - q[0]) <= RTOL * gsum
+
+
+def test_c4_full_size_every_total(ctx, rr):
+    w = synth.config_c4()
+    b, pf = w.basis, w.portfolio
+    upload(ctx, w)
+    out = ctx.alloc_outputs(b.n_nodes, b.n_scen, r0=False, stats=True)
+    _say("C4 full size, every total")
+    ctx.reserve_recurrence(0, b.n_nodes, 0, b.n_scen, 12, out)
+    torch.cuda.synchronize()
+    red = oracle.reserves_reduced(b, pf, 0, b.n_nodes, 0, b.n_scen, 12, want_r=False)
+    tot = to_np(out["totals"])
+    scale = red["abs_totals"]
+    live = scale > 0
+    assert np.all(tot[~live] == 0.0)
+    err = np.abs(tot - red["totals"])
+    assert np.all(err[live] <= RTOL * scale[live]), float((err[live] / scale[live]).max())
+    mean, q = oracle.node_stats(red["totals"])
+    st = to_np(out["stats"])
+    smax = scale.max(axis=1)
+    assert np.all(np.abs(st[:, 0] - mean) <= RTOL * smax + 0.0)
+    assert np.all(np.abs(st[:, 1] - q) <= RTOL * smax + 0.0)

@@ -1069,3 +1069,12 @@ def test_large_markov_recurrence_equals_summation(m):
     dense = oracle.reserves(b, pf)
     red = oracle.reserves_reduced(b, pf)
     np.testing.assert_allclose(red["r_all"], dense["r_all"], rtol=1e-13, atol=1e-11)
+
+
+def test_reduced_mode_absolute_totals():
+    rng = np.random.default_rng(900)
+    w = synth.random_small(rng, n=150, n_steps=60, n_scen=3, n_nodes=2, shock=True)
+    red = oracle.reserves_reduced(w.basis, w.portfolio, node_step=12)
+    r = red["r_all"][..., 0]
+    np.testing.assert_allclose(red["abs_totals"], np.abs(r).sum(axis=1), rtol=1e-14)
+    np.testing.assert_allclose(red["totals"], r.sum(axis=1), rtol=1e-12, atol=1e-9)
