@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librr.so")
+# RR_LIB names another build of the same library (e.g. the host-sanitizer
+# build of the CPU checks); by default the in-tree librr.so.
+LIB_PATH = os.environ.get("RR_LIB") or os.path.join(_HERE, "librr.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ERANGE, RR_ESTATE = 0, -1, -2, -3, -4, -5
 SL_ANN, JL_ANN, REV_ANN, LS_ANN, TERM, ENDOW, ENDOW_ASSUR, CF_TABLE = range(8)

@@ -98,6 +98,41 @@ def build(verbose: bool = False, jobs: int = 4, incremental: bool = False) -> st
     return LIB
 
 
+SAN_LIB = os.path.join(OBJDIR, "librr_hostsan.so")
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """A CPU-only checking build: the host runtime (validation, planning,
+    the ABI) compiled with AddressSanitizer and UndefinedBehaviorSanitizer,
+    linked with the device objects of the last build(), as _build/librr_hostsan.so.
+    Load it with the clang ASan runtime preloaded; it is never the product
+    library."""
+    dev, host = _sources()
+    inc = ["-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include"]
+    objs = []
+    for s in dev:
+        o = os.path.join(OBJDIR, s + ".o")
+        if not os.path.exists(o):
+            raise RuntimeError(f"{o} is missing: run build() first")
+        objs.append(o)
+    san = ["-g", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-fno-sanitize-recover=undefined"]
+    for s in host:
+        o = os.path.join(OBJDIR, s + ".san.o")
+        cmd = [HIPCC, *HOST_FLAGS, *san, *inc, "-c", os.path.join(CSRC, s), "-o", o]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(o)
+    link = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Xarch_host", "-fsanitize=address",
+            "-Xarch_host", "-fsanitize=undefined", "-shared-libasan", "-o", SAN_LIB, *objs,
+            "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print(LIB)
