@@ -558,7 +558,7 @@ def main():
         ctx.close()
         ctx = rr.Context(0)
         result["surrogate"] = surrogate_leg(rr, synth, ctx, w, exact_totals, n_val, ms_per_step,
-                                            args.steps, sync)
+                                            args.steps, sync, epochs=args.surrogate_epochs)
 
     if not args.no_secondary:
         sec = {}
@@ -574,6 +574,24 @@ def main():
         e2 = timed_steps(f2, 20, sync)
         sec["C2_single_scenario"] = {"valuations_per_s": w2.portfolio.n / (e2 / 20),
                                      "ms_per_step": 1e3 * e2 / 20, "policies": w2.portfolio.n}
+        # Path mode: the reserve at every step of every policy (state 0),
+        # bound by the HBM writes of the path.
+        po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=0)
+        fp = lambda: ctx.reserve_recurrence(0, 1, 0, 1, 12, po)
+        for _ in range(3):
+            fp()
+        ep = timed_steps(fp, 20, sync)
+        ctx.set_option(rr.OPT_KERNEL_TIMING, 1)
+        ctx.kernel_times()
+        timed_steps(fp, 20, sync)
+        kp = float(np.mean(ctx.kernel_times()))
+        ctx.set_option(rr.OPT_KERNEL_TIMING, 0)
+        path_bytes = po["path"].numel() * 8
+        sec["C2_path_mode"] = {"ms_per_step": 1e3 * ep / 20, "kernel_ms": kp,
+                               "path_bytes": path_bytes,
+                               "kernel_write_GBps": path_bytes / (kp * 1e-3) / 1e9,
+                               "frac_hbm_peak": path_bytes / (kp * 1e-3) / 8e12,
+                               "policy_steps": int(po["path"].numel())}
         ctx.close()
         ctx = rr.Context(0)
         w4 = synth.config_c4()
