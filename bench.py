@@ -245,6 +245,41 @@ def surrogate_leg(rr, synth, ctx, w, exact_totals, n_val, exact_ms, steps, sync,
     }
 
 
+def c2_legs(rr, synth, ctx, sync, steps=20, path_only=False):
+    """C2 (100,000 mixed policies, one flat scenario): r0 and totals per call
+    (latency-bound), then path mode (the state-0 reserve at every step of
+    every policy), bound by the HBM writes of the path."""
+    w2 = synth.config_c2()
+    ctx.basis_upload(w2.basis.q, w2.basis.v)
+    ctx.portfolio_upload(w2.portfolio)
+    out = {}
+    if not path_only:
+        o2 = ctx.alloc_outputs(1, 1)
+        f2 = lambda: ctx.reserve_recurrence(0, 1, 0, 1, 12, o2)
+        for _ in range(3):
+            f2()
+        e2 = timed_steps(f2, steps, sync)
+        out["C2_single_scenario"] = {"valuations_per_s": w2.portfolio.n / (e2 / steps),
+                                     "ms_per_step": 1e3 * e2 / steps, "policies": w2.portfolio.n}
+    po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=0)
+    fp = lambda: ctx.reserve_recurrence(0, 1, 0, 1, 12, po)
+    for _ in range(3):
+        fp()
+    ep = timed_steps(fp, steps, sync)
+    ctx.set_option(rr.OPT_KERNEL_TIMING, 1)
+    ctx.kernel_times()
+    timed_steps(fp, steps, sync)
+    kp = float(np.mean(ctx.kernel_times()))
+    ctx.set_option(rr.OPT_KERNEL_TIMING, 0)
+    path_bytes = po["path"].numel() * 8
+    out["C2_path_mode"] = {"ms_per_step": 1e3 * ep / steps, "kernel_ms": kp,
+                           "path_bytes": path_bytes,
+                           "kernel_write_GBps": path_bytes / (kp * 1e-3) / 1e9,
+                           "frac_hbm_peak": path_bytes / (kp * 1e-3) / 8e12,
+                           "policy_steps": int(po["path"].numel())}
+    return out
+
+
 def generated_scenarios_leg(rr, synth, sync, steps=20):
     """C3 with its 1,000 Vasicek scenarios generated on the device each step
     (a fresh Philox key per step): generation alone, and generation plus the
@@ -392,6 +427,9 @@ def main():
                     help="only the C4 expected-reserve-per-node leg")
     ap.add_argument("--generated-only", action="store_true",
                     help="only the device-generated-scenario leg (for profiling)")
+    ap.add_argument("--c2-only", action="store_true",
+                    help="only the C2 legs (one scenario: r0 mode, then path mode)")
+    ap.add_argument("--c2-path-only", action="store_true", help="only the C2 path-mode leg")
     ap.add_argument("--representative-only", action="store_true",
                     help="only the representative 500,000-annuity portfolio leg (for profiling)")
     ap.add_argument("--block-k", type=int, default=0, help="pin scenarios per lane (0 = autotune)")
@@ -436,6 +474,11 @@ def main():
         return
     if args.node_means_only:
         print(json.dumps(node_means_leg(rr, synth, sync)))
+        return
+    if args.c2_only or args.c2_path_only:
+        ctx = rr.Context(0)
+        print(json.dumps(c2_legs(rr, synth, ctx, sync, steps=args.steps, path_only=args.c2_path_only)))
+        ctx.close()
         return
     if args.generated_only:
         print(json.dumps(generated_scenarios_leg(rr, synth, sync, steps=args.steps)))
@@ -564,34 +607,7 @@ def main():
         sec = {}
         ctx.close()
         ctx = rr.Context(0)
-        w2 = synth.config_c2()
-        ctx.basis_upload(w2.basis.q, w2.basis.v)
-        ctx.portfolio_upload(w2.portfolio)
-        o2 = ctx.alloc_outputs(1, 1)
-        f2 = lambda: ctx.reserve_recurrence(0, 1, 0, 1, 12, o2)
-        for _ in range(3):
-            f2()
-        e2 = timed_steps(f2, 20, sync)
-        sec["C2_single_scenario"] = {"valuations_per_s": w2.portfolio.n / (e2 / 20),
-                                     "ms_per_step": 1e3 * e2 / 20, "policies": w2.portfolio.n}
-        # Path mode: the reserve at every step of every policy (state 0),
-        # bound by the HBM writes of the path.
-        po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=0)
-        fp = lambda: ctx.reserve_recurrence(0, 1, 0, 1, 12, po)
-        for _ in range(3):
-            fp()
-        ep = timed_steps(fp, 20, sync)
-        ctx.set_option(rr.OPT_KERNEL_TIMING, 1)
-        ctx.kernel_times()
-        timed_steps(fp, 20, sync)
-        kp = float(np.mean(ctx.kernel_times()))
-        ctx.set_option(rr.OPT_KERNEL_TIMING, 0)
-        path_bytes = po["path"].numel() * 8
-        sec["C2_path_mode"] = {"ms_per_step": 1e3 * ep / 20, "kernel_ms": kp,
-                               "path_bytes": path_bytes,
-                               "kernel_write_GBps": path_bytes / (kp * 1e-3) / 1e9,
-                               "frac_hbm_peak": path_bytes / (kp * 1e-3) / 8e12,
-                               "policy_steps": int(po["path"].numel())}
+        sec.update(c2_legs(rr, synth, ctx, sync))
         ctx.close()
         ctx = rr.Context(0)
         w4 = synth.config_c4()

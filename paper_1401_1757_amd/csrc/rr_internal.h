@@ -112,6 +112,7 @@ struct RecParams {
     int n_pad;
     int n_user;
     int ring_off;             // curve-ring launches: first double of the rings in LDS
+    int path_lds;             // path output: first double of the wavefronts' stages in LDS
     const Tile *tiles;
     int n_tiles;
     // work
@@ -137,6 +138,13 @@ struct RecParams {
 // discount factors of its K scenarios in LDS, two chunks of RING_C steps.
 constexpr int RING_C = 16;
 constexpr int ring_doubles_per_wave(int K) { return 2 * RING_C * K; }
+
+// Path output stage (one policy per lane): each wavefront keeps PATH_T steps
+// of its 64 lanes in LDS, rows PATH_ROW doubles apart (PATH_ROW = 2 mod 32
+// puts the 32 lanes of a half-wave read on distinct banks).
+constexpr int PATH_T = 16;
+constexpr int PATH_ROW = 66;
+constexpr int PATH_STAGE_DOUBLES = PATH_T * PATH_ROW;
 
 // Launchers (rr_kernels.hip).  All are asynchronous on `stream`.  ring: the
 // curve-ring instances (supported_ring(K, J); no vector or pattern tiles;

@@ -670,6 +670,33 @@ __device__ __forceinline__ f32x4 lds_f4(const unsigned char *base, int byte_off)
     return *reinterpret_cast<const f32x4 *>(base + byte_off);
 }
 
+// Pre-activations of layer-2 output chunk c2 (units 32 c2 .. 32 c2 + 31) for
+// NG row groups: bias plus the eight contraction chunks of a1.
+template <int NG>
+__device__ __forceinline__ void layer2_chunk(const unsigned char *lds, int w2lane, int q, int r16,
+                                             int c2, const bf16x8 (&a1)[NG][8], f32x4 (&za)[NG],
+                                             f32x4 (&zb)[NG])
+{
+    const f32x4 ba = lds_f4(lds, LDS_B2 + (32 * c2 + 4 * q) * 4);
+    const f32x4 bb = lds_f4(lds, LDS_B2 + (32 * c2 + 16 + 4 * q) * 4);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        za[g] = ba;
+        zb[g] = bb;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int sw = ((4 * c + q) ^ r16) * 16;
+        const bf16x8 wa = lds8(lds, w2lane + c2 * (32 * 512) + sw);
+        const bf16x8 wb = lds8(lds, w2lane + c2 * (32 * 512) + 16 * 512 + sw);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            za[g] = mfma(wa, a1[g][c], za[g]);
+            zb[g] = mfma(wb, a1[g][c], zb[g]);
+        }
+    }
+}
+
 // NG groups of 16 rows (scenarios) per unit.
 template <int NG>
 __global__ void __launch_bounds__(INFER_THREADS, 1) k_infer(Infer f, Weights w)
@@ -773,32 +800,72 @@ __global__ void __launch_bounds__(INFER_THREADS, 1) k_infer(Infer f, Weights w)
                     a1[g][c] = pack8(gelu4(za), gelu4(zb));
                 }
             }
-            // Layer 2 + GELU + head, two output tiles (one head chunk) at a time.
+            // Layer 2 + GELU + head, two output tiles (one head chunk) at a
+            // time, as a two-stage pipeline: while the MFMAs of chunk c2 run,
+            // the VALU evaluates the GELU of chunk c2 - 1, two values per
+            // contraction step, so the matrix and vector units of the SIMD
+            // work at once.  Every accumulator sees the same operations in
+            // the same order as in a plain loop.
             f32x4 yacc[NG];
 #pragma unroll
             for (int g = 0; g < NG; ++g) yacc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+            f32x4 za[NG], zb[NG];
+            layer2_chunk<NG>(lds, w2lane, q, r16, 0, a1, za, zb);
 #pragma unroll 1
-            for (int c2 = 0; c2 < 8; ++c2) {
+            for (int c2 = 1; c2 < 8; ++c2) {
+                float h[NG][8];   // GELU of chunk c2 - 1: [g][0..3] from za, [g][4..7] from zb
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        h[g][i] = za[g][i];
+                        h[g][4 + i] = zb[g][i];
+                    }
+                }
                 const f32x4 ba = lds_f4(lds, LDS_B2 + (32 * c2 + 4 * q) * 4);
                 const f32x4 bb = lds_f4(lds, LDS_B2 + (32 * c2 + 16 + 4 * q) * 4);
-                f32x4 za[NG], zb[NG];
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     za[g] = ba;
                     zb[g] = bb;
                 }
+                constexpr int PER = NG * 8 / 8;   // GELU values per contraction step
+                // Weight fragments one contraction step ahead of their MFMAs.
+                const int wrow = w2lane + c2 * (32 * 512);
+                bf16x8 wa = lds8(lds, wrow + ((q ^ r16) * 16));
+                bf16x8 wb = lds8(lds, wrow + 16 * 512 + ((q ^ r16) * 16));
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    const int sw = ((4 * c + q) ^ r16) * 16;
-                    const bf16x8 wa = lds8(lds, w2lane + c2 * (32 * 512) + sw);
-                    const bf16x8 wb = lds8(lds, w2lane + c2 * (32 * 512) + 16 * 512 + sw);
+                    bf16x8 na = wa, nb = wb;
+                    if (c < 7) {
+                        const int sw = ((4 * (c + 1) + q) ^ r16) * 16;
+                        na = lds8(lds, wrow + sw);
+                        nb = lds8(lds, wrow + 16 * 512 + sw);
+                    }
 #pragma unroll
                     for (int g = 0; g < NG; ++g) {
                         za[g] = mfma(wa, a1[g][c], za[g]);
                         zb[g] = mfma(wb, a1[g][c], zb[g]);
                     }
+                    wa = na;
+                    wb = nb;
+#pragma unroll
+                    for (int j = 0; j < PER; ++j) {
+                        const int e = c * PER + j;
+                        h[e / 8][e % 8] = gelu_f(h[e / 8][e % 8]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                const bf16x8 w3 = lds8(lds, LDS_W3 + c2 * 1024 + r16 * 64 + q * 16);
+                const bf16x8 w3 = lds8(lds, LDS_W3 + (c2 - 1) * 1024 + r16 * 64 + q * 16);
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const f32x4 lo = {h[g][0], h[g][1], h[g][2], h[g][3]};
+                    const f32x4 hi = {h[g][4], h[g][5], h[g][6], h[g][7]};
+                    yacc[g] = mfma(w3, pack8(lo, hi), yacc[g]);
+                }
+            }
+            {
+                const bf16x8 w3 = lds8(lds, LDS_W3 + 7 * 1024 + r16 * 64 + q * 16);
 #pragma unroll
                 for (int g = 0; g < NG; ++g) yacc[g] = mfma(w3, pack8(gelu4(za[g]), gelu4(zb[g])), yacc[g]);
             }

@@ -54,6 +54,54 @@ __device__ __forceinline__ double wave_sum(double x)
            (__hiloint2double(hi2, lo2) + __hiloint2double(hi3, lo3));
 }
 
+// Path output (one scenario and one policy per lane): the state-0 reserve at
+// every step, stored per policy as consecutive doubles.  Written directly, a
+// step's store touches 64 cache lines (one per lane).  Instead the wavefront
+// keeps the last PATH_T steps of its 64 lanes in LDS and, when a block of
+// PATH_T aligned steps is complete, writes it out per policy: lane l takes
+// step t0 + l % PATH_T of policy (64 / PATH_T) j + l / PATH_T in round j, so a
+// store instruction covers four runs of PATH_T consecutive doubles.  The
+// stage's rows are PATH_ROW doubles apart, which spreads a round's reads over
+// the LDS banks.
+struct PathStage {
+    double *base;    // this lane's path (entry t at base[t]); null: the lane writes none
+    int S;           // entries t < S come from the steps (entry S is written first)
+    double *buf;     // the wavefront's PATH_STAGE_DOUBLES of LDS; null: no path output
+};
+
+// Every lane of the wavefront calls path_put for each step t, from its top
+// step down to t = 0 (the values of a lane with t >= S are not written out).
+__device__ __forceinline__ void path_put(const PathStage &ps, int t, double r, int lane)
+{
+    ps.buf[(t & (PATH_T - 1)) * PATH_ROW + lane] = r;
+    if ((t & (PATH_T - 1)) == 0) {
+        __builtin_amdgcn_wave_barrier();
+        const int u = lane & (PATH_T - 1);
+        constexpr int PER = 64 / PATH_T;   // policies per round
+        constexpr int B = 4;               // rounds whose LDS operations are issued together
+        // A global store: a flat one would also count against the LDS
+        // counter and make the next rounds' LDS operations wait for it.
+        typedef __attribute__((address_space(1))) double global_double;
+#pragma unroll
+        for (int j0 = 0; j0 < 64 / PER; j0 += B) {
+            unsigned long long dst[B];
+            int S[B];
+            double x[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const int src = PER * (j0 + i) + lane / PATH_T;
+                dst[i] = __shfl((unsigned long long)ps.base, src);
+                S[i] = __shfl(ps.S, src);
+                x[i] = ps.buf[u * PATH_ROW + src];
+            }
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                if (dst[i] != 0ull && t + u < S[i]) ((global_double *)dst[i])[t + u] = x[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 template <bool LDSQ>
 __device__ __forceinline__ double qload(const double *__restrict__ lds, const double *__restrict__ glob,
                                         int idx)
@@ -258,8 +306,9 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
                                              const double *__restrict__ vb, int stride,
                                              const ScalarLane (&L)[J], PatLane (&PL)[J], int cfs,
                                              double m, int smax, int smin, double (&r)[J][K],
-                                             double *path, double *ring = nullptr)
+                                             const PathStage &ps, double *ring = nullptr)
 {
+    const int plane = threadIdx.x & 63;
     // Cash flow of step t from the table (table tiles only).
     auto cfload = [&](int j, int t) -> double {
         if constexpr (FLOW == FLOW_TABLE) return L[j].cfb[(ptrdiff_t)t * cfs];
@@ -318,7 +367,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
                 apply(r[j], vk[u], p, c, a0);
             }
             if constexpr (K == 1 && J == 1) {
-                if (path != nullptr) path[tb - u] = r[0][0];
+                if (ps.buf != nullptr) path_put(ps, tb - u, r[0][0], plane);
             }
         }
     };
@@ -352,7 +401,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
             apply(r[j], vk, p, c, on ? a0 : L[j].rS);
         }
         if constexpr (K == 1 && J == 1) {
-            if (path != nullptr && t < L[0].S) path[t] = r[0][0];
+            if (ps.buf != nullptr) path_put(ps, t, r[0][0], plane);
         }
     }
     if constexpr (VR) {
@@ -458,7 +507,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
             apply(r[j], vk, p, c, a0);
         }
         if constexpr (K == 1 && J == 1) {
-            if (path != nullptr) path[t] = r[0][0];
+            if (ps.buf != nullptr) path_put(ps, t, r[0][0], plane);
         }
     }
 }
@@ -469,7 +518,8 @@ template <int K, int J, bool LDSQ, bool TWO, int FLOW, bool VR = false>
 __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__restrict__ lq,
                                            const double *__restrict__ vcurves, int node_rel,
                                            int tile, int count, const Tile &T0, int item_smax,
-                                           int item_smin, int sb, int lane, double *ring = nullptr)
+                                           int item_smin, int sb, int lane, double *ring = nullptr,
+                                           double *pstage = nullptr)
 {
     const int node = P.node_begin + node_rel;
     const int shift = node * P.node_step;
@@ -514,12 +564,14 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
         }
     }
     const double *vb = vcurves + (size_t)node * P.n_steps * P.scen_pad + (P.scen_begin + sb);
-    double *path = nullptr;
+    PathStage ps{nullptr, 0, nullptr};
     if constexpr (K == 1 && J == 1) {
+        ps.buf = pstage;
+        ps.S = L[0].S;
         if (P.path != nullptr && uid[0] >= 0) {
             if (L[0].S > 0) {
-                path = P.path + P.path_off[uid[0]];
-                path[L[0].S] = r[0][0];
+                ps.base = P.path + P.path_off[uid[0]];
+                ps.base[L[0].S] = r[0][0];
             } else {
                 P.path[P.path_off[uid[0]]] = 0.0;   // expired: its one entry is 0
             }
@@ -527,10 +579,10 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
     }
     if (m == 1.0)
         scalar_steps<K, J, LDSQ, TWO, false, FLOW, VR>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m,
-                                                       smax, smin, r, path, ring);
+                                                       smax, smin, r, ps, ring);
     else
         scalar_steps<K, J, LDSQ, TWO, true, FLOW, VR>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m,
-                                                      smax, smin, r, path, ring);
+                                                      smax, smin, r, ps, ring);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         if (j < count) {
@@ -558,8 +610,15 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
                                              const double *__restrict__ vb, int stride, int qa,
                                              int qb, double m, const double (&cf)[7], PatLane &pl,
                                              int S, int smax, int smin, double (&r0)[K],
-                                             double (&r1)[K], double (&r2)[K], double *path)
+                                             double (&r1)[K], double (&r2)[K], const PathStage &ps)
 {
+    const int plane = threadIdx.x & 63;
+    // Path output: every lane at every step (uniform control flow).
+    auto put = [&](int t) {
+        if constexpr (K == 1) {
+            if (ps.buf != nullptr) path_put(ps, t, r0[0], plane);
+        }
+    };
     auto apply = [&](const double (&vk)[K], double px, double py, int t) {
         double f = 1.0;
         if constexpr (ESC) f = pat_factor(pl, t);
@@ -590,9 +649,6 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
             r0[k] = fma(vk[k], a, c00a);
             r2[k] = fma(vk[k], c, c10a);
         }
-        if constexpr (K == 1) {
-            if (path != nullptr) path[t] = r0[0];
-        }
     };
     int t = smax - 1;
     const double *vt = vb + (ptrdiff_t)t * stride;
@@ -602,6 +658,7 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
         for (int k = 0; k < K; ++k) vk[k] = vt[k];
         if (t < S)
             apply(vk, p_eff<LDSQ, SHOCK>(lq, gq, qa + t, m), p_eff<LDSQ, SHOCK>(lq, gq, qb + t, m), t);
+        put(t);
     }
     constexpr int U = StepBlock<K>::U;
     auto load_block = [&](int tb, const double *vtb, double (&vk)[U][K], double (&qx)[U],
@@ -626,6 +683,7 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
                 y = 1.0 - fmin(1.0, m * (1.0 - y));
             }
             apply(vk[u], x, y, tb - u);
+            put(tb - u);
         }
     };
     if constexpr (StepBlock<K>::PIPE) {
@@ -664,13 +722,15 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
 #pragma unroll
         for (int k = 0; k < K; ++k) vk[k] = vt[k];
         apply(vk, p_eff<LDSQ, SHOCK>(lq, gq, qa + t, m), p_eff<LDSQ, SHOCK>(lq, gq, qb + t, m), t);
+        put(t);
     }
 }
 
 template <int K, bool LDSQ, bool LAST, bool ESC>
 __device__ __forceinline__ void run_vector(const RecParams &P, const double *__restrict__ lq,
                                            const double *__restrict__ vcurves, int node_rel,
-                                           int tile, const Tile &T, int sb, int lane)
+                                           int tile, const Tile &T, int sb, int lane,
+                                           double *pstage)
 {
     const int node = P.node_begin + node_rel;
     const int shift = node * P.node_step;
@@ -693,11 +753,12 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
 #pragma unroll
     for (int k = 0; k < K; ++k) { r0[k] = 0.0; r1[k] = 0.0; r2[k] = 0.0; }
 
-    double *path = nullptr;
+    PathStage ps{nullptr, S, nullptr};
     if constexpr (K == 1) {
+        ps.buf = pstage;
         if (P.path != nullptr && live) {
-            path = P.path + P.path_off[uid];
-            path[S] = 0.0;
+            ps.base = P.path + P.path_off[uid];
+            ps.base[S] = 0.0;
         } else if (P.path != nullptr && uid >= 0) {
             P.path[P.path_off[uid]] = 0.0;         // expired: its one entry is 0
         }
@@ -707,10 +768,10 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
     if constexpr (ESC) pl = pat_init(P, slot, shift, S - 1);
     if (m == 1.0)
         vector_steps<K, LDSQ, LAST, false, ESC>(lq, P.q, vb, P.scen_pad, qa, qb, m, cf, pl, S, smax,
-                                                smin, r0, r1, r2, path);
+                                                smin, r0, r1, r2, ps);
     else
         vector_steps<K, LDSQ, LAST, true, ESC>(lq, P.q, vb, P.scen_pad, qa, qb, m, cf, pl, S, smax,
-                                               smin, r0, r1, r2, path);
+                                               smin, r0, r1, r2, ps);
     store_results<K>(P, node_rel, tile, sb, lane, uid, live, r0, r1, r2, LAST, true);
 }
 
@@ -721,7 +782,7 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
 template <int K, bool LDSQ, bool TWO, bool SHOCK>
 __device__ __forceinline__ void run_frac(const RecParams &P, const double *__restrict__ lq,
                                          const double *__restrict__ vcurves, int node_rel, int tile,
-                                         const Tile &T, int sb, int lane)
+                                         const Tile &T, int sb, int lane, double *pstage)
 {
     const int node = P.node_begin + node_rel;
     const int shift = node * P.node_step;
@@ -742,12 +803,13 @@ __device__ __forceinline__ void run_frac(const RecParams &P, const double *__res
     double r[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) r[k] = 0.0;
-    double *path = nullptr;
+    PathStage ps{nullptr, S, nullptr};
     if constexpr (K == 1) {
+        ps.buf = pstage;
         if (P.path != nullptr && uid >= 0) {
             if (live) {
-                path = P.path + P.path_off[uid];
-                path[S] = 0.0;
+                ps.base = P.path + P.path_off[uid];
+                ps.base[S] = 0.0;
             } else {
                 P.path[P.path_off[uid]] = 0.0;   // expired: its one entry is 0
             }
@@ -768,7 +830,7 @@ __device__ __forceinline__ void run_frac(const RecParams &P, const double *__res
             r[k] = on ? nr : r[k];
         }
         if constexpr (K == 1) {
-            if (path != nullptr && on) path[t] = r[0];
+            if (ps.buf != nullptr) path_put(ps, t, r[0], lane);
         }
     }
     store_results<K>(P, node_rel, tile, sb, lane, uid, live, r, r, r, false, false);
@@ -1070,6 +1132,10 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
     }
     double *ring = nullptr;
     if constexpr (VR) ring = s_q + P.ring_off + (threadIdx.x >> 6) * ring_doubles_per_wave(K);
+    double *pstage = nullptr;   // path output (one scenario per lane): the wavefront's stage
+    if constexpr (K == 1) {
+        if (P.path != nullptr) pstage = s_q + P.path_lds + (threadIdx.x >> 6) * PATH_STAGE_DOUBLES;
+    }
     const int lane = threadIdx.x & 63;
     int qcur = blockIdx.x % P.n_queues;
     __shared__ int s_win[2];   // window mode: first item of the window, its queue (-1: none left)
@@ -1155,11 +1221,11 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
                 if (T.flow == FLOW_FRAC) {
                     const bool shock = P.shock[P.node_begin + node_rel] != 1.0;
                     if (T.kind == KIND_JOINT) {
-                        if (shock) run_frac<K, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
-                        else run_frac<K, LDSQ, true, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                        if (shock) run_frac<K, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane, pstage);
+                        else run_frac<K, LDSQ, true, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane, pstage);
                     } else {
-                        if (shock) run_frac<K, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
-                        else run_frac<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                        if (shock) run_frac<K, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane, pstage);
+                        else run_frac<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane, pstage);
                     }
                 } else if (T.flow == FLOW_MARKOV) {
                     run_markov<K>(P, vcurves, node_rel, tile, T, sb, lane);
@@ -1170,29 +1236,36 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
                         run_three<K, LDSQ, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
                 } else if (T.flow == FLOW_TABLE)
                     run_scalar<K, 1, LDSQ, false, FLOW_TABLE>(P, s_q, vcurves, node_rel, tile, 1, T,
-                                                              T.smax, T.smin, sb, lane);
+                                                              T.smax, T.smin, sb, lane, nullptr,
+                                                              pstage);
                 else if (T.kind == KIND_SINGLE)
                     run_scalar<K, 1, LDSQ, false, FLOW_PATTERN>(P, s_q, vcurves, node_rel, tile, 1, T,
-                                                                T.smax, T.smin, sb, lane);
+                                                                T.smax, T.smin, sb, lane, nullptr,
+                                                                pstage);
                 else if (T.kind == KIND_JOINT)
                     run_scalar<K, 1, LDSQ, true, FLOW_PATTERN>(P, s_q, vcurves, node_rel, tile, 1, T,
-                                                               T.smax, T.smin, sb, lane);
+                                                               T.smax, T.smin, sb, lane, nullptr,
+                                                               pstage);
                 else if (T.kind == KIND_REV)
-                    run_vector<K, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                    run_vector<K, LDSQ, false, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane,
+                                                 pstage);
                 else
-                    run_vector<K, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                    run_vector<K, LDSQ, true, true>(P, s_q, vcurves, node_rel, tile, T, sb, lane,
+                                                 pstage);
             }
         } else if (T.kind == KIND_SINGLE) {
             run_scalar<K, J, LDSQ, false, FLOW_LEVEL, VR>(P, s_q, vcurves, node_rel, tile, count, T,
-                                                          smax, smin, sb, lane, ring);
+                                                          smax, smin, sb, lane, ring, pstage);
         } else if (T.kind == KIND_JOINT) {
             run_scalar<K, J, LDSQ, true, FLOW_LEVEL, VR>(P, s_q, vcurves, node_rel, tile, count, T,
-                                                         smax, smin, sb, lane, ring);
+                                                         smax, smin, sb, lane, ring, pstage);
         } else if constexpr (VEC) {
             if (T.kind == KIND_REV)
-                run_vector<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                run_vector<K, LDSQ, false, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane,
+                                                 pstage);
             else
-                run_vector<K, LDSQ, true, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane);
+                run_vector<K, LDSQ, true, false>(P, s_q, vcurves, node_rel, tile, T, sb, lane,
+                                                 pstage);
         }
     }
     // The last wavefront to finish re-arms the queues for the next launch.
@@ -1214,10 +1287,11 @@ static void launch_kjp(const RecParams &p, int grid, size_t lds, hipStream_t s)
         else
             hipLaunchKernelGGL((k_recurrence<K, J, true, false, PAT>), g, b, lds, s, p, p.v, p.items, p.tiles, p.qbeg);
     } else {
+        // lds: the path stages when the run writes a path, else 0
         if (p.has_vector)
-            hipLaunchKernelGGL((k_recurrence<K, J, false, true, PAT>), g, b, 0, s, p, p.v, p.items, p.tiles, p.qbeg);
+            hipLaunchKernelGGL((k_recurrence<K, J, false, true, PAT>), g, b, lds, s, p, p.v, p.items, p.tiles, p.qbeg);
         else
-            hipLaunchKernelGGL((k_recurrence<K, J, false, false, PAT>), g, b, 0, s, p, p.v, p.items, p.tiles, p.qbeg);
+            hipLaunchKernelGGL((k_recurrence<K, J, false, false, PAT>), g, b, lds, s, p, p.v, p.items, p.tiles, p.qbeg);
     }
 }
 
