@@ -139,6 +139,30 @@ def test_path_at_a_later_node_with_expired_policies(ctx):
     assert_reserves_close(got, path, np.maximum(gross, 0), what="path")
 
 
+def test_path_every_term_1_to_80(ctx):
+    """Path mode with every term from 1 to 80 months across all products:
+    the kernel writes paths out in aligned blocks of 16 steps, so this
+    covers blocks that are partial at the top, that end exactly at S and
+    that hold one step.  The buffer starts as NaN; every entry must match."""
+    rng = np.random.default_rng(91)
+    w = synth.random_small(rng, n=1280, n_steps=80, n_scen=2, n_nodes=1, shock=True)
+    b, pf = w.basis, w.portfolio
+    pf.term_m[:] = (np.arange(len(pf.term_m)) % 80 + 1).astype(np.int32)
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    _say("path, terms 1..80")
+    po = ctx.alloc_outputs(1, 1, r0=False, totals=False, path_node=0)
+    po["path"].fill_(float("nan"))
+    ctx.reserve_recurrence(0, 1, 1, 1, 12, po)
+    torch.cuda.synchronize()
+    path, off = oracle.reserve_paths(b, pf, node=0, scen=1, node_step=12)
+    ref = oracle.reserves(b, pf, 0, 1, 1, 1, 12)
+    gross = np.repeat(ref["gross"][0, :, 0], np.diff(off))
+    got = to_np(po["path"])
+    assert not np.isnan(got).any()
+    assert_reserves_close(got, path, np.maximum(gross, 0), what="path")
+
+
 def test_many_tiles_chunked_totals(ctx):
     """Over 512 tiles with a wide scenario range: the totals are summed in
     tile chunks, then the chunks in order; every total against the oracle."""
