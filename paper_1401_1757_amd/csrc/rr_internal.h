@@ -118,7 +118,7 @@ struct RecParams {
     // work
     const Item *items;
     const int *qbeg;          // [n_queues + 1]
-    int *counters;            // [MAX_QUEUES + 1]: queue heads, then finished-wave count
+    int *counters;            // [MAX_QUEUES + 1]: queue heads, then finished-workgroup count
     int n_queues;
     int win;                  // 1: workgroups take windows of WG_THREADS/64 items together
     // run

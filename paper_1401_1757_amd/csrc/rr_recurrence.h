@@ -356,8 +356,12 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
             }
     };
     // One block of U steps, every policy of the block active (t < smin).
+    // Path output goes out after the block, so that the block's steps stay
+    // one branch-free stretch of code (the coefficients of later steps
+    // overlap the chain of earlier ones).
     auto run_block = [&](int tb, const double (&vk)[U][K], const double (&q1)[U][J],
                          const double (&q2)[U][J], const double (&cv)[U][J]) {
+        double hist[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -366,8 +370,12 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
                 coeffs(j, tb - u, q1[u][j], q2[u][j], cv[u][j], p, c, a0);
                 apply(r[j], vk[u], p, c, a0);
             }
-            if constexpr (K == 1 && J == 1) {
-                if (ps.buf != nullptr) path_put(ps, tb - u, r[0][0], plane);
+            hist[u] = r[0][0];
+        }
+        if constexpr (K == 1 && J == 1) {
+            if (ps.buf != nullptr) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) path_put(ps, tb - u, hist[u], plane);
             }
         }
     };
@@ -673,8 +681,10 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
             qy[u] = qload<LDSQ>(lq, gq, qb + tb - u);
         }
     };
+    // Path output after the block (the block's steps stay branch-free).
     auto run_block = [&](int tb, const double (&vk)[U][K], const double (&qx)[U],
                          const double (&qy)[U]) {
+        double hist[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             double x = qx[u], y = qy[u];
@@ -683,7 +693,13 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
                 y = 1.0 - fmin(1.0, m * (1.0 - y));
             }
             apply(vk[u], x, y, tb - u);
-            put(tb - u);
+            hist[u] = r0[0];
+        }
+        if constexpr (K == 1) {
+            if (ps.buf != nullptr) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) path_put(ps, tb - u, hist[u], plane);
+            }
         }
     };
     if constexpr (StepBlock<K>::PIPE) {
@@ -1268,10 +1284,13 @@ k_recurrence(RecParams P, const double *__restrict__ vcurves, const Item *__rest
                                                  pstage);
         }
     }
-    // The last wavefront to finish re-arms the queues for the next launch.
-    if (lane == 0) {
-        const int total = (int)(gridDim.x * (blockDim.x / 64));
-        if (atomicAdd(&P.counters[MAX_QUEUES], 1) == total - 1) {
+    // The last workgroup to finish re-arms the queues for the next launch.
+    // One atomic per workgroup, not per wavefront: every completion atomic
+    // goes to the same address and they serialise there, which at the end
+    // of a launch whose wavefronts finish together cost tens of microseconds.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (atomicAdd(&P.counters[MAX_QUEUES], 1) == (int)gridDim.x - 1) {
             for (int i = 0; i <= MAX_QUEUES; ++i) atomicExch(&P.counters[i], 0);
         }
     }
