@@ -802,10 +802,11 @@ __global__ void __launch_bounds__(INFER_THREADS, 1) k_infer(Infer f, Weights w)
             }
             // Layer 2 + GELU + head, two output tiles (one head chunk) at a
             // time, as a two-stage pipeline: while the MFMAs of chunk c2 run,
-            // the VALU evaluates the GELU of chunk c2 - 1, two values per
-            // contraction step, so the matrix and vector units of the SIMD
-            // work at once.  Every accumulator sees the same operations in
-            // the same order as in a plain loop.
+            // the VALU evaluates the GELU of chunk c2 - 1, NG values per
+            // contraction step (scheduling fences keep them interleaved), so
+            // the matrix and vector units of the SIMD work at once.  Every
+            // accumulator sees the same operations in the same order as in a
+            // plain loop.
             f32x4 yacc[NG];
 #pragma unroll
             for (int g = 0; g < NG; ++g) yacc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
