@@ -1394,7 +1394,7 @@ static int enqueue_run(rr_ctx *c, const rr_run *run, const rr_outputs *out, Plan
 {
     RecParams P = make_params(c, run, out, pl, partial);
     const size_t lds = recurrence_lds_bytes(P, pl->K, pl->ring);
-    if (lds > c->lds_per_block)   // tables (<= 64 KB) and path stages (66 KB) fit 160 KB
+    if (lds > c->lds_per_block)   // tables (<= 64 KB) and path stages (68 KB) fit 160 KB
         return fail(c, RR_ERANGE, "recurrence launch needs more LDS than a workgroup has");
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (timed) {

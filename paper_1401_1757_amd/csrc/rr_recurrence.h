@@ -361,7 +361,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
     // overlap the chain of earlier ones).
     auto run_block = [&](int tb, const double (&vk)[U][K], const double (&q1)[U][J],
                          const double (&q2)[U][J], const double (&cv)[U][J]) {
-        double hist[U];
+        [[maybe_unused]] double hist[U];   // path output (one scenario and policy per lane)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -370,7 +370,7 @@ __device__ __forceinline__ void scalar_steps(const double *__restrict__ lq,
                 coeffs(j, tb - u, q1[u][j], q2[u][j], cv[u][j], p, c, a0);
                 apply(r[j], vk[u], p, c, a0);
             }
-            hist[u] = r[0][0];
+            if constexpr (K == 1 && J == 1) hist[u] = r[0][0];
         }
         if constexpr (K == 1 && J == 1) {
             if (ps.buf != nullptr) {
@@ -684,7 +684,7 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
     // Path output after the block (the block's steps stay branch-free).
     auto run_block = [&](int tb, const double (&vk)[U][K], const double (&qx)[U],
                          const double (&qy)[U]) {
-        double hist[U];
+        [[maybe_unused]] double hist[U];   // path output (one scenario per lane)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             double x = qx[u], y = qy[u];
@@ -693,7 +693,7 @@ __device__ __forceinline__ void vector_steps(const double *__restrict__ lq,
                 y = 1.0 - fmin(1.0, m * (1.0 - y));
             }
             apply(vk[u], x, y, tb - u);
-            hist[u] = r0[0];
+            if constexpr (K == 1) hist[u] = r0[0];
         }
         if constexpr (K == 1) {
             if (ps.buf != nullptr) {
