@@ -62,12 +62,29 @@ __device__ __forceinline__ double wave_sum(double x)
 // step t0 + l % PATH_T of policy (64 / PATH_T) j + l / PATH_T in round j, so a
 // store instruction covers four runs of PATH_T consecutive doubles.  The
 // stage's rows are PATH_ROW doubles apart, which spreads a round's reads over
-// the LDS banks.
+// the LDS banks; each lane's round targets (address and S of the policy it
+// writes for) are fetched once per item.
 struct PathStage {
     double *base;    // this lane's path (entry t at base[t]); null: the lane writes none
     int S;           // entries t < S come from the steps (entry S is written first)
     double *buf;     // the wavefront's PATH_STAGE_DOUBLES of LDS; null: no path output
+    unsigned long long rdst[PATH_T];   // flush round j: the path this lane writes into
+    int rS[PATH_T];                    // and that policy's S (0: no path)
 };
+
+// The flush targets of the lane's rounds, once per item (every lane, after
+// base and S are set): round j writes for policy (64 / PATH_T) j + l / PATH_T.
+__device__ __forceinline__ void path_prepare(PathStage &ps, int lane)
+{
+    constexpr int PER = 64 / PATH_T;
+    const int Sm = ps.base != nullptr ? ps.S : 0;
+#pragma unroll
+    for (int j = 0; j < PATH_T; ++j) {
+        const int src = PER * j + lane / PATH_T;
+        ps.rdst[j] = __shfl((unsigned long long)ps.base, src);
+        ps.rS[j] = __shfl(Sm, src);
+    }
+}
 
 // Every lane of the wavefront calls path_put for each step t, from its top
 // step down to t = 0 (the values of a lane with t >= S are not written out).
@@ -84,19 +101,12 @@ __device__ __forceinline__ void path_put(const PathStage &ps, int t, double r, i
         typedef __attribute__((address_space(1))) double global_double;
 #pragma unroll
         for (int j0 = 0; j0 < 64 / PER; j0 += B) {
-            unsigned long long dst[B];
-            int S[B];
             double x[B];
 #pragma unroll
-            for (int i = 0; i < B; ++i) {
-                const int src = PER * (j0 + i) + lane / PATH_T;
-                dst[i] = __shfl((unsigned long long)ps.base, src);
-                S[i] = __shfl(ps.S, src);
-                x[i] = ps.buf[u * PATH_ROW + src];
-            }
+            for (int i = 0; i < B; ++i) x[i] = ps.buf[u * PATH_ROW + PER * (j0 + i) + lane / PATH_T];
 #pragma unroll
             for (int i = 0; i < B; ++i)
-                if (dst[i] != 0ull && t + u < S[i]) ((global_double *)dst[i])[t + u] = x[i];
+                if (t + u < ps.rS[j0 + i]) ((global_double *)ps.rdst[j0 + i])[t + u] = x[i];
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -584,6 +594,7 @@ __device__ __forceinline__ void run_scalar(const RecParams &P, const double *__r
                 P.path[P.path_off[uid[0]]] = 0.0;   // expired: its one entry is 0
             }
         }
+        if (ps.buf != nullptr) path_prepare(ps, lane);
     }
     if (m == 1.0)
         scalar_steps<K, J, LDSQ, TWO, false, FLOW, VR>(lq, P.q, vb, P.scen_pad, L, PL, P.cf_cols, m,
@@ -778,6 +789,7 @@ __device__ __forceinline__ void run_vector(const RecParams &P, const double *__r
         } else if (P.path != nullptr && uid >= 0) {
             P.path[P.path_off[uid]] = 0.0;         // expired: its one entry is 0
         }
+        if (ps.buf != nullptr) path_prepare(ps, lane);
     }
     // A lane takes its first step at t = S - 1 (the head skips t >= S).
     PatLane pl{0, 12, 0, 1.0, 1.0, 0};
@@ -830,6 +842,7 @@ __device__ __forceinline__ void run_frac(const RecParams &P, const double *__res
                 P.path[P.path_off[uid]] = 0.0;   // expired: its one entry is 0
             }
         }
+        if (ps.buf != nullptr) path_prepare(ps, lane);
     }
     for (int t = smax - 1; t >= 0; --t) {
         const double x1 = p_eff<LDSQ, SHOCK>(lq, P.q, qa + t, m);
