@@ -1439,14 +1439,32 @@ int rr::host::run_items(rr_ctx *c, const rr_run *run, const std::vector<Item> &i
     int rc;
     if (fresh || pl.n_items != (int)items.size()) {
         HIPCHK(c, hipStreamSynchronize(c->stream));   // the item buffers may be in use
-        std::vector<int> qbeg = {0, (int)items.size()};
-        if ((rc = upload_vec(c, pl.items, items))) return rc;
+        // Longest first, dealt round-robin to the per-XCD queues, taken in
+        // windows of WG_THREADS/64 items: one queue taken item by item put
+        // every wavefront's atomic on the same counter.
+        std::vector<Item> sorted(items);
+        auto steps = [&](const Item &it) {
+            return c->tiles_host[it.tile].smax - (run->node_begin + it.node_rel) * run->node_step_m;
+        };
+        std::stable_sort(sorted.begin(), sorted.end(),
+                         [&](const Item &a, const Item &b) { return steps(a) > steps(b); });
+        const int nq = c->opt_xcd ? MAX_QUEUES : 1;
+        std::vector<Item> dealt;
+        dealt.reserve(sorted.size());
+        std::vector<int> qbeg(nq + 1, 0);
+        for (int q = 0; q < nq; ++q) {
+            qbeg[q] = (int)dealt.size();
+            for (size_t i = q; i < sorted.size(); i += nq) dealt.push_back(sorted[i]);
+        }
+        qbeg[nq] = (int)dealt.size();
+        if ((rc = upload_vec(c, pl.items, dealt))) return rc;
         if ((rc = upload_vec(c, pl.qbeg, qbeg))) return rc;
+        pl.n_queues = nq;
     }
     pl.K = K;
     pl.J = 1;
     pl.n_items = (int)items.size();
-    pl.n_queues = 1;
+    pl.win = 1;
     pl.wg_per_cu = 2;
     pl.grid = std::max(1, std::min(c->n_cu * 2, (pl.n_items + WG_THREADS / 64 - 1) / (WG_THREADS / 64)));
     rr_run r = *run;

@@ -26,7 +26,7 @@ constexpr char kMagicNode[8] = {'R', 'R', 'S', 'U', 'R', 'N', '0', '1'};   // no
 constexpr int kVersion = 1;
 constexpr int kProducts[4] = {RR_SL_ANN, RR_JL_ANN, RR_TERM, RR_ENDOW};
 constexpr int kChunk = 16;   // policies per work unit of the fused inference kernel
-constexpr int kFbK = 4;      // scenarios per lane for fallback tiles (short items, wide launch)
+constexpr int kFbK = 8;      // scenarios per lane of the exact fallback items
 
 struct BlobHeader {
     char magic[8];
@@ -147,8 +147,9 @@ struct rr::Surrogate {
 
     // fallback plan cache
     std::vector<uint64_t> plan_key;
-    std::vector<Item> fb_tiles;     // tiles with a policy outside the box x blocks of kFbK scenarios
-    std::vector<Item> fb_scens;     // the other tiles x scenarios outside the box
+    std::vector<Item> fb_items;     // exact fallback: tiles with a policy outside the box x every
+                                    // block of kFbK scenarios, other tiles x the blocks holding a
+                                    // scenario outside the box
     int64_t fb_rows = 0, in_rows = 0;
 
     // network workspaces (rows padded to 64)
@@ -1028,7 +1029,7 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
         HIPCHK(c, hipMemcpyAsync(pf.data(), S->pflag.p, pf.size() * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipMemcpyAsync(so.data(), S->sok.p, so.size() * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        std::vector<Item> tiles_items, scen_items;
+        std::vector<Item> fb_items;
         int64_t fb = 0, in = 0;
         for (int k = 0; k < run->node_count; ++k) {
             std::vector<char> bad_tile(c->n_tiles, 0), bad_scen(run->scen_count, 0);
@@ -1044,30 +1045,29 @@ extern "C" int rr_surrogate_infer(rr_ctx *c, const rr_run *run, const rr_outputs
                 if (!so[(size_t)k * run->scen_count + s]) { bad_scen[s] = 1; ++nbad_scen; }
             in += live_ok * (run->scen_count - nbad_scen);
             fb += live * run->scen_count - live_ok * (run->scen_count - nbad_scen);
-            for (int tl = 0; tl < c->n_tiles; ++tl) {
-                if (bad_tile[tl]) {
-                    for (int s = 0; s < run->scen_count; s += kFbK) tiles_items.push_back(Item{k, tl, s, 1});
-                } else {
-                    for (int s = 0; s < run->scen_count; ++s)
-                        if (bad_scen[s]) scen_items.push_back(Item{k, tl, s, 1});
-                }
-            }
+            // Blocks of kFbK scenarios holding one outside the box: the
+            // block's other rows are computed too and later overwritten by
+            // the network (one launch for both kinds of fallback rows).
+            std::vector<char> bad_block((run->scen_count + kFbK - 1) / kFbK, 0);
+            for (int s = 0; s < run->scen_count; ++s)
+                if (bad_scen[s]) bad_block[s / kFbK] = 1;
+            for (int tl = 0; tl < c->n_tiles; ++tl)
+                for (int b = 0; b < (int)bad_block.size(); ++b)
+                    if (bad_tile[tl] || bad_block[b]) fb_items.push_back(Item{k, tl, b * kFbK, 1});
         }
-        S->fb_tiles.swap(tiles_items);
-        S->fb_scens.swap(scen_items);
+        S->fb_items.swap(fb_items);
         S->fb_rows = fb;
         S->in_rows = in;
         S->plan_key = key;
     }
     double *exact = nullptr;
-    if (!S->fb_tiles.empty() || !S->fb_scens.empty()) {
+    if (!S->fb_items.empty()) {
         if (mask & RR_OUT_R0) exact = out->r0;
         else {
             HIPCHK(c, S->exact.alloc((size_t)ns * n));
             exact = S->exact.p;
         }
-        if ((rc = run_items(c, run, S->fb_tiles, kFbK, exact, 0, fresh))) return rc;
-        if ((rc = run_items(c, run, S->fb_scens, 1, exact, 1, fresh))) return rc;
+        if ((rc = run_items(c, run, S->fb_items, kFbK, exact, 0, fresh))) return rc;
     }
     if (S->fb_rows > 0 && !exact)   // k_infer would read exact rows nobody computed
         return fail(c, RR_EDEVICE, "surrogate fallback plan has %lld rows but no work items",
