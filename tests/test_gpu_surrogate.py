@@ -500,6 +500,37 @@ def test_invalid_surrogate_calls(ctx, rr):
     assert e.value.code == rr.RR_EINVAL
 
 
+def test_infer_repeated_calls_give_the_same_bits(ctx, rr, omodel):
+    """Inference is deterministic across calls that reuse its plan and
+    buffers: five calls in a row, with the outputs cleared and exact
+    valuations run on the stream between them, must each give the first
+    call's bits and report."""
+    rng = np.random.default_rng(45)
+    p = synth.random_mlp_params(rng)
+    w = parity_workload()
+    b, pf = w.basis, w.portfolio
+    ctx.basis_upload(b.q, b.v, b.shock)
+    ctx.portfolio_upload(pf)
+    ctx.surrogate_set_weights(blob_of(rr, omodel, p))
+    _say("repeated inference")
+    out = ctx.alloc_outputs(b.n_nodes, b.n_scen, stats=True)
+    ctx.surrogate_infer(0, b.n_nodes, 0, b.n_scen, 12, out)
+    torch.cuda.synchronize()
+    keys = ("r0", "totals", "stats")
+    ref = {k: to_np(out[k]).copy() for k in keys}
+    rep0 = dict(out["report"])
+    assert rep0["n_fallback"] > 0 and rep0["n_in_range"] > 0
+    for _ in range(5):
+        for k in keys:
+            out[k].fill_(float("nan"))
+        ctx.reserve_recurrence(0, b.n_nodes, 0, b.n_scen, 12)
+        ctx.surrogate_infer(0, b.n_nodes, 0, b.n_scen, 12, out)
+        torch.cuda.synchronize()
+        for k in keys:
+            assert np.array_equal(to_np(out[k]), ref[k]), k
+        assert dict(out["report"]) == rep0
+
+
 def test_infer_after_curves_regenerated_in_place(ctx, rr, omodel):
     """Regression: the fallback work list depends on the scenario range flags,
     which change when the curves are regenerated in place (same sizes, same
